@@ -1,0 +1,170 @@
+/*
+ * mr3.h -- C ABI of an MI355X-native mixed-precision MRRR eigensolver for the
+ * real symmetric tridiagonal eigenproblem T z = lambda z.
+ *
+ * Method: Petschow, Quintana-Orti, Bientinesi, "Improved accuracy and
+ * parallelism for MRRR-based eigensolvers -- a mixed precision approach"
+ * (arXiv:1304.1864).  Citations below name the paper's sections, algorithm,
+ * equations and tables.
+ *
+ * The problem (Section 1): given the diagonal d[0..n-1] and off-diagonal
+ * e[0..n-2] of T, compute eigenvalues lambda_i (the i-th smallest, ascending)
+ * and unit eigenvectors z_i for an index set I.  Following the mixed precision
+ * scheme of Section 3.1, input and output are in one format (binary_x) and all
+ * internal work uses a more precise one (binary_y):
+ *   mr3_solve_f32 : x = binary32, y = binary64  (the single/double pairing, Sec. 4.1)
+ *   mr3_solve_f64 : x = binary64, y = double-double (FMA-based double-word
+ *                   arithmetic; stands in for the paper's software binary128,
+ *                   Sec. 4.1 double/quadruple)
+ * The solver is Algorithm 1 (MRRR) with the adjustments of Section 3.2:
+ * splitting with |e_i| <= eps_x ||T||_1, a definite root representation
+ * perturbed by random relative amounts xi = eps_x, eigenvalue bisection on a
+ * binary64 copy of each representation, classification with gaptol
+ * (1e-5 for f32, 1e-10 for f64), shifts of clusters by the stationary qd
+ * transform in y, and Rayleigh quotient iteration with twisted factorizations
+ * stopped at ||r|| <= gap * eps_x * sqrt(n) (Sec. 3.2, "Rayleigh quotient
+ * iteration").
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * Memory.  d, e, W, Z are DEVICE pointers on the handle's device, owned by
+ *   the caller; the library keeps no pointer after returning.  m (the count
+ *   of eigenpairs found) is a HOST pointer.  Workspace is allocated by the
+ *   library from a per-handle pool that grows on demand and is released by
+ *   mr3_destroy.
+ * Layout.  d has length n, e has length n-1 (e may be NULL when n <= 1).
+ *   W receives m eigenvalues in ascending order.  Z (column-major, leading
+ *   dimension ldz >= max(1, n)) receives the m unit eigenvectors; Z == NULL
+ *   computes eigenvalues only.  The sign of each eigenvector is fixed so that
+ *   its entry of largest magnitude is positive.
+ * Ranges.  MR3_RANGE_ALL: all n eigenpairs.  MR3_RANGE_VALUE: eigenvalues in
+ *   the half-open interval [vl, vu).  MR3_RANGE_INDEX: indices il..iu,
+ *   1-based, inclusive (the index set I of Section 1).
+ * Synchronisation.  All device work is issued on `stream` (a hipStream_t, or
+ *   NULL for the null stream).  Calls return after the results are complete
+ *   (the library synchronises `stream` internally to size its work lists).
+ * Errors.  0 on success.  -k: argument k (1-based position in the call) is
+ *   invalid (negative n, NULL pointer where one is required, non-finite
+ *   input, vl >= vu, il < 1 or iu > n or il > iu + 1, ldz < n, unknown range).
+ *   MR3_ERR_NUMERIC (+1): internal numerical failure after every fallback.
+ *   MR3_ERR_HIP (+2): a HIP runtime call failed.  MR3_ERR_NO_DEVICE (+3):
+ *   no usable GPU.  On a nonzero status the outputs are undefined.
+ * Threads.  A handle may be used by one host thread at a time.
+ */
+#ifndef MR3_H
+#define MR3_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MR3_OK 0
+#define MR3_ERR_NUMERIC 1
+#define MR3_ERR_HIP 2
+#define MR3_ERR_NO_DEVICE 3
+
+typedef enum { MR3_RANGE_ALL = 0, MR3_RANGE_VALUE = 1, MR3_RANGE_INDEX = 2 } mr3_range;
+
+typedef struct mr3_handle_s *mr3_handle;
+
+/* Tunable parameters (Section 3.2, Section 4.1).  Zero in a field selects the
+ * per-precision default given in brackets [f32 path / f64 path]. */
+typedef struct {
+    double gaptol;         /* classification tolerance, eq. (gaptol interval) [1e-5 / 1e-10] */
+    double bisect_rel;     /* relative width of initial eigenvalue intervals [1e-2 * gaptol] */
+    double xi;             /* relative size of the root perturbation [eps_x] */
+    double k_elg;          /* element-growth bound for accepting a shifted
+                              representation, as a multiple of spdiam [10] */
+    double k_rs;           /* RQI stopping constant: ||r|| <= k_rs*gap*eps_x*sqrt(n) [1] */
+    int max_depth;         /* cap on the depth of the representation tree [6] */
+    int rqi_max_iter;      /* RQI iterations before the bisection fallback [10] */
+    int lanes_per_eig;     /* bisection lanes per eigenvalue, power of two <= 64;
+                              0 = chosen from the problem size */
+    unsigned long long seed; /* seed of the counter-based perturbation generator [0x5eed] */
+    /* fault injection (tests): force the bisection fallback of RQI for every
+     * eigenvector; reject every candidate shift so the least-growth candidate
+     * is used */
+    int force_rqi_fallback;
+    int force_best_candidate;
+} mr3_params;
+
+/* Diagnostics of the last solve on a handle (Section 4.2 reports d_max and
+ * the clustering rho = largest cluster / n). */
+typedef struct {
+    int64_t n_eigenpairs;     /* m of the last call (summed over a batch) */
+    int64_t n_blocks;         /* irreducible blocks after splitting */
+    int d_max;                /* depth of the deepest representation-tree node */
+    int64_t n_clusters;       /* clusters processed (all levels) */
+    int64_t largest_cluster;  /* size of the largest cluster */
+    int64_t n_rqi_iters;      /* RQI iterations summed over eigenvectors */
+    int64_t n_fallbacks;      /* eigenvectors that needed the bisection fallback */
+    int64_t n_best_candidate; /* shifts accepted as least-growth candidate */
+} mr3_stats;
+
+/* Create a handle on HIP device `device`.  Fails with MR3_ERR_NO_DEVICE if it
+ * does not exist. */
+int mr3_create(mr3_handle *h, int device);
+/* Release the handle and its workspace pool. */
+int mr3_destroy(mr3_handle h);
+/* Fill *p with the defaults for `precision` (32 or 64). */
+int mr3_default_params(mr3_params *p, int precision);
+/* Replace the handle's parameters (copied).  NULL restores the defaults. */
+int mr3_set_params(mr3_handle h, const mr3_params *p);
+/* Diagnostics of the last solve. */
+int mr3_get_stats(mr3_handle h, mr3_stats *s);
+
+/* Single problem, FP32 input/output with binary64 internal arithmetic
+ * (Section 4.1, single/double).  Arguments (1-based positions, used in the
+ * -k error codes): 1 h, 2 n, 3 d, 4 e, 5 range, 6 vl, 7 vu, 8 il, 9 iu,
+ * 10 m, 11 W, 12 Z, 13 ldz, 14 stream. */
+int mr3_solve_f32(mr3_handle h, int64_t n, const float *d, const float *e, int range,
+                  double vl, double vu, int64_t il, int64_t iu, int64_t *m, float *W,
+                  float *Z, int64_t ldz, void *stream);
+
+/* Single problem, FP64 input/output with double-double internal arithmetic
+ * (Section 4.1, double/quadruple, with double-double as y).  Same arguments. */
+int mr3_solve_f64(mr3_handle h, int64_t n, const double *d, const double *e, int range,
+                  double vl, double vu, int64_t il, int64_t iu, int64_t *m, double *W,
+                  double *Z, int64_t ldz, void *stream);
+
+/* Per-problem range of a batched call. */
+typedef struct {
+    int range;      /* mr3_range */
+    double vl, vu;  /* MR3_RANGE_VALUE */
+    int64_t il, iu; /* MR3_RANGE_INDEX */
+} mr3_range_desc;
+
+/* Many independent problems of one precision in one pass of the pipeline
+ * (every stage is a single launch over all problems).
+ * Arguments: 1 h, 2 count, 3 precision (32 or 64), 4 n[count] (host),
+ * 5 de_off[count] (host; problem p reads d + de_off[p] and e + de_off[p]),
+ * 6 d, 7 e (device, float or double per precision), 8 ranges[count] (host,
+ * NULL = all), 9 m[count] (host, output), 10 W (device), 11 w_off[count]
+ * (host), 12 Z (device, may be NULL), 13 z_off[count] (host), 14 ldz[count]
+ * (host), 15 stream. */
+int mr3_solve_batched(mr3_handle h, int64_t count, int precision, const int64_t *n,
+                      const int64_t *de_off, const void *d, const void *e,
+                      const mr3_range_desc *ranges, int64_t *m, void *W, const int64_t *w_off,
+                      void *Z, const int64_t *z_off, const int64_t *ldz, void *stream);
+
+/* Verification (not part of a solve; Section 1, eq. (1)).  For the FP64
+ * eigenpairs (W, Z) of the FP64 tridiagonal (d, e), all device pointers:
+ * orth_out[0] = max_{i != j} |z_i^T z_j| and orth_out[1] = max_i |z_i^T z_i - 1|,
+ * computed from Z^T Z with FP64 matrix-core (MFMA) tiles; resid_out[0] =
+ * max_i ||T z_i - lambda_i z_i||_1 / ||T||_1.  Host outputs.  Arguments: 1 h,
+ * 2 n, 3 m, 4 d, 5 e, 6 W, 7 Z, 8 ldz, 9 orth_out[2], 10 resid_out[1],
+ * 11 stream. */
+int mr3_check_f64(mr3_handle h, int64_t n, int64_t m, const double *d, const double *e,
+                  const double *W, const double *Z, int64_t ldz, double *orth_out,
+                  double *resid_out, void *stream);
+
+/* Library version string. */
+const char *mr3_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MR3_H */

@@ -1,0 +1,321 @@
+"""MI355X-native mixed-precision MRRR for the symmetric tridiagonal eigenproblem.
+
+Thin ctypes binding over ``libmr3.so`` (C ABI in ``include/mr3.h``).  The
+functions named like the C entry points take torch tensors where the C call
+takes device pointers and only marshal arguments; every step of the solve runs
+in the library's HIP kernels.  There is no CPU fallback: importing works
+without a GPU, but any call fails loudly if the library or the device is
+missing.
+
+Convenience wrappers:
+    solve(d, e, range="all", vl=..., vu=..., il=..., iu=..., vectors=True)
+        d, e: 1-D CUDA tensors (float32 -> FP32 I/O with binary64 inside,
+        float64 -> FP64 I/O with double-double inside).  Returns (W, Z).
+    solve_batched(ds, es, ...)   many problems in one pass
+    check(d, e, W, Z)            (orthogonality, residual) of FP64 results
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmr3.so")
+
+RANGE_ALL, RANGE_VALUE, RANGE_INDEX = 0, 1, 2
+MR3_OK, MR3_ERR_NUMERIC, MR3_ERR_HIP, MR3_ERR_NO_DEVICE = 0, 1, 2, 3
+
+
+class MR3Error(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn} returned {code}")
+        self.code = code
+
+
+class mr3_params(ctypes.Structure):
+    _fields_ = [
+        ("gaptol", ctypes.c_double),
+        ("bisect_rel", ctypes.c_double),
+        ("xi", ctypes.c_double),
+        ("k_elg", ctypes.c_double),
+        ("k_rs", ctypes.c_double),
+        ("max_depth", ctypes.c_int),
+        ("rqi_max_iter", ctypes.c_int),
+        ("lanes_per_eig", ctypes.c_int),
+        ("seed", ctypes.c_ulonglong),
+        ("force_rqi_fallback", ctypes.c_int),
+        ("force_best_candidate", ctypes.c_int),
+    ]
+
+
+class mr3_stats(ctypes.Structure):
+    _fields_ = [
+        ("n_eigenpairs", ctypes.c_int64),
+        ("n_blocks", ctypes.c_int64),
+        ("d_max", ctypes.c_int),
+        ("n_clusters", ctypes.c_int64),
+        ("largest_cluster", ctypes.c_int64),
+        ("n_rqi_iters", ctypes.c_int64),
+        ("n_fallbacks", ctypes.c_int64),
+        ("n_best_candidate", ctypes.c_int64),
+    ]
+
+
+class mr3_range_desc(ctypes.Structure):
+    _fields_ = [
+        ("range", ctypes.c_int),
+        ("vl", ctypes.c_double),
+        ("vu", ctypes.c_double),
+        ("il", ctypes.c_int64),
+        ("iu", ctypes.c_int64),
+    ]
+
+
+EXPORTS = [
+    "mr3_create", "mr3_destroy", "mr3_default_params", "mr3_set_params", "mr3_get_stats",
+    "mr3_solve_f32", "mr3_solve_f64", "mr3_solve_batched", "mr3_check_f64", "mr3_version",
+]
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load libmr3.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(p)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    lib.mr3_create.argtypes = [ctypes.POINTER(vp), i32]
+    lib.mr3_destroy.argtypes = [vp]
+    lib.mr3_default_params.argtypes = [ctypes.POINTER(mr3_params), i32]
+    lib.mr3_set_params.argtypes = [vp, ctypes.POINTER(mr3_params)]
+    lib.mr3_get_stats.argtypes = [vp, ctypes.POINTER(mr3_stats)]
+    for name in ("mr3_solve_f32", "mr3_solve_f64"):
+        getattr(lib, name).argtypes = [vp, i64, vp, vp, i32, dbl, dbl, i64, i64, pi64, vp, vp, i64, vp]
+    lib.mr3_solve_batched.argtypes = [vp, i64, i32, pi64, pi64, vp, vp,
+                                      ctypes.POINTER(mr3_range_desc), pi64, vp, pi64, vp, pi64,
+                                      pi64, vp]
+    lib.mr3_check_f64.argtypes = [vp, i64, i64, vp, vp, vp, vp, i64,
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
+    lib.mr3_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name != "mr3_version":
+            getattr(lib, name).restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(fn, rc):
+    if rc != MR3_OK:
+        raise MR3Error(fn, rc)
+
+
+class Handle:
+    """Owns an mr3_handle (device, parameters, workspace pool)."""
+
+    def __init__(self, device: int | None = None):
+        lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device() if torch.cuda.is_available() else 0
+        self._h = ctypes.c_void_p()
+        _check("mr3_create", lib.mr3_create(ctypes.byref(self._h), int(device)))
+        self.device = device
+
+    def close(self):
+        if self._h:
+            load_library().mr3_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def set_params(self, **kw):
+        p = default_params(kw.pop("precision", 64))
+        for k, v in kw.items():
+            setattr(p, k, v)
+        _check("mr3_set_params", load_library().mr3_set_params(self._h, ctypes.byref(p)))
+
+    def reset_params(self):
+        _check("mr3_set_params", load_library().mr3_set_params(self._h, None))
+
+    def stats(self) -> dict:
+        s = mr3_stats()
+        _check("mr3_get_stats", load_library().mr3_get_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in mr3_stats._fields_}
+
+
+def default_params(precision: int = 64) -> mr3_params:
+    p = mr3_params()
+    _check("mr3_default_params", load_library().mr3_default_params(ctypes.byref(p), precision))
+    return p
+
+
+_default_handle = None
+
+
+def default_handle() -> Handle:
+    global _default_handle
+    if _default_handle is None:
+        _default_handle = Handle()
+    return _default_handle
+
+
+# --------------------------------------------------------------------------
+# same-name wrappers of the C entry points
+# --------------------------------------------------------------------------
+def mr3_solve_f32(h, n, d, e, range_, vl, vu, il, iu, W, Z, ldz, stream=None) -> int:
+    m = ctypes.c_int64(0)
+    rc = load_library().mr3_solve_f32(h.ptr, n, _ptr(d), _ptr(e), range_, vl, vu, il, iu,
+                                      ctypes.byref(m), _ptr(W), _ptr(Z), ldz, _stream_ptr(stream))
+    _check("mr3_solve_f32", rc)
+    return m.value
+
+
+def mr3_solve_f64(h, n, d, e, range_, vl, vu, il, iu, W, Z, ldz, stream=None) -> int:
+    m = ctypes.c_int64(0)
+    rc = load_library().mr3_solve_f64(h.ptr, n, _ptr(d), _ptr(e), range_, vl, vu, il, iu,
+                                      ctypes.byref(m), _ptr(W), _ptr(Z), ldz, _stream_ptr(stream))
+    _check("mr3_solve_f64", rc)
+    return m.value
+
+
+def mr3_check_f64(h, n, m, d, e, W, Z, ldz, stream=None):
+    orth = (ctypes.c_double * 2)()
+    res = (ctypes.c_double * 1)()
+    rc = load_library().mr3_check_f64(h.ptr, n, m, _ptr(d), _ptr(e), _ptr(W), _ptr(Z), ldz,
+                                      orth, res, _stream_ptr(stream))
+    _check("mr3_check_f64", rc)
+    return (orth[0], orth[1]), res[0]
+
+
+def mr3_solve_batched(h, count, precision, n, de_off, d, e, ranges, W, w_off, Z, z_off, ldz,
+                      stream=None):
+    i64a = ctypes.c_int64 * count
+    n_a, de_a, wo_a = i64a(*n), i64a(*de_off), i64a(*w_off)
+    zo_a = i64a(*z_off) if Z is not None else None
+    ld_a = i64a(*ldz) if Z is not None else None
+    m_a = i64a()
+    rg = None
+    if ranges is not None:
+        rg = (mr3_range_desc * count)()
+        for p, r in enumerate(ranges):
+            rg[p].range, rg[p].vl, rg[p].vu, rg[p].il, rg[p].iu = r
+    rc = load_library().mr3_solve_batched(h.ptr, count, precision, n_a, de_a, _ptr(d), _ptr(e), rg,
+                                          m_a, _ptr(W), wo_a, _ptr(Z), zo_a, ld_a,
+                                          _stream_ptr(stream))
+    _check("mr3_solve_batched", rc)
+    return list(m_a)
+
+
+# --------------------------------------------------------------------------
+# convenience wrappers
+# --------------------------------------------------------------------------
+_RANGES = {"all": RANGE_ALL, "value": RANGE_VALUE, "index": RANGE_INDEX}
+
+
+def solve(d: torch.Tensor, e: torch.Tensor, range: str = "all", vl: float = 0.0, vu: float = 0.0,
+          il: int = 1, iu: int | None = None, vectors: bool = True, handle: Handle | None = None,
+          stream=None):
+    """Eigenpairs of the tridiagonal (d, e); returns (W[m], Z[n, m] or None)."""
+    if not d.is_cuda:
+        raise ValueError("d and e must be device tensors")
+    h = handle or default_handle()
+    n = d.numel()
+    if iu is None:
+        iu = n
+    rk = _RANGES[range]
+    cap = n if rk != RANGE_INDEX else max(iu - il + 1, 0)
+    W = torch.empty(max(cap, 1), dtype=d.dtype, device=d.device)
+    # column-major n x cap == row-major (cap, n)
+    Zt = torch.empty((max(cap, 1), max(n, 1)), dtype=d.dtype, device=d.device) if vectors else None
+    fn = mr3_solve_f32 if d.dtype == torch.float32 else mr3_solve_f64
+    if d.dtype not in (torch.float32, torch.float64) or e.dtype != d.dtype:
+        raise ValueError("d and e must both be float32 or both float64")
+    m = fn(h, n, d.contiguous(), e.contiguous() if n > 1 else None, rk, vl, vu, il, iu, W, Zt,
+           max(n, 1), stream)
+    W = W[:m]
+    Z = Zt[:m].T if vectors else None
+    return W, Z
+
+
+def solve_batched(ds, es, ranges=None, vectors: bool = True, handle: Handle | None = None,
+                  stream=None):
+    """Solve many problems (lists of 1-D device tensors of one dtype) in one
+    pass.  Returns lists of W and Z (Z[p] is n_p x m_p)."""
+    h = handle or default_handle()
+    dtype = ds[0].dtype
+    dev = ds[0].device
+    count = len(ds)
+    n = [int(x.numel()) for x in ds]
+    off, o = [], 0
+    for k in n:
+        off.append(o)
+        o += k
+    dcat = torch.cat([x.reshape(-1) for x in ds]) if o else torch.empty(1, dtype=dtype, device=dev)
+    ecat = torch.zeros(max(o, 1), dtype=dtype, device=dev)
+    for p, x in enumerate(es):
+        if n[p] > 1:
+            ecat[off[p]:off[p] + n[p] - 1] = x.reshape(-1)[: n[p] - 1]
+    caps = []
+    for p in range(count):
+        if ranges is not None and ranges[p][0] == RANGE_INDEX:
+            caps.append(max(ranges[p][4] - ranges[p][3] + 1, 0))
+        else:
+            caps.append(n[p])
+    w_off, z_off, acc_w, acc_z = [], [], 0, 0
+    for p in range(count):
+        w_off.append(acc_w)
+        z_off.append(acc_z)
+        acc_w += caps[p]
+        acc_z += caps[p] * n[p]
+    W = torch.empty(max(acc_w, 1), dtype=dtype, device=dev)
+    Z = torch.empty(max(acc_z, 1), dtype=dtype, device=dev) if vectors else None
+    ldz = [max(k, 1) for k in n]
+    ms = mr3_solve_batched(h, count, 32 if dtype == torch.float32 else 64, n, off, dcat, ecat,
+                           ranges, W, w_off, Z, z_off, ldz, stream)
+    Ws = [W[w_off[p]:w_off[p] + ms[p]] for p in range(count)]
+    Zs = None
+    if vectors:
+        Zs = [Z[z_off[p]:z_off[p] + ms[p] * n[p]].view(ms[p], n[p]).T for p in range(count)]
+    return Ws, Zs
+
+
+def check(d: torch.Tensor, e: torch.Tensor, W: torch.Tensor, Z: torch.Tensor,
+          handle: Handle | None = None, stream=None):
+    """(max off-diagonal |Z^T Z|, max |diag - 1|), max ||T z - lambda z||_1/||T||_1
+    for FP64 results, computed on the device (FP64 MFMA Gram matrix)."""
+    h = handle or default_handle()
+    n, m = d.numel(), W.numel()
+    Zcm = Z.T.contiguous()  # (m, n) row-major == n x m column-major, ldz = n
+    return mr3_check_f64(h, n, m, d.contiguous(), e.contiguous() if n > 1 else None,
+                         W.contiguous(), Zcm, max(n, 1), stream)
+
+
+def version() -> str:
+    return load_library().mr3_version().decode()

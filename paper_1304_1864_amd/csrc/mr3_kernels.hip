@@ -1,0 +1,1318 @@
+// HIP kernels of the mixed-precision MRRR hot path (gfx950).
+//
+// Algorithm 1 of the paper (MRRR), with the mixed precision adjustments of its
+// Section 3.2, mapped onto the GPU level by level:
+//   k_prep      preprocessing: ||T||_1, power-of-two scaling, splitting,
+//               per-block Gerschgorin bounds and requested index ranges
+//   k_root      root representation M_root = T - mu I (definite, mu just
+//               outside the spectrum) and its random relative perturbation
+//               (Alg. 1 lines 1-2; Sec. 3.2 "Random perturbations")
+//   k_pq        off-diagonal prefix/suffix products used by the eigenvector
+//               recurrences (shared by every node of a tree)
+//   k_bisect    multisection on Sturm counts of a binary64 copy of a
+//               representation (Alg. 1 lines 3 and 14; Sec. 3.2 "Arithmetic
+//               used to approximate eigenvalues")
+//   k_classify  singleton / cluster partition by reldist >= gaptol (Alg. 1
+//               line 7; Sec. 2 "Classification of the eigenvalues")
+//   k_rqi       Rayleigh quotient iteration with twisted factorizations
+//               (Alg. 1 lines 9-11; Sec. 2 "Rayleigh quotient iteration",
+//               Sec. 3.2 stopping criterion)
+//   k_zout      eigenvector normalisation, y -> x rounding, coalesced Z stores
+//   k_child_*   cluster shifts M - tau I by the stationary qd transform in y
+//               with an element-growth acceptance test (Alg. 1 line 13;
+//               Sec. 2 "Shifting the spectrum", "Requirements on the
+//               representations")
+//
+// Recurrences.  For a representation L D L^T (data d_i and lld_i = d_i l_i^2,
+// off-diagonals e_i = d_i l_i shared by all nodes of a tree) and a shift tau,
+// the stationary transform L D L^T - tau I = L+ D+ L+^T runs
+//     s_1 = -tau,  d+_i = d_i + s_i,  s_{i+1} = lld_i s_i / d+_i - tau
+// and the progressive one L D L^T - tau I = U Omega U^T runs
+//     p_n = d_n - tau,  w_{i+1} = lld_i + p_{i+1},  p_i = d_i p_{i+1} / w_{i+1} - tau.
+// Both are evaluated here in an equivalent division-free form: writing
+// s_i = a_i / b_i gives  c_i = d_i b_i + a_i  (= d+_i b_i),
+// a_{i+1} = lld_i a_i - tau c_i,  b_{i+1} = c_i;  writing p_i = alpha_i / beta_i
+// gives  rho_{i+1} = lld_i beta_{i+1} + alpha_{i+1}  (= w_{i+1} beta_{i+1}),
+// alpha_i = d_i alpha_{i+1} - tau rho_{i+1},  beta_i = rho_{i+1}.  Each sum is
+// one rounding of the same operands as in the divided form, so the mixed
+// relative stability of the qd transforms carries over; the pairs are rescaled
+// by powers of two (exact) to stay in range.  sign(d+_i) = sign(c_i) sign(b_i)
+// gives the Sturm count (Sylvester inertia) without a division.
+// The twisted factorization at index r has gamma_r = s_r + p_r + tau, and the
+// solution of N_r^T z = e_r is, up to scaling,
+//     z_k = P_k b_k      (k <= r),   P_k = prod_{j<k} (-1/e_j)
+//     z_k = Q_k beta_k   (k >= r),   Q_k = prod_{j>=k} (-1/e_j)
+// which follows from z_{k+1} = -z_k d+_k / e_k and z_k = -z_{k+1} w_{k+1} / e_k.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dd.hpp"
+#include "mr3_types.hpp"
+
+namespace mr3 {
+
+#define MR3_BIG 1.0e300
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int dexp(double x) { return __builtin_amdgcn_frexp_exp(x); }
+
+__device__ __forceinline__ int sign_differs(double c, double b) {
+    return (int)(((unsigned)__double2hiint(c) ^ (unsigned)__double2hiint(b)) >> 31);
+}
+
+// counter-based generator (splitmix64 finaliser) -> uniform in [-1, 1)
+__device__ __forceinline__ double urand_pm1(unsigned long long seed, unsigned long long row,
+                                            unsigned long long arr) {
+    unsigned long long z = seed * 0x9E3779B97F4A7C15ull + row * 0xBF58476D1CE4E5B9ull +
+                           (arr + 1ull) * 0x94D049BB133111EBull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 2.220446049250313e-16 - 1.0;  // 2^-52 * [0, 2^53) - 1
+}
+
+// Sturm count of the tridiagonal (Td, Te) rows [0, n) at x: number of
+// eigenvalues below x (negative pivots of T - x I); used only in the
+// preprocessing, not on the hot path.
+__device__ int sturm_T(const double* __restrict__ Td, const double* __restrict__ Te, int64_t n,
+                       double x) {
+    const double pivmin = 1e-290;
+    int cnt = 0;
+    double q = 1.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double off = (i > 0) ? Te[i - 1] : 0.0;
+        double t = Td[i] - x;
+        if (off != 0.0) t -= (off * off) / q;
+        if (fabs(t) < pivmin) t = -pivmin;
+        cnt += (t < 0.0);
+        q = t;
+    }
+    return cnt;
+}
+
+// Sturm count of the binary64 representation (d, lld) at x (division free)
+__device__ __forceinline__ int negcount64(const double* __restrict__ D,
+                                          const double* __restrict__ LL, int64_t n, double x) {
+    double a = -x, b = 1.0;
+    int neg = 0;
+    int64_t i = 0;
+    for (; i + 4 <= n; i += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double c = __fma_rn(D[i + u], b, a);
+            neg += sign_differs(c, b);
+            a = __fma_rn(-x, c, LL[i + u] * a);
+            b = c;
+        }
+        const int em = max(dexp(a), dexp(b));
+        a = __builtin_ldexp(a, -em);
+        b = __builtin_ldexp(b, -em);
+    }
+    for (; i < n; ++i) {
+        const double c = __fma_rn(D[i], b, a);
+        neg += sign_differs(c, b);
+        a = __fma_rn(-x, c, LL[i] * a);
+        b = c;
+    }
+    return neg;
+}
+
+// the same count in working precision y
+template <class Y>
+__device__ int negcount_y(const Y* __restrict__ D, const Y* __restrict__ LL, int64_t n, Y x) {
+    Y a = neg(x), b = y_from(1.0, Y());
+    int neg_ = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        Y c = mul_add(D[i], b, a);
+        neg_ += sign_differs(hi_of(c), hi_of(b));
+        a = sub(mul(LL[i], a), mul(x, c));
+        b = c;
+        if ((i & 3) == 3) {
+            const int em = max(y_exp(a), y_exp(b));
+            a = y_ldexp(a, -em);
+            b = y_ldexp(b, -em);
+        }
+    }
+    return neg_;
+}
+
+__device__ __forceinline__ double block_reduce_max(double v, double* sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// a1: preprocessing (one workgroup of 256 per problem)
+// ---------------------------------------------------------------------------
+// Index-range resolution for a split problem: find x with count(x) <= c on
+// the split matrix, as close as the arithmetic allows to the eigenvalue c+1,
+// and the per-block counts there; eigenvalues that tie across blocks inside
+// the final bracket are handed to blocks in block order.
+__device__ void index_boundary(const double* Td, const double* Te, int64_t n, double glo,
+                               double ghi, int64_t c, int nb, BlockInfo* bi, int which,
+                               double* sh_x, int* sh_c) {
+    const int t = threadIdx.x;
+    __shared__ double s_lo, s_hi;
+    __shared__ int s_done;
+    if (t == 0) {
+        s_lo = glo;
+        s_hi = ghi;
+        s_done = (c <= 0) ? 1 : 0;
+    }
+    __syncthreads();
+    for (int round = 0; round < 12 && !s_done; ++round) {
+        const double lo = s_lo, hi = s_hi;
+        const double x = lo + (hi - lo) * ((double)(t + 1) / 256.0);
+        sh_x[t] = x;
+        sh_c[t] = (t < 255) ? sturm_T(Td, Te, n, x) : (int)n;
+        __syncthreads();
+        if (t == 0) {
+            int f = 255;  // first point with count > c
+            for (int q = 0; q < 255; ++q)
+                if (sh_c[q] > c) { f = q; break; }
+            const double nlo = (f > 0) ? sh_x[f - 1] : lo;
+            const double nhi = (f < 255) ? sh_x[f] : hi;
+            if (f > 0 && sh_c[f - 1] == c) s_done = 1;
+            if (nlo == s_lo && nhi == s_hi) s_done = 1;
+            s_lo = nlo;
+            s_hi = nhi;
+        }
+        __syncthreads();
+    }
+    const double xlo = s_lo, xhi = s_hi;
+    // per-block counts at both ends of the final bracket
+    for (int b = t; b < nb; b += blockDim.x) {
+        const int64_t s = bi[b].start;
+        const int64_t e_ = (b + 1 < nb) ? bi[b + 1].start : n;
+        int clo = (c <= 0) ? 0 : sturm_T(Td + s, Te + s, e_ - s, xlo);
+        int chi = (c <= 0) ? 0 : sturm_T(Td + s, Te + s, e_ - s, xhi);
+        if (which == 0) {
+            bi[b].il = clo;
+            bi[b].gl = (double)chi;  // temporary: count at the upper end
+        } else {
+            bi[b].iu = clo;
+            bi[b].gu = (double)chi;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        int64_t total = 0;
+        for (int b = 0; b < nb; ++b) total += (which == 0) ? bi[b].il : bi[b].iu;
+        int64_t deficit = c - total;
+        for (int b = 0; b < nb && deficit > 0; ++b) {
+            const int64_t room = (int64_t)((which == 0) ? bi[b].gl : bi[b].gu) -
+                                 ((which == 0) ? bi[b].il : bi[b].iu);
+            const int64_t take = room < deficit ? room : deficit;
+            if (which == 0) bi[b].il += take; else bi[b].iu += take;
+            deficit -= take;
+        }
+    }
+    __syncthreads();
+}
+
+template <class X>
+__global__ void __launch_bounds__(256)
+k_prep(const ProbDesc* __restrict__ probs, const X* __restrict__ din, const X* __restrict__ ein,
+       double eps_x, double* __restrict__ Td, double* __restrict__ Te, ProbInfo* __restrict__ info,
+       BlockInfo* __restrict__ binfo) {
+    __shared__ double sh[256];
+    __shared__ int shi[256];
+    const int p = blockIdx.x;
+    const int t = threadIdx.x;
+    const ProbDesc pd = probs[p];
+    const int64_t n = pd.n;
+    const X* d = din + pd.in_off;
+    const X* e = ein + pd.in_off;
+    double* td = Td + pd.row0;
+    double* te = Te + pd.row0;
+    BlockInfo* bi = binfo + pd.row0;
+    if (n == 0) {
+        if (t == 0) { info[p].nblocks = 0; info[p].err = 0; info[p].sexp = 0; info[p].tnorm = 0; }
+        return;
+    }
+    // ||T||_1 and finiteness
+    double rmax = 0.0;
+    int bad = 0;
+    for (int64_t i = t; i < n; i += blockDim.x) {
+        const double di = (double)d[i];
+        const double el = (i > 0) ? fabs((double)e[i - 1]) : 0.0;
+        const double er = (i + 1 < n) ? fabs((double)e[i]) : 0.0;
+        if (!isfinite(di) || !isfinite(el) || !isfinite(er)) bad = 1;
+        rmax = fmax(rmax, el + fabs(di) + er);
+    }
+    shi[t] = bad;
+    const double tnorm = block_reduce_max(rmax, sh);
+    int anybad = 0;
+    for (int q = 0; q < 256; ++q) anybad |= shi[q];
+    if (anybad) {
+        if (t == 0) { info[p].err = 1; info[p].nblocks = 0; }
+        return;
+    }
+    const int sexp = (tnorm > 0.0) ? -dexp(tnorm) : 0;
+    const double tn = __builtin_ldexp(tnorm, sexp);
+    const double thresh = eps_x * tn;
+    for (int64_t i = t; i < n; i += blockDim.x) {
+        td[i] = __builtin_ldexp((double)d[i], sexp);
+        double ev = 0.0;
+        if (i + 1 < n) {
+            ev = __builtin_ldexp((double)e[i], sexp);
+            if (fabs(ev) <= thresh) ev = 0.0;  // split (Sec. 3.2 "Preprocessing")
+        }
+        te[i] = ev;
+    }
+    __syncthreads();
+    // block starts: row i starts a block if i == 0 or e_{i-1} was set to zero
+    const int64_t chunk = (n + blockDim.x - 1) / blockDim.x;
+    const int64_t c0 = t * chunk, c1 = min(n, c0 + chunk);
+    int cnt = 0;
+    for (int64_t i = c0; i < c1; ++i) cnt += (i == 0 || te[i - 1] == 0.0);
+    shi[t] = cnt;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int q = 0; q < 256; ++q) { int v = shi[q]; shi[q] = run; run += v; }
+        info[p].nblocks = run;
+        info[p].sexp = sexp;
+        info[p].tnorm = tn;
+        info[p].err = 0;
+    }
+    __syncthreads();
+    int pos = shi[t];
+    for (int64_t i = c0; i < c1; ++i)
+        if (i == 0 || te[i - 1] == 0.0) bi[pos++].start = i;
+    __syncthreads();
+    const int nb = info[p].nblocks;
+    for (int b = t; b < nb; b += blockDim.x) {
+        const int64_t s = bi[b].start;
+        const int64_t en = (b + 1 < nb) ? bi[b + 1].start : n;
+        double gl = MR3_BIG, gu = -MR3_BIG;
+        for (int64_t i = s; i < en; ++i) {
+            const double off = ((i > s) ? fabs(te[i - 1]) : 0.0) + ((i + 1 < en) ? fabs(te[i]) : 0.0);
+            gl = fmin(gl, td[i] - off);
+            gu = fmax(gu, td[i] + off);
+        }
+        bi[b].n = en - s;
+        if (pd.range == RANGE_VALUE) {
+            const double vl = __builtin_ldexp(pd.vl, sexp), vu = __builtin_ldexp(pd.vu, sexp);
+            bi[b].il = sturm_T(td + s, te + s, en - s, vl) + 1;
+            bi[b].iu = sturm_T(td + s, te + s, en - s, vu);
+        } else if (pd.range == RANGE_INDEX && nb == 1) {
+            bi[b].il = pd.il;
+            bi[b].iu = pd.iu;
+        } else {
+            bi[b].il = 1;
+            bi[b].iu = en - s;
+        }
+        bi[b].gl = gl;
+        bi[b].gu = gu;
+    }
+    __syncthreads();
+    if (pd.range == RANGE_INDEX && nb > 1) {
+        double glo = MR3_BIG, ghi = -MR3_BIG;
+        for (int b = 0; b < nb; ++b) { glo = fmin(glo, bi[b].gl); ghi = fmax(ghi, bi[b].gu); }
+        // keep the Gerschgorin bounds; the boundary search uses il/iu and
+        // gl/gu of the block records as scratch, so save them first
+        __shared__ double s_gl[1], s_gu[1];
+        (void)s_gl; (void)s_gu;
+        const double span = fmax(ghi - glo, 1e-300);
+        glo -= 1e-3 * span;
+        ghi += 1e-3 * span;
+        // stash Gerschgorin bounds in Te-adjacent scratch: recompute afterwards
+        index_boundary(td, te, n, glo, ghi, pd.il - 1, nb, bi, 0, sh, shi);
+        index_boundary(td, te, n, glo, ghi, pd.iu, nb, bi, 1, sh, shi);
+        for (int b = t; b < nb; b += blockDim.x) {
+            const int64_t s = bi[b].start;
+            const int64_t en = s + bi[b].n;
+            bi[b].il = bi[b].il + 1;  // first requested local index
+            double gl = MR3_BIG, gu = -MR3_BIG;
+            for (int64_t i = s; i < en; ++i) {
+                const double off = ((i > s) ? fabs(te[i - 1]) : 0.0) + ((i + 1 < en) ? fabs(te[i]) : 0.0);
+                gl = fmin(gl, td[i] - off);
+                gu = fmax(gu, td[i] + off);
+            }
+            bi[b].gl = gl;
+            bi[b].gu = gu;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a2: root representation (one workgroup of 256 per block)
+// ---------------------------------------------------------------------------
+template <class Y>
+__global__ void __launch_bounds__(256)
+k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
+       const double* __restrict__ Te, Params prm, Y* __restrict__ rep_d, Y* __restrict__ rep_lld,
+       Y* __restrict__ rep_e, double* __restrict__ d64, double* __restrict__ lld64,
+       Node* __restrict__ nodes, Slot* __restrict__ slots, int* __restrict__ status) {
+    __shared__ double sx[256];
+    __shared__ int sc[256];
+    __shared__ double s_lo, s_hi, s_mu;
+    __shared__ int s_ok, s_right;
+    const int bidx = blockIdx.x;
+    const int t = threadIdx.x;
+    const Block blk = blocks[bidx];
+    const int64_t n = blk.n;
+    if (n == 0) return;
+    const double* td = Td + blk.row0;
+    const double* te = Te + blk.row0;
+    const double gl = blk.gl, gu = blk.gu;
+    const double spd = fmax(gu - gl, 1e-300);
+    // which end: all eigenvalues -> the more populated end; a subset -> the
+    // end nearer to the requested indices
+    if (t == 0) {
+        int right;
+        if (blk.il == 1 && blk.iu == n) {
+            const int c1 = sturm_T(td, te, n, gl + 0.25 * spd);
+            const int c3 = sturm_T(td, te, n, gu - 0.25 * spd);
+            right = ((int64_t)n - c3 > c1) ? 1 : 0;
+        } else {
+            right = (blk.il + blk.iu > n + 1) ? 1 : 0;
+        }
+        s_right = right;
+        s_lo = gl - 1e-3 * spd;
+        s_hi = gu + 1e-3 * spd;
+    }
+    __syncthreads();
+    const int right = s_right;
+    // bracket the extreme eigenvalue by multisection (4 rounds x 255 points)
+    const int64_t target = right ? n - 1 : 0;  // count threshold
+    for (int round = 0; round < 4; ++round) {
+        const double lo = s_lo, hi = s_hi;
+        const double x = lo + (hi - lo) * ((double)(t + 1) / 256.0);
+        sx[t] = x;
+        sc[t] = (t < 255) ? sturm_T(td, te, n, x) : (int)n;
+        __syncthreads();
+        if (t == 0) {
+            int f = 255;
+            for (int q = 0; q < 255; ++q)
+                if (sc[q] > target) { f = q; break; }
+            s_lo = (f > 0) ? sx[f - 1] : lo;
+            s_hi = (f < 255) ? sx[f] : hi;
+        }
+        __syncthreads();
+    }
+    // shift and factor T - mu I = L D L^T in binary64 (continuant form:
+    // q_i = (a_i - mu) q_{i-1} - e_{i-1}^2 q_{i-2},  d_i = q_i / q_{i-1})
+    double delta = fmax(2.0 * (s_hi - s_lo), 8.0 * (double)n * 1.1102230246251565e-16);
+    for (int attempt = 0; attempt < 40; ++attempt) {
+        if (t == 0) {
+            const double mu = right ? s_hi + delta : s_lo - delta;
+            s_mu = mu;
+            int ok = 1;
+            double qm = 1.0, q = td[0] - mu;
+            d64[blk.row0] = q;
+            ok &= right ? (q < 0.0) : (q > 0.0);
+            for (int64_t i = 1; i < n; ++i) {
+                const double ee = te[i - 1];
+                const double qn = __fma_rn(td[i] - mu, q, -(ee * ee) * qm);
+                const double di = qn / q;
+                d64[blk.row0 + i] = di;
+                ok &= right ? (di < 0.0) : (di > 0.0);
+                qm = q;
+                q = qn;
+                if ((i & 3) == 0) {
+                    const int em = max(dexp(q), dexp(qm));
+                    q = __builtin_ldexp(q, -em);
+                    qm = __builtin_ldexp(qm, -em);
+                }
+            }
+            s_ok = ok;
+        }
+        __syncthreads();
+        if (s_ok) break;
+        delta *= 4.0;
+        __syncthreads();
+    }
+    if (!s_ok) {
+        if (t == 0) atomicOr(status, 1);
+        return;
+    }
+    const double mu = s_mu;
+    // random relative perturbation of the data in y (Alg. 1 line 2), keyed by
+    // the row index within the problem so that results do not depend on how
+    // problems are batched
+    const Y one = y_from(1.0, Y());
+    for (int64_t i = t; i < n; i += blockDim.x) {
+        const unsigned long long row = (unsigned long long)(blk.start + i);
+        const unsigned long long key = prm.seed + 0x9E37ull * (unsigned long long)blk.prob;
+        const double xi_d = prm.xi * urand_pm1(key, row, 0);
+        const Y dt = mul(y_from(d64[blk.row0 + i], Y()), add_acc(one, y_from(xi_d, Y())));
+        rep_d[blk.row0 + i] = dt;
+    }
+    __syncthreads();
+    for (int64_t i = t; i < n; i += blockDim.x) {
+        const unsigned long long row = (unsigned long long)(blk.start + i);
+        const unsigned long long key = prm.seed + 0x9E37ull * (unsigned long long)blk.prob;
+        const Y dt = rep_d[blk.row0 + i];
+        Y ll = y_from(0.0, Y());
+        Y et = y_from(0.0, Y());
+        if (i + 1 < n) {
+            const double xi_e = prm.xi * urand_pm1(key, row, 1);
+            et = mul(y_from(te[i], Y()), add_acc(one, y_from(xi_e, Y())));
+            ll = div(mul(et, et), dt);
+        }
+        rep_e[blk.row0 + i] = et;
+        rep_lld[blk.row0 + i] = ll;
+        d64[blk.row0 + i] = to_double(dt);
+        lld64[blk.row0 + i] = to_double(ll);
+    }
+    // root node and initial intervals of the block's slots
+    const double slack = 16.0 * prm.xi + 64.0 * 1.1102230246251565e-16;
+    double ilo, ihi;
+    if (right) {
+        ilo = (gl - mu) * (1.0 + slack) - 1e-300;
+        ihi = 0.0;
+    } else {
+        ilo = 0.0;
+        ihi = (gu - mu) * (1.0 + slack) + 1e-300;
+    }
+    if (t == 0) {
+        Node nd;
+        nd.block = bidx;
+        nd.depth = 0;
+        nd.rep = blk.row0;
+        nd.first = blk.slot0;
+        nd.last = blk.slot0 + blk.nslot - 1;
+        nd.sigma_hi = mu;
+        nd.sigma_lo = 0.0;
+        nd.spdiam = spd;
+        nodes[bidx] = nd;
+    }
+    for (int64_t s = blk.slot0 + t; s < blk.slot0 + blk.nslot; s += blockDim.x) {
+        slots[s].node = bidx;
+        slots[s].lo = ilo;
+        slots[s].hi = ihi;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// eigenvector products P_k = prod_{j<k} (-1/e_j), Q_k = prod_{j>=k, j<n-1} (-1/e_j)
+// kept as (y mantissa, binary exponent); one workgroup of 256 per block
+// ---------------------------------------------------------------------------
+template <class Y>
+__device__ __forceinline__ void normalise(Y& m, int& e) {
+    const int k = y_exp(m);
+    m = y_ldexp(m, -k);
+    e += k;
+}
+
+template <class Y>
+__global__ void __launch_bounds__(256)
+k_pq(const Block* __restrict__ blocks, const Y* __restrict__ rep_e, Y* __restrict__ P,
+     int* __restrict__ Pe, Y* __restrict__ Q, int* __restrict__ Qe) {
+    __shared__ Y sm[256];
+    __shared__ int se[256];
+    const Block blk = blocks[blockIdx.x];
+    const int t = threadIdx.x;
+    const int64_t n = blk.n;
+    if (n == 0) return;
+    const Y* e = rep_e + blk.row0;
+    const int64_t chunk = (n + blockDim.x - 1) / blockDim.x;
+    const int64_t c0 = min(n, (int64_t)t * chunk), c1 = min(n, c0 + chunk);
+    const Y one = y_from(1.0, Y());
+    // prefix products
+    Y m = one;
+    int ex = 0;
+    for (int64_t j = c0; j < c1; ++j)
+        if (j + 1 < n) { m = mul(m, neg(div(one, e[j]))); normalise(m, ex); }
+    sm[t] = m;
+    se[t] = ex;
+    __syncthreads();
+    if (t == 0) {
+        Y run = one;
+        int re = 0;
+        for (int q = 0; q < (int)blockDim.x; ++q) {
+            Y v = sm[q];
+            int ve = se[q];
+            sm[q] = run;
+            se[q] = re;
+            run = mul(run, v);
+            re += ve;
+            normalise(run, re);
+        }
+    }
+    __syncthreads();
+    m = sm[t];
+    ex = se[t];
+    for (int64_t j = c0; j < c1; ++j) {
+        P[blk.row0 + j] = m;
+        Pe[blk.row0 + j] = ex;
+        if (j + 1 < n) { m = mul(m, neg(div(one, e[j]))); normalise(m, ex); }
+    }
+    __syncthreads();
+    // suffix products
+    m = one;
+    ex = 0;
+    for (int64_t j = c1 - 1; j >= c0; --j)
+        if (j + 1 < n) { m = mul(m, neg(div(one, e[j]))); normalise(m, ex); }
+    sm[t] = m;
+    se[t] = ex;
+    __syncthreads();
+    if (t == 0) {
+        Y run = one;
+        int re = 0;
+        for (int q = (int)blockDim.x - 1; q >= 0; --q) {
+            Y v = sm[q];
+            int ve = se[q];
+            sm[q] = run;
+            se[q] = re;
+            run = mul(run, v);
+            re += ve;
+            normalise(run, re);
+        }
+    }
+    __syncthreads();
+    m = sm[t];
+    ex = se[t];
+    for (int64_t j = c1 - 1; j >= c0; --j) {
+        if (j + 1 < n) { m = mul(m, neg(div(one, e[j]))); normalise(m, ex); }
+        Q[blk.row0 + j] = m;
+        Qe[blk.row0 + j] = ex;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a3: multisection on Sturm counts (L lanes per slot, groups inside a wave)
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ void __launch_bounds__(256)
+k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slots,
+         const Node* __restrict__ nodes, const Block* __restrict__ blocks,
+         const double* __restrict__ d64, const double* __restrict__ lld64, double rtol,
+         double widen) {
+    constexpr int G = 256 / L;
+    const int g = threadIdx.x / L;
+    const int q = threadIdx.x % L;
+    const int64_t idx = (int64_t)blockIdx.x * G + g;
+    const bool active = idx < count;
+    int64_t s = 0, n = 0, j = 0;
+    double lo = 0.0, hi = 0.0;
+    const double* D = d64;
+    const double* LL = lld64;
+    if (active) {
+        s = list[idx];
+        const Slot sl = slots[s];
+        const Node nd = nodes[sl.node];
+        n = blocks[nd.block].n;
+        D = d64 + nd.rep;
+        LL = lld64 + nd.rep;
+        j = sl.idx;
+        lo = sl.lo;
+        hi = sl.hi;
+    }
+    const int lane = threadIdx.x & 63;
+    const int gbase = lane - q;  // first lane of this group within the wave
+    // make sure the bracket holds: count(lo) <= j-1 < count(hi)
+    bool fix = active;
+    for (int it = 0; it < 64; ++it) {
+        int cl = 0, ch = 0;
+        if (fix) {
+            if (q == 0) cl = negcount64(D, LL, n, lo);
+            if (q == 1 || L == 1) ch = negcount64(D, LL, n, hi);
+        }
+        // share within the group
+        const int cl0 = __shfl(cl, gbase, 64);
+        const int ch0 = (L == 1) ? ch : __shfl(ch, gbase + 1, 64);
+        bool okb = !fix || (cl0 <= j - 1 && ch0 >= j);
+        if (fix && !okb) {
+            const double w = fmax(hi - lo, fmax(fabs(lo), fabs(hi)) * 1e-15) + 1e-300;
+            if (cl0 > j - 1) lo -= w;
+            if (ch0 < j) hi += w;
+        }
+        fix = fix && !okb;
+        if (!__any(fix)) break;
+    }
+    // multisection until the relative width reaches rtol
+    bool busy = active;
+    for (int it = 0; it < 400; ++it) {
+        if (busy) {
+            const double w = hi - lo;
+            const double scale = fmax(fabs(lo), fabs(hi));
+            if (w <= rtol * scale || w <= 1e-300 || !(w > 0.0)) busy = false;
+        }
+        if (!__any(busy)) break;
+        const double h = (hi - lo) / (double)(L + 1);
+        const double x = lo + h * (double)(q + 1);
+        int c = 0;
+        if (busy) c = negcount64(D, LL, n, x);
+        const unsigned long long m = __ballot(busy && c >= j);
+        if (busy) {
+            const unsigned long long gm = (m >> gbase) & ((L == 64) ? ~0ull : ((1ull << L) - 1ull));
+            const int f = gm ? __builtin_ctzll(gm) : L;  // first point with count >= j
+            const double nlo = (f > 0) ? lo + h * (double)f : lo;
+            const double nhi = (f < L) ? lo + h * (double)(f + 1) : hi;
+            if (nlo == lo && nhi == hi) busy = false;
+            lo = nlo;
+            hi = nhi;
+        }
+    }
+    if (active && q == 0) {
+        const double w = widen * fmax(fabs(lo), fabs(hi));
+        slots[s].lo = lo - w;
+        slots[s].hi = hi + w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a4: classification (one workgroup per node)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double reldist(const Slot& a, const Slot& b) {
+    const double den = fmax(fmax(fabs(a.lo), fabs(a.hi)), fmax(fabs(b.lo), fabs(b.hi)));
+    if (den == 0.0) return MR3_BIG;
+    return (b.lo - a.hi) / den;
+}
+
+__global__ void __launch_bounds__(256)
+k_classify(const int64_t* __restrict__ node_list, int64_t count, const Node* __restrict__ nodes,
+           Slot* __restrict__ slots, int* __restrict__ start_flag, double gaptol, int force_single) {
+    const int64_t ni = node_list[blockIdx.x];
+    const Node nd = nodes[ni];
+    const int t = threadIdx.x;
+    for (int64_t s = nd.first + t; s <= nd.last; s += blockDim.x) {
+        int f = 1;
+        if (s > nd.first && !force_single) f = reldist(slots[s - 1], slots[s]) >= gaptol;
+        start_flag[s] = f;
+    }
+    __syncthreads();
+    for (int64_t s = nd.first + t; s <= nd.last; s += blockDim.x) {
+        if (!start_flag[s]) continue;
+        int64_t e = s;
+        while (e < nd.last && !start_flag[e + 1]) ++e;
+        bool req = false;
+        for (int64_t u = s; u <= e; ++u) req |= (slots[u].out >= 0);
+        const double lg = (s > nd.first) ? slots[s].lo - slots[s - 1].hi : slots[s].lgap;
+        const double rg = (e < nd.last) ? slots[e + 1].lo - slots[e].hi : slots[e].rgap;
+        if (e == s) {
+            slots[s].kind = req ? KIND_SINGLETON : KIND_HELPER;
+            slots[s].lgap = lg;
+            slots[s].rgap = rg;
+        } else if (req) {
+            slots[s].kind = KIND_CLUSTER_HEAD;
+            slots[s].run_end = e;
+            slots[s].lgap = lg;
+            slots[e].rgap = rg;
+            for (int64_t u = s + 1; u <= e; ++u) slots[u].kind = KIND_CLUSTER_MEMBER;
+        } else {
+            for (int64_t u = s; u <= e; ++u) slots[u].kind = KIND_DROPPED;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a6: Rayleigh quotient iteration with twisted factorizations
+// one wave per 32 singletons; lane 2q sweeps top-down, lane 2q+1 bottom-up
+// ---------------------------------------------------------------------------
+template <class Y>
+struct Half {  // per-lane sweep output
+    Y sp;        // s_r (top lane) or p_r (bottom lane)
+    double zr;   // z at the twist row, in the lane's storage frame
+    double ss;   // sum of squares of stored z, storage frame
+    double zmax; // largest |stored z| and its signed value / row
+    double zmaxv;
+    int64_t zmaxk;
+    int64_t ev1, ev2;  // rebasing events (see below)
+    double ev2f;
+};
+
+// One sweep of one lane at shift tau with twist index r.  The top lane
+// (top == true) runs the stationary transform over rows 0..r, the bottom lane
+// the progressive one over rows n-1..r, and each stores its part of z
+// (rows < r resp. > r) into its tile column.  Stored values are kept below
+// 2^400 by rebasing the storage exponent; the output kernel multiplies values
+// stored before the last rebase by ev2f and zeroes those stored before the
+// one-but-last (they are below 2^-400 of the final maximum).
+template <class Y>
+__device__ Half<Y> sweep(bool top, const Y* __restrict__ D, const Y* __restrict__ LL,
+                         const Y* __restrict__ PQ, const int* __restrict__ PQe, int64_t n,
+                         int64_t r, Y tau, double* __restrict__ col, bool store, int64_t steps) {
+    Half<Y> h;
+    h.ss = 0.0;
+    h.zmax = 0.0;
+    h.zmaxv = 0.0;
+    h.zmaxk = -1;
+    h.zr = 0.0;
+    h.ev1 = top ? 0 : n;
+    h.ev2 = top ? 0 : n;
+    h.ev2f = 1.0;
+    Y a, b;
+    if (top) {
+        a = neg(tau);
+        b = y_from(1.0, Y());
+    } else {
+        a = (steps > 0) ? sub(D[n - 1], tau) : neg(tau);
+        b = y_from(1.0, Y());
+    }
+    int eb = 0;    // binary exponent carried by b
+    int eref = 0;  // storage frame exponent
+    for (int64_t it = 0; it < steps; ++it) {
+        const int64_t k = top ? it : n - 1 - it;
+        const bool last = (k == r);
+        // z_k = PQ_k * b * 2^(PQe_k + eb - eref)
+        const Y pb = mul(PQ[k], b);
+        int ex = PQe[k] + eb - eref;
+        const int ez = y_exp(pb) + ex;
+        if (ez > 400) {
+            const int dlt = ez;
+            eref += dlt;
+            ex -= dlt;
+            h.ss = __builtin_ldexp(h.ss, -2 * dlt);
+            h.zmax = __builtin_ldexp(h.zmax, -dlt);
+            h.zmaxv = __builtin_ldexp(h.zmaxv, -dlt);
+            h.ev1 = h.ev2;
+            h.ev2 = k;
+            h.ev2f = __builtin_ldexp(1.0, -dlt);
+        }
+        const double zv = __builtin_ldexp(to_double(pb), ex);
+        if (last) {
+            h.zr = zv;
+            break;
+        }
+        if (store) col[k * 32] = zv;
+        h.ss = __fma_rn(zv, zv, h.ss);
+        if (fabs(zv) > h.zmax) {
+            h.zmax = fabs(zv);
+            h.zmaxv = zv;
+            h.zmaxk = k;
+        }
+        // advance the recurrence past row k
+        Y c;
+        if (top) {
+            c = mul_add(D[k], b, a);
+            a = sub(mul(LL[k], a), mul(tau, c));
+        } else {
+            c = mul_add(LL[k - 1], b, a);
+            a = sub(mul(D[k - 1], a), mul(tau, c));
+        }
+        b = c;
+        if ((it & 3) == 3) {
+            const int em = max(y_exp(a), y_exp(b));
+            a = y_ldexp(a, -em);
+            b = y_ldexp(b, -em);
+            eb += em;
+        }
+    }
+    h.sp = div(a, b);  // s_r = a_r / b_r  or  p_r = alpha_r / beta_r
+    return h;
+}
+
+template <class Y>
+__device__ __forceinline__ Y shfl_y(Y v, int src);
+template <>
+__device__ __forceinline__ double shfl_y<double>(double v, int src) { return __shfl(v, src, 64); }
+template <>
+__device__ __forceinline__ dd shfl_y<dd>(dd v, int src) {
+    return mk_dd(__shfl(v.hi, src, 64), __shfl(v.lo, src, 64));
+}
+
+template <class Y>
+__global__ void __launch_bounds__(64)
+k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict__ tile_off,
+      double* __restrict__ tiles, const Slot* __restrict__ slots, const Node* __restrict__ nodes,
+      const Block* __restrict__ blocks, const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld,
+      const double* __restrict__ d64, const double* __restrict__ lld64, const Y* __restrict__ P,
+      const int* __restrict__ Pe, const Y* __restrict__ Q, const int* __restrict__ Qe, Params prm,
+      double eps_y, RqiResult* __restrict__ res, unsigned long long* __restrict__ counters) {
+    const int lane = threadIdx.x;
+    const int pair = lane >> 1;
+    const bool top = (lane & 1) == 0;
+    const int64_t idx = (int64_t)blockIdx.x * 32 + pair;
+    const bool active = idx < count;
+    double* tile = tiles + tile_off[blockIdx.x] + pair;
+    int64_t n = 0, rep = 0, brow = 0;
+    double lo = 0, hi = 0, gap = 0, spd = 1;
+    if (active) {
+        const Slot sl = slots[list[idx]];
+        const Node nd = nodes[sl.node];
+        const Block bk = blocks[nd.block];
+        n = bk.n;
+        rep = nd.rep;
+        brow = bk.row0;
+        lo = sl.lo;
+        hi = sl.hi;
+        spd = nd.spdiam;
+        double lg = sl.lgap, rg = sl.rgap;
+        if (!(lg > 0.0)) lg = (lg < 0.0) ? MR3_BIG : fmax(hi - lo, 1e-300);
+        if (!(rg > 0.0)) rg = (rg < 0.0) ? MR3_BIG : fmax(hi - lo, 1e-300);
+        gap = fmin(fmin(lg, rg), spd);
+    }
+    const Y* D = rep_d + rep;
+    const Y* LL = rep_lld + rep;
+    const double* D64 = d64 + rep;
+    const double* LL64 = lld64 + rep;
+    // ---- twist index from a binary64 pass on the copy (argmin |gamma_k|) ----
+    const double tau0 = 0.5 * (lo + hi);
+    const int64_t hh = n / 2;
+    double a = 0, b = 1;
+    if (top) { a = -tau0; b = 1.0; } else if (n > 0) { a = D64[n - 1] - tau0; b = 1.0; }
+    const int64_t len1 = active ? (top ? hh : n - hh) : 0;
+    const int64_t len2 = active ? (top ? n - hh : hh) : 0;
+    for (int64_t it = 0; it < len1; ++it) {
+        const int64_t k = top ? it : n - 1 - it;
+        tile[k * 32] = a / b;
+        double c;
+        if (top) {
+            c = __fma_rn(D64[k], b, a);
+            a = __fma_rn(-tau0, c, LL64[k] * a);
+        } else {
+            if (k == 0) break;
+            c = __fma_rn(LL64[k - 1], b, a);
+            a = __fma_rn(-tau0, c, D64[k - 1] * a);
+        }
+        b = c;
+        if ((it & 3) == 3) {
+            const int em = max(dexp(a), dexp(b));
+            a = __builtin_ldexp(a, -em);
+            b = __builtin_ldexp(b, -em);
+        }
+    }
+    __syncthreads();
+    double gmin = INFINITY;
+    int64_t rmin = n / 2;
+    for (int64_t it = 0; it < len2; ++it) {
+        const int64_t k = top ? hh + it : hh - 1 - it;
+        const double g = fabs(a / b + tile[k * 32] + tau0);
+        if (g < gmin || (g == gmin && k < rmin)) { gmin = g; rmin = k; }
+        double c;
+        if (top) {
+            if (k == n - 1) break;
+            c = __fma_rn(D64[k], b, a);
+            a = __fma_rn(-tau0, c, LL64[k] * a);
+        } else {
+            if (k == 0) break;
+            c = __fma_rn(LL64[k - 1], b, a);
+            a = __fma_rn(-tau0, c, D64[k - 1] * a);
+        }
+        b = c;
+        if ((it & 3) == 3) {
+            const int em = max(dexp(a), dexp(b));
+            a = __builtin_ldexp(a, -em);
+            b = __builtin_ldexp(b, -em);
+        }
+    }
+    {
+        const double go = __shfl_xor(gmin, 1, 64);
+        const int64_t ro = __shfl_xor(rmin, 1, 64);
+        if (go < gmin || (go == gmin && ro < rmin)) { gmin = go; rmin = ro; }
+    }
+    int64_t r = rmin;
+    if (r < 0 || r >= n) r = n / 2;
+    __syncthreads();
+    // ---- RQI in y at a fixed twist ----
+    const double sqn = sqrt((double)(n > 0 ? n : 1));
+    const double tol = prm.k_rs * gap * prm.eps_x * sqn;
+    Y lam = y_from(tau0, Y());
+    bool done = !active;
+    bool fallback = prm.force_rqi_fallback != 0;
+    int iters = 0;
+    Half<Y> mine;
+    mine.sp = lam;
+    mine.zr = 1.0;
+    mine.ss = 0.0;
+    mine.zmax = 0.0;
+    mine.zmaxv = 0.0;
+    mine.zmaxk = -1;
+    mine.ev1 = top ? 0 : n;
+    mine.ev2 = top ? 0 : n;
+    mine.ev2f = 1.0;
+    Y lam_out = lam;
+    double nz2 = 1.0;
+    double zT = 1, zB = 1;
+    for (int it = 0; it < prm.rqi_max_iter && !fallback; ++it) {
+        if (!__any(!done)) break;
+        const int64_t steps = done ? 0 : (top ? r + 1 : n - r);
+        Half<Y> h = sweep<Y>(top, D, LL, top ? P + brow : Q + brow, top ? Pe + brow : Qe + brow,
+                             n, r, lam, tile, true, steps);
+        const Y spo = shfl_y<Y>(h.sp, lane ^ 1);
+        const double zro = __shfl_xor(h.zr, 1, 64);
+        const double sso = __shfl_xor(h.ss, 1, 64);
+        if (done) continue;
+        ++iters;
+        const Y s_r = top ? h.sp : spo;
+        const Y p_r = top ? spo : h.sp;
+        const double zrT = top ? h.zr : zro, zrB = top ? zro : h.zr;
+        const double ssT = top ? h.ss : sso, ssB = top ? sso : h.ss;
+        const Y gam = add_acc(add_acc(s_r, p_r), lam);
+        const double nrm2 = 1.0 + (n > 1 ? ssT / (zrT * zrT) : 0.0) * (r > 0 ? 1.0 : 0.0) +
+                            (r < n - 1 ? ssB / (zrB * zrB) : 0.0);
+        const double g = to_double(gam);
+        if (!(nrm2 >= 1.0) || !isfinite(nrm2) || zrT == 0.0 || zrB == 0.0) {
+            fallback = true;
+            break;
+        }
+        const double resid = fabs(g) / sqrt(nrm2);
+        const double corr = g / nrm2;
+        const Y lnew = add(lam, y_from(corr, Y()));
+        mine = h;
+        lam_out = lnew;
+        nz2 = nrm2;
+        zT = zrT;
+        zB = zrB;
+        if (resid <= tol || fabs(corr) <= 4.0 * eps_y * fabs(hi_of(lam))) {
+            done = true;
+            continue;
+        }
+        const double lh = hi_of(lnew);
+        if (!(lh >= lo && lh <= hi)) {
+            fallback = true;
+            break;
+        }
+        lam = lnew;
+        // move the twist to the largest entry if the current one is poor
+        const double relT = h.zmax / fabs(zrT), relB = h.zmax / fabs(zrB);
+        const double mT = top ? relT : __shfl_xor(relT, 1, 64);
+        const double mB = top ? __shfl_xor(relB, 1, 64) : relB;
+        const int64_t kT = top ? h.zmaxk : __shfl_xor(h.zmaxk, 1, 64);
+        const int64_t kB = top ? __shfl_xor(h.zmaxk, 1, 64) : h.zmaxk;
+        if (fmax(mT, mB) > 2.0) r = (mT >= mB) ? kT : kB;
+    }
+    // both lanes of a pair agree on `fallback`; a pair that did not converge
+    // in rqi_max_iter iterations also falls back
+    fallback = active && (fallback || !done);
+    if (__any(fallback)) {
+        // bisection in y to relative width eps_x sqrt(n) gaptol, then one
+        // RQI step (Sec. 2 "Rayleigh quotient iteration"; Sec. 3.2)
+        double blo = lo, bhi = hi;
+        Y ylo = y_from(blo, Y()), yhi = y_from(bhi, Y());
+        const double rt = fmax(prm.eps_x * sqn * prm.gaptol, 8.0 * eps_y);
+        bool busy = fallback;
+        for (int it = 0; it < 300; ++it) {
+            if (busy) {
+                const double w = hi_of(sub(yhi, ylo));
+                if (!(w > rt * fmax(fabs(hi_of(ylo)), fabs(hi_of(yhi))))) busy = false;
+            }
+            if (!__any(busy)) break;
+            // two interior points: the top lane takes 1/3, the bottom 2/3
+            const Y w3 = mul(sub(yhi, ylo), y_from(1.0 / 3.0, Y()));
+            const Y x = top ? add(ylo, w3) : add(ylo, add(w3, w3));
+            const int j = (int)slots[list[active ? idx : 0]].idx;
+            int c = busy ? negcount_y<Y>(D, LL, n, x) : 0;
+            const int co = __shfl_xor(c, 1, 64);
+            const Y xo = shfl_y<Y>(x, lane ^ 1);
+            if (busy) {
+                const int c1 = top ? c : co, c2 = top ? co : c;
+                const Y x1 = top ? x : xo, x2 = top ? xo : x;
+                if (c1 >= j) yhi = x1;
+                else if (c2 >= j) { ylo = x1; yhi = x2; }
+                else ylo = x2;
+            }
+        }
+        lam = mul(add(ylo, yhi), y_from(0.5, Y()));
+        const int64_t steps = fallback ? (top ? r + 1 : n - r) : 0;
+        Half<Y> h = sweep<Y>(top, D, LL, top ? P + brow : Q + brow, top ? Pe + brow : Qe + brow, n,
+                             r, lam, tile, true, steps);
+        const Y spo = shfl_y<Y>(h.sp, lane ^ 1);
+        const double zro = __shfl_xor(h.zr, 1, 64);
+        const double sso = __shfl_xor(h.ss, 1, 64);
+        if (fallback) {
+            const Y s_r = top ? h.sp : spo;
+            const Y p_r = top ? spo : h.sp;
+            const double zrT = top ? h.zr : zro, zrB = top ? zro : h.zr;
+            const double ssT = top ? h.ss : sso, ssB = top ? sso : h.ss;
+            const Y gam = add_acc(add_acc(s_r, p_r), lam);
+            const double nrm2 = 1.0 + (r > 0 ? ssT / (zrT * zrT) : 0.0) +
+                                (r < n - 1 ? ssB / (zrB * zrB) : 0.0);
+            mine = h;
+            lam_out = add(lam, y_from(to_double(gam) / nrm2, Y()));
+            nz2 = nrm2;
+            zT = zrT;
+            zB = zrB;
+            ++iters;
+        }
+    }
+    // exchange the per-lane storage bookkeeping and publish the result
+    const double zmaxo = __shfl_xor(mine.zmax, 1, 64);
+    const double zmaxvo = __shfl_xor(mine.zmaxv, 1, 64);
+    const int64_t ev1o = __shfl_xor(mine.ev1, 1, 64);
+    const int64_t ev2o = __shfl_xor(mine.ev2, 1, 64);
+    const double ev2fo = __shfl_xor(mine.ev2f, 1, 64);
+    if (active && top) {
+        const double nz = sqrt(nz2);
+        // sign: largest entry of the final vector positive
+        const double cT = (r > 0) ? mine.zmax / fabs(zT) : 0.0;
+        const double cB = (r < n - 1) ? zmaxo / fabs(zB) : 0.0;
+        double sgn = 1.0;
+        if (cT > 1.0 && cT >= cB) sgn = ((mine.zmaxv < 0) != (zT < 0)) ? -1.0 : 1.0;
+        else if (cB > 1.0) sgn = ((zmaxvo < 0) != (zB < 0)) ? -1.0 : 1.0;
+        RqiResult o;
+        const Y lam_T = add(lam_out, y_from(0.0, Y()));
+        o.lam_hi = hi_of(lam_T);
+        o.lam_lo = to_double(sub(lam_T, y_from(hi_of(lam_T), Y())));
+        o.fT = sgn / (zT * nz);
+        o.fB = sgn / (zB * nz);
+        o.rowr = sgn / nz;
+        o.r = r;
+        o.evT1 = mine.ev1;
+        o.evT2 = mine.ev2;
+        o.evT2f = mine.ev2f;
+        o.evB1 = ev1o;
+        o.evB2 = ev2o;
+        o.evB2f = ev2fo;
+        o.iters = iters;
+        o.status = fallback ? 1 : 0;
+        if (!isfinite(o.fT) || !isfinite(o.fB) || !isfinite(o.rowr)) o.status = 2;
+        res[idx] = o;
+        atomicAdd(&counters[0], (unsigned long long)iters);
+        if (fallback) atomicAdd(&counters[1], 1ull);
+        if (o.status == 2) atomicAdd(&counters[2], 1ull);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a7: output -- eigenvalue, normalised eigenvector rounded to x, coalesced
+// column stores through an LDS transpose (one workgroup per 32 singletons)
+// ---------------------------------------------------------------------------
+template <class X, class Y>
+__global__ void __launch_bounds__(256)
+k_zout(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict__ tile_off,
+       const double* __restrict__ tiles, const Slot* __restrict__ slots,
+       const Node* __restrict__ nodes, const Block* __restrict__ blocks,
+       const ProbInfo* __restrict__ pinfo, const RqiResult* __restrict__ res, X* __restrict__ W,
+       const int64_t* __restrict__ w_off, X* __restrict__ Z, const int64_t* __restrict__ z_off,
+       const int64_t* __restrict__ ldz) {
+    __shared__ double buf[64][33];
+    __shared__ int64_t s_n[32], s_r[32], s_col[32], s_evT1[32], s_evT2[32], s_evB1[32], s_evB2[32];
+    __shared__ double s_fT[32], s_fB[32], s_rowr[32], s_evT2f[32], s_evB2f[32];
+    __shared__ X* s_z[32];
+    __shared__ int64_t s_rows;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * 32;
+    const double* tile = tiles + tile_off[blockIdx.x];
+    if (t < 32) {
+        const int64_t idx = base + t;
+        s_n[t] = 0;
+        if (idx < count) {
+            const Slot sl = slots[list[idx]];
+            const Node nd = nodes[sl.node];
+            const Block bk = blocks[nd.block];
+            const RqiResult o = res[idx];
+            const int p = bk.prob;
+            const int sexp = pinfo[p].sexp;
+            // eigenvalue of T: lambda[M] + sigma, rounded to x, unscaled
+            Y lam = add_acc(mk_y<Y>(o.lam_hi, o.lam_lo), mk_y<Y>(nd.sigma_hi, nd.sigma_lo));
+            W[w_off[p] + sl.out] = (X)__builtin_ldexp(to_double(lam), -sexp);
+            s_n[t] = bk.n;
+            s_r[t] = o.r;
+            s_fT[t] = o.fT;
+            s_fB[t] = o.fB;
+            s_rowr[t] = o.rowr;
+            s_evT1[t] = o.evT1;
+            s_evT2[t] = o.evT2;
+            s_evT2f[t] = o.evT2f;
+            s_evB1[t] = o.evB1;
+            s_evB2[t] = o.evB2;
+            s_evB2f[t] = o.evB2f;
+            s_z[t] = Z ? Z + z_off[p] + sl.out * ldz[p] + bk.start : nullptr;
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        int64_t m = 0;
+        for (int q = 0; q < 32; ++q) m = max(m, s_n[q]);
+        s_rows = m;
+    }
+    __syncthreads();
+    if (Z == nullptr) return;
+    const int64_t rows = s_rows;
+    const int wv = t >> 6, ln = t & 63;
+    for (int64_t r0 = 0; r0 < rows; r0 += 64) {
+        for (int e = t; e < 64 * 32; e += 256) {
+            const int rr = e >> 5, cc = e & 31;
+            buf[rr][cc] = (r0 + rr < rows) ? tile[(r0 + rr) * 32 + cc] : 0.0;
+        }
+        __syncthreads();
+        for (int cc = wv * 8; cc < wv * 8 + 8; ++cc) {
+            const int64_t k = r0 + ln;
+            if (k >= s_n[cc] || s_z[cc] == nullptr) continue;
+            const int64_t r = s_r[cc];
+            double v;
+            if (k < r) {
+                double f = s_fT[cc];
+                if (k < s_evT2[cc]) f = (k >= s_evT1[cc]) ? f * s_evT2f[cc] : 0.0;
+                v = buf[ln][cc] * f;
+            } else if (k == r) {
+                v = s_rowr[cc];
+            } else {
+                double f = s_fB[cc];
+                if (k > s_evB2[cc]) f = (k <= s_evB1[cc]) ? f * s_evB2f[cc] : 0.0;
+                v = buf[ln][cc] * f;
+            }
+            s_z[cc][k] = (X)v;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a5: cluster shifts.  k_child_select evaluates 32 candidate shifts on each
+// side of a cluster in binary64 on the parent's copy (Sturm count check and
+// element growth max |d+_i|); k_child_rep forms the chosen child
+// representation in y.
+// ---------------------------------------------------------------------------
+struct ChildJob {
+    int64_t head;     // first slot of the cluster
+    int64_t last;     // last slot
+    int parent;       // parent node
+    int child;        // new node index
+    int64_t rep;      // first row of the child representation in the pool
+    int64_t tmp;      // first row of the scratch rows
+    double tau;       // chosen shift (parent frame), written by k_child_select
+    int best;         // 1 if no candidate passed the growth test
+    int pad;
+};
+
+__global__ void __launch_bounds__(64)
+k_child_select(ChildJob* __restrict__ jobs, int64_t njobs, const Slot* __restrict__ slots,
+               const Node* __restrict__ nodes, const Block* __restrict__ blocks,
+               const double* __restrict__ d64, const double* __restrict__ lld64, Params prm) {
+    const int64_t jb = blockIdx.x;
+    if (jb >= njobs) return;
+    const int lane = threadIdx.x;
+    ChildJob job = jobs[jb];
+    const Node nd = nodes[job.parent];
+    const int64_t n = blocks[nd.block].n;
+    const Slot sp = slots[job.head], sq = slots[job.last];
+    const double* D = d64 + nd.rep;
+    const double* LL = lld64 + nd.rep;
+    const bool left = lane < 32;
+    const int step = lane & 31;
+    const double wid = fmax(sp.hi - sp.lo, sq.hi - sq.lo);
+    const double delta0 = fmax(0.25 * wid, 4.0 * 1.1102230246251565e-16 *
+                                               fmax(fmax(fabs(sp.lo), fabs(sq.hi)), 1e-300));
+    const double delta = __builtin_ldexp(delta0, step);
+    const double gapo = left ? sp.lgap : sq.rgap;
+    bool valid = !(gapo >= 0.0 && delta > 0.5 * gapo);
+    const double tau = left ? sp.lo - delta : sq.hi + delta;
+    // stationary transform at tau with element growth and inertia
+    double a = -tau, b = 1.0, gmax = 0.0;
+    int negc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double c = __fma_rn(D[i], b, a);
+        negc += sign_differs(c, b);
+        gmax = fmax(gmax, fabs(c / b));
+        a = __fma_rn(-tau, c, LL[i] * a);
+        b = c;
+        if ((i & 3) == 3) {
+            const int em = max(dexp(a), dexp(b));
+            a = __builtin_ldexp(a, -em);
+            b = __builtin_ldexp(b, -em);
+        }
+    }
+    const int64_t want = left ? sp.idx - 1 : sq.idx;
+    valid = valid && (negc == want) && isfinite(gmax);
+    const bool pass = valid && !prm.force_best_candidate && gmax <= prm.k_elg * nd.spdiam;
+    // choose: per side the smallest passing step, then the side with the
+    // smaller growth; if nothing passes, the valid candidate of least growth
+    const unsigned long long pm = __ballot(pass);
+    const unsigned long long vm = __ballot(valid);
+    __shared__ double sg[64], st[64];
+    sg[lane] = valid ? gmax : INFINITY;
+    st[lane] = tau;
+    __syncthreads();
+    if (lane == 0) {
+        int pick = -1, best = 0;
+        const unsigned lmask = (unsigned)(pm & 0xffffffffull), rmask = (unsigned)(pm >> 32);
+        const int lp = lmask ? __builtin_ctz(lmask) : -1;
+        const int rp = rmask ? 32 + __builtin_ctz(rmask) : -1;
+        if (lp >= 0 && rp >= 0) pick = (sg[rp] < sg[lp]) ? rp : lp;
+        else if (lp >= 0) pick = lp;
+        else if (rp >= 0) pick = rp;
+        else if (vm) {
+            best = 1;
+            double g = INFINITY;
+            for (int q = 0; q < 64; ++q)
+                if (((vm >> q) & 1ull) && sg[q] < g) { g = sg[q]; pick = q; }
+        }
+        jobs[jb].tau = (pick >= 0) ? st[pick] : sp.lo - delta0;
+        jobs[jb].best = (pick >= 0) ? best : 2;
+    }
+}
+
+template <class Y>
+__global__ void __launch_bounds__(64)
+k_child_rep(const ChildJob* __restrict__ jobs, int64_t njobs, Slot* __restrict__ slots,
+            Node* __restrict__ nodes, const Block* __restrict__ blocks, Y* __restrict__ rep_d,
+            Y* __restrict__ rep_lld, const Y* __restrict__ rep_e, double* __restrict__ d64,
+            double* __restrict__ lld64, Y* __restrict__ tmpc, int* __restrict__ tmpe, double widen_k,
+            double eps_x) {
+    const int64_t jb = blockIdx.x;
+    if (jb >= njobs) return;
+    const int t = threadIdx.x;
+    const ChildJob job = jobs[jb];
+    const Node pn = nodes[job.parent];
+    const Block bk = blocks[pn.block];
+    const int64_t n = bk.n;
+    const Y* D = rep_d + pn.rep;
+    const Y* LL = rep_lld + pn.rep;
+    const Y* E = rep_e + bk.row0;
+    Y* C = tmpc + job.tmp;
+    int* CE = tmpe + job.tmp;
+    const Y tau = y_from(job.tau, Y());
+    if (t == 0) {
+        // sequential stationary transform in y: c_i = d+_i b_i
+        Y a = neg(tau), b = y_from(1.0, Y());
+        int eb = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            const Y c = mul_add(D[i], b, a);
+            C[i] = c;
+            CE[i] = eb;
+            a = sub(mul(LL[i], a), mul(tau, c));
+            b = c;
+            if ((i & 3) == 3) {
+                const int em = max(y_exp(a), y_exp(b));
+                a = y_ldexp(a, -em);
+                b = y_ldexp(b, -em);
+                eb += em;
+            }
+        }
+    }
+    __syncthreads();
+    Y* cd = rep_d + job.rep;
+    Y* cl = rep_lld + job.rep;
+    for (int64_t i = t; i < n; i += blockDim.x) {
+        // d+_i = c_i / c_{i-1} (c_{-1} = 1), then lld+_i = e_i^2 / d+_i
+        Y dp = C[i];
+        if (i > 0) dp = y_ldexp(div(C[i], C[i - 1]), CE[i] - CE[i - 1]);
+        cd[i] = dp;
+        Y ll = y_from(0.0, Y());
+        if (i + 1 < n) ll = div(mul(E[i], E[i]), dp);
+        cl[i] = ll;
+        d64[job.rep + i] = to_double(dp);
+        lld64[job.rep + i] = to_double(ll);
+    }
+    if (t == 0) {
+        Node c;
+        c.block = pn.block;
+        c.depth = pn.depth + 1;
+        c.rep = job.rep;
+        c.first = job.head;
+        c.last = job.last;
+        const Y sg = add_acc(mk_y<Y>(pn.sigma_hi, pn.sigma_lo), tau);
+        c.sigma_hi = hi_of(sg);
+        c.sigma_lo = to_double(sub(sg, y_from(hi_of(sg), Y())));
+        c.spdiam = pn.spdiam;
+        nodes[job.child] = c;
+    }
+    // move the cluster's slots to the child; intervals in the child frame,
+    // widened by the binary64-copy uncertainty of the parent
+    for (int64_t s = job.head + t; s <= job.last; s += blockDim.x) {
+        const double lo = slots[s].lo, hi = slots[s].hi;
+        const double w = widen_k * (double)n * eps_x * fmax(fabs(lo), fabs(hi));
+        slots[s].node = job.child;
+        slots[s].lo = (lo - job.tau) - w;
+        slots[s].hi = (hi - job.tau) + w;
+        slots[s].kind = KIND_NONE;
+    }
+}
+
+}  // namespace mr3

@@ -1,0 +1,762 @@
+// Host driver and C ABI of the mixed-precision MRRR library.
+//
+// One call runs Algorithm 1 of the paper for every irreducible block of every
+// problem in the call, level by level over the representation trees:
+//   preprocess -> root representations -> bisection -> [classify -> RQI on
+//   singletons + output | child shifts -> child bisection]* -> order check
+// The host only reads back counts (blocks, singletons, clusters, tile sizes)
+// to size the next launches; all arithmetic runs in the kernels.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "../../include/mr3.h"
+#include "mr3_kernels.hip"
+
+namespace mr3 {
+
+// --------------------------------------------------------------------------
+// small device utilities used only by the driver
+// --------------------------------------------------------------------------
+struct SelectKind {
+    const Slot* slots;
+    const Node* nodes;
+    int kind;
+    int depth;
+    __host__ __device__ bool operator()(const int64_t& s) const {
+        const Slot& sl = slots[s];
+        return sl.kind == kind && nodes[sl.node].depth == depth;
+    }
+};
+
+struct SelectDepth {
+    const Slot* slots;
+    const Node* nodes;
+    int depth;
+    __host__ __device__ bool operator()(const int64_t& s) const {
+        return nodes[slots[s].node].depth == depth;
+    }
+};
+
+__global__ void k_chunk_rows(const int64_t* __restrict__ list, int64_t count,
+                             const Slot* __restrict__ slots, const Node* __restrict__ nodes,
+                             const Block* __restrict__ blocks, int64_t* __restrict__ rows,
+                             int64_t nchunk) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nchunk) return;
+    int64_t m = 0;
+    for (int q = 0; q < 32; ++q) {
+        const int64_t i = c * 32 + q;
+        if (i < count) m = max(m, blocks[nodes[slots[list[i]].node].block].n);
+    }
+    rows[c] = m * 32;
+}
+
+struct ClusterRec {
+    int64_t head, last;
+    int parent;
+    int pad;
+};
+
+__global__ void k_cluster_recs(const int64_t* __restrict__ heads, int64_t count,
+                               const Slot* __restrict__ slots, ClusterRec* __restrict__ out) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= count) return;
+    const Slot s = slots[heads[c]];
+    ClusterRec r;
+    r.head = heads[c];
+    r.last = s.run_end;
+    r.parent = s.node;
+    r.pad = 0;
+    out[c] = r;
+}
+
+template <class X>
+__global__ void k_check_sorted(const ProbDesc* __restrict__ probs, const int64_t* __restrict__ m,
+                               const X* __restrict__ W, const int64_t* __restrict__ w_off,
+                               int* __restrict__ bad, int count) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    const X* w = W + w_off[p];
+    int b = 0;
+    for (int64_t i = 1; i < m[p]; ++i) b |= !(w[i - 1] <= w[i]);
+    bad[p] = b;
+}
+
+template <class X>
+__global__ void k_zero_cols(X* __restrict__ Z, int64_t z_off, int64_t ldz, int64_t n, int64_t m) {
+    const int64_t total = n * m;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t col = t / n, row = t % n;
+        Z[z_off + col * ldz + row] = (X)0;
+    }
+}
+
+// --------------------------------------------------------------------------
+// device buffers
+// --------------------------------------------------------------------------
+struct Buf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes, bool keep = false, hipStream_t st = 0) {
+        if (bytes <= cap) return hipSuccess;
+        size_t nc = std::max(bytes, cap + cap / 2);
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, nc);
+        if (e != hipSuccess) return e;
+        if (keep && p && cap) {
+            e = hipMemcpyAsync(q, p, cap, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) { (void)hipFree(q); return e; }
+        }
+        if (p) (void)hipFree(p);
+        p = q;
+        cap = nc;
+        return hipSuccess;
+    }
+    template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+enum BufId {
+    B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BLOCKS, B_SLOTS, B_NODES, B_REPD, B_REPL, B_REPE,
+    B_D64, B_L64, B_P, B_PE, B_Q, B_QE, B_LIST, B_LIST2, B_CNT, B_TILEOFF, B_TILES, B_RES,
+    B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_WOFF, B_ZOFF, B_LDZ, B_M, B_BAD, B_COUNTERS,
+    B_BOFF, B_CREC, B_CHECK, B_NBUF
+};
+
+}  // namespace mr3
+
+struct mr3_handle_s {
+    int device = 0;
+    mr3_params user{};
+    bool have_user = false;
+    mr3::Buf buf[mr3::B_NBUF];
+    mr3_stats stats{};
+};
+
+namespace mr3 {
+
+#define HIPCHK(x)                                              \
+    do {                                                       \
+        hipError_t _e = (x);                                   \
+        if (_e != hipSuccess) {                                \
+            last_hip_error = _e;                               \
+            return MR3_ERR_HIP;                                \
+        }                                                      \
+    } while (0)
+
+static thread_local hipError_t last_hip_error = hipSuccess;
+
+static void defaults(mr3_params* p, int precision) {
+    std::memset(p, 0, sizeof(*p));
+    p->gaptol = (precision == 32) ? 1e-5 : 1e-10;
+    p->bisect_rel = 1e-2 * p->gaptol;
+    p->xi = (precision == 32) ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
+    p->k_elg = 10.0;
+    p->k_rs = 1.0;
+    p->max_depth = 6;
+    p->rqi_max_iter = 10;
+    p->lanes_per_eig = 0;
+    p->seed = 0x5eedull;
+}
+
+static Params effective(const mr3_handle_s* h, int precision) {
+    mr3_params d;
+    defaults(&d, precision);
+    const mr3_params& u = h->user;
+    Params p;
+    p.gaptol = (h->have_user && u.gaptol > 0) ? u.gaptol : d.gaptol;
+    p.bisect_rel = (h->have_user && u.bisect_rel > 0) ? u.bisect_rel : 1e-2 * p.gaptol;
+    p.xi = (h->have_user && u.xi > 0) ? u.xi : d.xi;
+    p.k_elg = (h->have_user && u.k_elg > 0) ? u.k_elg : d.k_elg;
+    p.k_rs = (h->have_user && u.k_rs > 0) ? u.k_rs : d.k_rs;
+    p.eps_x = (precision == 32) ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
+    p.max_depth = (h->have_user && u.max_depth > 0) ? u.max_depth : d.max_depth;
+    p.rqi_max_iter = (h->have_user && u.rqi_max_iter > 0) ? u.rqi_max_iter : d.rqi_max_iter;
+    p.lanes_per_eig = h->have_user ? u.lanes_per_eig : 0;
+    p.force_rqi_fallback = h->have_user ? u.force_rqi_fallback : 0;
+    p.force_best_candidate = h->have_user ? u.force_best_candidate : 0;
+    p.seed = (h->have_user && u.seed) ? u.seed : d.seed;
+    return p;
+}
+
+template <class T>
+static hipError_t upload(Buf& b, const std::vector<T>& v, hipStream_t st) {
+    hipError_t e = b.ensure(std::max<size_t>(1, v.size()) * sizeof(T));
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+template <class T>
+static hipError_t download(std::vector<T>& v, const void* src, size_t count, hipStream_t st) {
+    v.resize(count);
+    if (count == 0) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(v.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
+}
+
+static void launch_bisect(int L, const int64_t* list, int64_t count, Slot* slots, const Node* nodes,
+                          const Block* blocks, const double* d64, const double* l64, double rtol,
+                          double widen, hipStream_t st) {
+    if (count <= 0) return;
+    const int G = 256 / L;
+    const dim3 grid((unsigned)((count + G - 1) / G));
+#define MR3_BIS(LL)                                                                      \
+    case LL:                                                                             \
+        hipLaunchKernelGGL(k_bisect<LL>, grid, dim3(256), 0, st, list, count, slots, nodes, \
+                           blocks, d64, l64, rtol, widen);                               \
+        break;
+    switch (L) {
+        MR3_BIS(1) MR3_BIS(2) MR3_BIS(4) MR3_BIS(8) MR3_BIS(16) MR3_BIS(32) MR3_BIS(64)
+        default:
+            hipLaunchKernelGGL(k_bisect<1>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                               list, count, slots, nodes, blocks, d64, l64, rtol, widen);
+    }
+#undef MR3_BIS
+}
+
+// lanes per eigenvalue: enough lanes to give the device ~64K concurrent
+// counts, at most 64 (one wave), at least 1
+static int pick_lanes(int64_t count, int user) {
+    if (user > 0) {
+        int L = 1;
+        while (L * 2 <= user && L < 64) L *= 2;
+        return L;
+    }
+    int L = 1;
+    while (L < 64 && count * L * 2 <= 65536) L *= 2;
+    return L;
+}
+
+template <class X, class Y>
+static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const int64_t* de_off,
+                      const X* d, const X* e, const mr3_range_desc* ranges, int64_t* m_out, X* W,
+                      const int64_t* w_off_h, X* Z, const int64_t* z_off_h, const int64_t* ldz_h,
+                      hipStream_t st) {
+    const int precision = sizeof(X) == 4 ? 32 : 64;
+    const Params prm = effective(h, precision);
+    const bool is_dd = sizeof(Y) == 16;
+    Buf* B = h->buf;
+    mr3_stats stats{};
+    HIPCHK(hipSetDevice(h->device));
+    // ---- problems ----
+    std::vector<ProbDesc> probs((size_t)count);
+    int64_t R = 0;
+    for (int64_t p = 0; p < count; ++p) {
+        ProbDesc& pd = probs[p];
+        pd.n = n_h[p];
+        pd.in_off = de_off ? de_off[p] : 0;
+        pd.row0 = R;
+        pd.range = ranges ? ranges[p].range : RANGE_ALL;
+        pd.vl = ranges ? ranges[p].vl : 0.0;
+        pd.vu = ranges ? ranges[p].vu : 0.0;
+        pd.il = ranges ? ranges[p].il : 1;
+        pd.iu = ranges ? ranges[p].iu : pd.n;
+        if (pd.range == RANGE_ALL) { pd.il = 1; pd.iu = pd.n; }
+        R += pd.n;
+        m_out[p] = 0;
+    }
+    if (R == 0) { h->stats = stats; return MR3_OK; }
+    HIPCHK(upload(B[B_PROBS], probs, st));
+    HIPCHK(B[B_PINFO].ensure(sizeof(ProbInfo) * count));
+    HIPCHK(B[B_TD].ensure(sizeof(double) * R));
+    HIPCHK(B[B_TE].ensure(sizeof(double) * R));
+    HIPCHK(B[B_BINFO].ensure(sizeof(BlockInfo) * R));
+    hipLaunchKernelGGL(k_prep<X>, dim3((unsigned)count), dim3(256), 0, st, B[B_PROBS].as<ProbDesc>(),
+                       d, e, prm.eps_x, B[B_TD].as<double>(), B[B_TE].as<double>(),
+                       B[B_PINFO].as<ProbInfo>(), B[B_BINFO].as<BlockInfo>());
+    HIPCHK(hipGetLastError());
+    std::vector<ProbInfo> pinfo;
+    HIPCHK(download(pinfo, B[B_PINFO].p, (size_t)count, st));
+    for (int64_t p = 0; p < count; ++p)
+        if (pinfo[p].err) return -6;  // non-finite entry in d or e
+    // ---- blocks (gather the per-problem block records) ----
+    std::vector<Block> blocks;
+    std::vector<BlockInfo> bi;
+    {
+        // block records live at binfo[row0 + b]; fetch each problem's slice
+        std::vector<BlockInfo> all;
+        // one contiguous copy when the blocks are dense enough, else per problem
+        HIPCHK(download(all, B[B_BINFO].p, (size_t)R, st));
+        for (int64_t p = 0; p < count; ++p)
+            for (int b = 0; b < pinfo[p].nblocks; ++b) bi.push_back(all[probs[p].row0 + b]);
+    }
+    std::vector<int> multi(count, 0);
+    std::vector<Slot> slots;
+    std::vector<int64_t> m_p(count, 0);
+    {
+        size_t k = 0;
+        for (int64_t p = 0; p < count; ++p) {
+            multi[p] = pinfo[p].nblocks > 1;
+            for (int b = 0; b < pinfo[p].nblocks; ++b, ++k) {
+                const BlockInfo& x = bi[k];
+                Block bk{};
+                bk.prob = (int)p;
+                bk.row0 = probs[p].row0 + x.start;
+                bk.start = x.start;
+                bk.n = x.n;
+                bk.il = std::max<int64_t>(1, x.il);
+                bk.iu = std::min<int64_t>(x.n, x.iu);
+                bk.gl = x.gl;
+                bk.gu = x.gu;
+                bk.slot0 = (int64_t)slots.size();
+                if (bk.il <= bk.iu) {
+                    const int64_t lo_i = bk.il > 1 ? bk.il - 1 : bk.il;
+                    const int64_t hi_i = bk.iu < bk.n ? bk.iu + 1 : bk.iu;
+                    for (int64_t i = lo_i; i <= hi_i; ++i) {
+                        Slot s{};
+                        s.idx = i;
+                        const bool req = (i >= bk.il && i <= bk.iu);
+                        s.out = req ? (multi[p] ? -2 : (i - bk.il) + (probs[p].range == RANGE_INDEX && !multi[p] ? 0 : 0)) : -1;
+                        if (req && !multi[p]) s.out = i - bk.il;
+                        s.lgap = (i == lo_i) ? (i == 1 ? MR3_BIG : -1.0) : 0.0;
+                        s.rgap = (i == hi_i) ? (i == bk.n ? MR3_BIG : -1.0) : 0.0;
+                        s.kind = KIND_NONE;
+                        slots.push_back(s);
+                    }
+                    m_p[p] += bk.iu - bk.il + 1;
+                }
+                bk.nslot = (int64_t)slots.size() - bk.slot0;
+                blocks.push_back(bk);
+            }
+        }
+    }
+    const int64_t NB = (int64_t)blocks.size();
+    const int64_t K = (int64_t)slots.size();
+    stats.n_blocks = NB;
+    for (int64_t p = 0; p < count; ++p) { m_out[p] = m_p[p]; stats.n_eigenpairs += m_p[p]; }
+    if (K == 0) { h->stats = stats; return MR3_OK; }
+    // nodes: roots first (node index == block index), children appended
+    int64_t node_cap = NB + K;  // each cluster head creates at most one node per level
+    HIPCHK(upload(B[B_BLOCKS], blocks, st));
+    HIPCHK(upload(B[B_SLOTS], slots, st));
+    HIPCHK(B[B_NODES].ensure(sizeof(Node) * (size_t)std::max<int64_t>(node_cap, 1)));
+    // representation pool: root rows first
+    int64_t pool_rows = R;
+    HIPCHK(B[B_REPD].ensure(sizeof(Y) * R));
+    HIPCHK(B[B_REPL].ensure(sizeof(Y) * R));
+    HIPCHK(B[B_D64].ensure(sizeof(double) * R));
+    HIPCHK(B[B_L64].ensure(sizeof(double) * R));
+    HIPCHK(B[B_REPE].ensure(sizeof(Y) * R));
+    HIPCHK(B[B_P].ensure(sizeof(Y) * R));
+    HIPCHK(B[B_Q].ensure(sizeof(Y) * R));
+    HIPCHK(B[B_PE].ensure(sizeof(int) * R));
+    HIPCHK(B[B_QE].ensure(sizeof(int) * R));
+    HIPCHK(B[B_COUNTERS].ensure(sizeof(unsigned long long) * 8 + sizeof(int) * 8));
+    HIPCHK(hipMemsetAsync(B[B_COUNTERS].p, 0, sizeof(unsigned long long) * 8 + sizeof(int) * 8, st));
+    unsigned long long* counters = B[B_COUNTERS].as<unsigned long long>();
+    int* status = reinterpret_cast<int*>(counters + 8);
+    // outputs
+    std::vector<int64_t> w_off(w_off_h, w_off_h + count), z_off(count, 0), ldz(count, 1);
+    if (Z) {
+        for (int64_t p = 0; p < count; ++p) { z_off[p] = z_off_h[p]; ldz[p] = ldz_h[p]; }
+    }
+    HIPCHK(upload(B[B_WOFF], w_off, st));
+    HIPCHK(upload(B[B_ZOFF], z_off, st));
+    HIPCHK(upload(B[B_LDZ], ldz, st));
+    if (Z) {
+        for (int64_t p = 0; p < count; ++p)
+            if (multi[p] && m_p[p] > 0) {
+                const int64_t tot = probs[p].n * m_p[p];
+                const unsigned g = (unsigned)std::min<int64_t>((tot + 255) / 256, 4096);
+                hipLaunchKernelGGL(k_zero_cols<X>, dim3(g), dim3(256), 0, st, Z, z_off[p], ldz[p],
+                                   probs[p].n, m_p[p]);
+            }
+    }
+    Block* dblocks = B[B_BLOCKS].as<Block>();
+    Slot* dslots = B[B_SLOTS].as<Slot>();
+    Node* dnodes = B[B_NODES].as<Node>();
+    // ---- a2: root representations ----
+    hipLaunchKernelGGL(k_root<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_TD].as<double>(),
+                       B[B_TE].as<double>(), prm, B[B_REPD].as<Y>(), B[B_REPL].as<Y>(),
+                       B[B_REPE].as<Y>(), B[B_D64].as<double>(), B[B_L64].as<double>(), dnodes,
+                       dslots, status);
+    hipLaunchKernelGGL(k_pq<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_REPE].as<Y>(),
+                       B[B_P].as<Y>(), B[B_PE].as<int>(), B[B_Q].as<Y>(), B[B_QE].as<int>());
+    HIPCHK(hipGetLastError());
+    // ---- a3: bisection of every slot on its root ----
+    std::vector<int64_t> all_slots((size_t)K);
+    std::iota(all_slots.begin(), all_slots.end(), 0);
+    HIPCHK(upload(B[B_LIST], all_slots, st));
+    const double widen0 = (is_dd ? 10.0 : 4.0) * 1.1102230246251565e-16;  // per unit of n
+    // bisection widening is relative: widen * n_block; blocks differ in n, so
+    // use the largest block (a conservative widening)
+    int64_t nmax = 0;
+    for (auto& b : blocks) nmax = std::max(nmax, b.n);
+    const double widen_root = widen0 * (double)nmax;
+    int L = pick_lanes(K, prm.lanes_per_eig);
+    launch_bisect(L, B[B_LIST].as<int64_t>(), K, dslots, dnodes, dblocks, B[B_D64].as<double>(),
+                  B[B_L64].as<double>(), prm.bisect_rel, widen_root, st);
+    HIPCHK(hipGetLastError());
+    // ---- output columns of split problems: order by eigenvalue ----
+    bool any_multi = false;
+    for (int64_t p = 0; p < count; ++p) any_multi |= (multi[p] && m_p[p] > 0);
+    if (any_multi) {
+        std::vector<Slot> cur;
+        HIPCHK(download(cur, dslots, (size_t)K, st));
+        std::vector<Node> roots;
+        HIPCHK(download(roots, dnodes, (size_t)NB, st));
+        for (int64_t p = 0; p < count; ++p) {
+            if (!multi[p]) continue;
+            std::vector<std::pair<double, int64_t>> v;
+            for (int64_t b = 0; b < NB; ++b) {
+                if (blocks[b].prob != p) continue;
+                for (int64_t s = blocks[b].slot0; s < blocks[b].slot0 + blocks[b].nslot; ++s)
+                    if (cur[s].out == -2)
+                        v.push_back({roots[b].sigma_hi + 0.5 * (cur[s].lo + cur[s].hi), s});
+            }
+            std::stable_sort(v.begin(), v.end(),
+                             [](const std::pair<double, int64_t>& a, const std::pair<double, int64_t>& b) {
+                                 return a.first < b.first;
+                             });
+            for (size_t i = 0; i < v.size(); ++i) cur[v[i].second].out = (int64_t)i;
+        }
+        HIPCHK(upload(B[B_SLOTS], cur, st));
+        dslots = B[B_SLOTS].as<Slot>();
+    }
+    // ---- levels of the representation trees ----
+    std::vector<int64_t> level_nodes((size_t)NB);
+    std::iota(level_nodes.begin(), level_nodes.end(), 0);
+    int64_t n_nodes = NB;
+    HIPCHK(B[B_FLAGS].ensure(sizeof(int) * K));
+    HIPCHK(B[B_LIST2].ensure(sizeof(int64_t) * K));
+    HIPCHK(B[B_CNT].ensure(sizeof(int64_t) * 4));
+    int64_t* dcnt = B[B_CNT].as<int64_t>();
+    hipcub::CountingInputIterator<int64_t> iter(0);
+    for (int depth = 0; !level_nodes.empty(); ++depth) {
+        stats.d_max = std::max(stats.d_max, depth);
+        HIPCHK(upload(B[B_LIST], level_nodes, st));
+        const int force_single = depth >= prm.max_depth;
+        hipLaunchKernelGGL(k_classify, dim3((unsigned)level_nodes.size()), dim3(256), 0, st,
+                           B[B_LIST].as<int64_t>(), (int64_t)level_nodes.size(), dnodes, dslots,
+                           B[B_FLAGS].as<int>(), prm.gaptol, force_single);
+        HIPCHK(hipGetLastError());
+        // compact the singletons and cluster heads of this level
+        size_t tmp_bytes = 0, tb2 = 0;
+        SelectKind sel_s{dslots, dnodes, KIND_SINGLETON, depth};
+        SelectKind sel_c{dslots, dnodes, KIND_CLUSTER_HEAD, depth};
+        HIPCHK(hipcub::DeviceSelect::If(nullptr, tmp_bytes, iter, B[B_LIST].as<int64_t>(), dcnt, K,
+                                        sel_s, st));
+        HIPCHK(hipcub::DeviceSelect::If(nullptr, tb2, iter, B[B_LIST2].as<int64_t>(), dcnt + 1, K,
+                                        sel_c, st));
+        HIPCHK(B[B_CUBTMP].ensure(std::max(tmp_bytes, tb2) + 256));
+        tmp_bytes = B[B_CUBTMP].cap;
+        HIPCHK(hipcub::DeviceSelect::If(B[B_CUBTMP].p, tmp_bytes, iter, B[B_LIST].as<int64_t>(),
+                                        dcnt, K, sel_s, st));
+        tmp_bytes = B[B_CUBTMP].cap;
+        HIPCHK(hipcub::DeviceSelect::If(B[B_CUBTMP].p, tmp_bytes, iter, B[B_LIST2].as<int64_t>(),
+                                        dcnt + 1, K, sel_c, st));
+        std::vector<int64_t> cnts;
+        HIPCHK(download(cnts, dcnt, 2, st));
+        const int64_t S = cnts[0], C = cnts[1];
+        // ---- a6 + a7: singletons ----
+        if (S > 0) {
+            const int64_t nchunk = (S + 31) / 32;
+            HIPCHK(B[B_TILEOFF].ensure(sizeof(int64_t) * (nchunk + 1)));
+            HIPCHK(B[B_FLAGS].ensure(sizeof(int64_t) * (nchunk + 1)));
+            int64_t* rows = reinterpret_cast<int64_t*>(B[B_FLAGS].p);
+            hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)((nchunk + 255) / 256)), dim3(256), 0, st,
+                               B[B_LIST].as<int64_t>(), S, dslots, dnodes, dblocks, rows, nchunk);
+            size_t sb = 0;
+            HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, sb, rows, B[B_TILEOFF].as<int64_t>(),
+                                                    nchunk + 1, st));
+            HIPCHK(B[B_CUBTMP].ensure(sb + 256));
+            sb = B[B_CUBTMP].cap;
+            HIPCHK(hipMemsetAsync(rows + nchunk, 0, sizeof(int64_t), st));
+            HIPCHK(hipcub::DeviceScan::ExclusiveSum(B[B_CUBTMP].p, sb, rows,
+                                                    B[B_TILEOFF].as<int64_t>(), nchunk + 1, st));
+            std::vector<int64_t> tot;
+            HIPCHK(download(tot, B[B_TILEOFF].as<int64_t>() + nchunk, 1, st));
+            HIPCHK(B[B_TILES].ensure(sizeof(double) * std::max<int64_t>(tot[0], 1)));
+            HIPCHK(B[B_RES].ensure(sizeof(RqiResult) * S));
+            hipLaunchKernelGGL(k_rqi<Y>, dim3((unsigned)nchunk), dim3(64), 0, st,
+                               B[B_LIST].as<int64_t>(), S, B[B_TILEOFF].as<int64_t>(),
+                               B[B_TILES].as<double>(), dslots, dnodes, dblocks, B[B_REPD].as<Y>(),
+                               B[B_REPL].as<Y>(), B[B_D64].as<double>(), B[B_L64].as<double>(),
+                               B[B_P].as<Y>(), B[B_PE].as<int>(), B[B_Q].as<Y>(), B[B_QE].as<int>(),
+                               prm, (double)YEps<Y>::v, B[B_RES].as<RqiResult>(), counters);
+            hipLaunchKernelGGL((k_zout<X, Y>), dim3((unsigned)nchunk), dim3(256), 0, st,
+                               B[B_LIST].as<int64_t>(), S, B[B_TILEOFF].as<int64_t>(),
+                               B[B_TILES].as<double>(), dslots, dnodes, dblocks,
+                               B[B_PINFO].as<ProbInfo>(), B[B_RES].as<RqiResult>(), W,
+                               B[B_WOFF].as<int64_t>(), Z, B[B_ZOFF].as<int64_t>(),
+                               B[B_LDZ].as<int64_t>());
+            HIPCHK(hipGetLastError());
+        }
+        level_nodes.clear();
+        if (C == 0) break;
+        // ---- a5: clusters -> child representations ----
+        HIPCHK(B[B_CREC].ensure(sizeof(ClusterRec) * C));
+        hipLaunchKernelGGL(k_cluster_recs, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, st,
+                           B[B_LIST2].as<int64_t>(), C, dslots, B[B_CREC].as<ClusterRec>());
+        std::vector<ClusterRec> crec;
+        HIPCHK(download(crec, B[B_CREC].p, (size_t)C, st));
+        std::vector<Node> pnodes;
+        // parent node info (block of each cluster) from the device
+        std::vector<ChildJob> jobs((size_t)C);
+        int64_t new_rows = 0, tmp_rows = 0;
+        {
+            std::vector<Node> allnodes;
+            HIPCHK(download(allnodes, dnodes, (size_t)n_nodes, st));
+            for (int64_t c = 0; c < C; ++c) {
+                const Node& pn = allnodes[crec[c].parent];
+                const int64_t nb = blocks[pn.block].n;
+                ChildJob j{};
+                j.head = crec[c].head;
+                j.last = crec[c].last;
+                j.parent = crec[c].parent;
+                j.child = (int)(n_nodes + c);
+                j.rep = pool_rows + new_rows;
+                j.tmp = tmp_rows;
+                new_rows += nb;
+                tmp_rows += nb;
+                jobs[c] = j;
+                stats.largest_cluster = std::max<int64_t>(stats.largest_cluster, j.last - j.head + 1);
+            }
+        }
+        stats.n_clusters += C;
+        if (n_nodes + C > node_cap) {
+            node_cap = n_nodes + C + K;
+            HIPCHK(B[B_NODES].ensure(sizeof(Node) * node_cap, true, st));
+            dnodes = B[B_NODES].as<Node>();
+        }
+        const int64_t need = pool_rows + new_rows;
+        HIPCHK(B[B_REPD].ensure(sizeof(Y) * need, true, st));
+        HIPCHK(B[B_REPL].ensure(sizeof(Y) * need, true, st));
+        HIPCHK(B[B_D64].ensure(sizeof(double) * need, true, st));
+        HIPCHK(B[B_L64].ensure(sizeof(double) * need, true, st));
+        HIPCHK(B[B_TMPC].ensure(sizeof(Y) * tmp_rows));
+        HIPCHK(B[B_TMPE].ensure(sizeof(int) * tmp_rows));
+        HIPCHK(upload(B[B_JOBS], jobs, st));
+        hipLaunchKernelGGL(k_child_select, dim3((unsigned)C), dim3(64), 0, st,
+                           B[B_JOBS].as<ChildJob>(), C, dslots, dnodes, dblocks,
+                           B[B_D64].as<double>(), B[B_L64].as<double>(), prm);
+        hipLaunchKernelGGL(k_child_rep<Y>, dim3((unsigned)C), dim3(64), 0, st,
+                           B[B_JOBS].as<ChildJob>(), C, dslots, dnodes, dblocks, B[B_REPD].as<Y>(),
+                           B[B_REPL].as<Y>(), B[B_REPE].as<Y>(), B[B_D64].as<double>(),
+                           B[B_L64].as<double>(), B[B_TMPC].as<Y>(), B[B_TMPE].as<int>(),
+                           is_dd ? 10.0 * 1.1102230246251565e-16 / prm.eps_x : 4.0 * 1.1102230246251565e-16 / prm.eps_x,
+                           prm.eps_x);
+        HIPCHK(hipGetLastError());
+        {
+            std::vector<ChildJob> done_jobs;
+            HIPCHK(download(done_jobs, B[B_JOBS].p, (size_t)C, st));
+            for (auto& j : done_jobs) {
+                if (j.best == 1) stats.n_best_candidate++;
+                if (j.best == 2) return MR3_ERR_NUMERIC;
+            }
+        }
+        pool_rows += new_rows;
+        n_nodes += C;
+        // ---- child bisection (Alg. 1 line 14) ----
+        size_t sb = 0;
+        SelectDepth seld{dslots, dnodes, depth + 1};
+        HIPCHK(hipcub::DeviceSelect::If(nullptr, sb, iter, B[B_LIST].as<int64_t>(), dcnt + 2, K, seld,
+                                        st));
+        HIPCHK(B[B_CUBTMP].ensure(sb + 256));
+        sb = B[B_CUBTMP].cap;
+        HIPCHK(hipcub::DeviceSelect::If(B[B_CUBTMP].p, sb, iter, B[B_LIST].as<int64_t>(), dcnt + 2, K,
+                                        seld, st));
+        std::vector<int64_t> c2;
+        HIPCHK(download(c2, dcnt + 2, 1, st));
+        const int64_t KC = c2[0];
+        L = pick_lanes(KC, prm.lanes_per_eig);
+        launch_bisect(L, B[B_LIST].as<int64_t>(), KC, dslots, dnodes, dblocks, B[B_D64].as<double>(),
+                      B[B_L64].as<double>(), prm.bisect_rel, widen_root, st);
+        HIPCHK(hipGetLastError());
+        for (int64_t c = 0; c < C; ++c) level_nodes.push_back(jobs[c].child);
+    }
+    // ---- diagnostics and the ascending-order check ----
+    std::vector<unsigned long long> ctr;
+    HIPCHK(download(ctr, counters, 8, st));
+    std::vector<int> sts;
+    HIPCHK(download(sts, status, 1, st));
+    stats.n_rqi_iters = (int64_t)ctr[0];
+    stats.n_fallbacks = (int64_t)ctr[1];
+    h->stats = stats;
+    if (sts[0] != 0 || ctr[2] != 0) return MR3_ERR_NUMERIC;
+    std::vector<int64_t> mv(m_p.begin(), m_p.end());
+    HIPCHK(upload(B[B_M], mv, st));
+    HIPCHK(B[B_BAD].ensure(sizeof(int) * count));
+    hipLaunchKernelGGL(k_check_sorted<X>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                       B[B_PROBS].as<ProbDesc>(), B[B_M].as<int64_t>(), W, B[B_WOFF].as<int64_t>(),
+                       B[B_BAD].as<int>(), (int)count);
+    std::vector<int> bad;
+    HIPCHK(download(bad, B[B_BAD].p, (size_t)count, st));
+    for (int64_t p = 0; p < count; ++p) {
+        if (!bad[p]) continue;
+        // rare: eigenvalues equal to working accuracy came out in the wrong
+        // order; sort the pairs on the host
+        const int64_t mp = m_p[p], np = probs[p].n;
+        std::vector<X> w((size_t)mp);
+        HIPCHK(hipMemcpy(w.data(), W + w_off[p], sizeof(X) * mp, hipMemcpyDeviceToHost));
+        std::vector<int64_t> perm((size_t)mp);
+        std::iota(perm.begin(), perm.end(), 0);
+        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return w[a] < w[b]; });
+        std::vector<X> w2((size_t)mp);
+        for (int64_t i = 0; i < mp; ++i) w2[i] = w[perm[i]];
+        HIPCHK(hipMemcpy(W + w_off[p], w2.data(), sizeof(X) * mp, hipMemcpyHostToDevice));
+        if (Z) {
+            std::vector<X> zc((size_t)(np * mp));
+            HIPCHK(hipMemcpy2D(zc.data(), sizeof(X) * np, Z + z_off[p], sizeof(X) * ldz[p],
+                               sizeof(X) * np, mp, hipMemcpyDeviceToHost));
+            std::vector<X> z2((size_t)(np * mp));
+            for (int64_t i = 0; i < mp; ++i)
+                std::memcpy(&z2[i * np], &zc[perm[i] * np], sizeof(X) * np);
+            HIPCHK(hipMemcpy2D(Z + z_off[p], sizeof(X) * ldz[p], z2.data(), sizeof(X) * np,
+                               sizeof(X) * np, mp, hipMemcpyHostToDevice));
+        }
+    }
+    return MR3_OK;
+}
+
+}  // namespace mr3
+
+// --------------------------------------------------------------------------
+// C ABI
+// --------------------------------------------------------------------------
+using namespace mr3;
+
+static int check_single(int64_t n, const void* d, const void* e, int range, double vl, double vu,
+                        int64_t il, int64_t iu, int64_t* m, const void* W, const void* Z,
+                        int64_t ldz) {
+    if (n < 0) return -2;
+    if (n > 0 && !d) return -3;
+    if (n > 1 && !e) return -4;
+    if (range < 0 || range > 2) return -5;
+    if (range == RANGE_VALUE && !(vl < vu)) return -7;
+    if (range == RANGE_INDEX && (il < 1 || iu > n || il > iu + 1)) return (il < 1) ? -8 : -9;
+    if (!m) return -10;
+    if (n > 0 && !W) return -11;
+    if (Z && ldz < std::max<int64_t>(1, n)) return -13;
+    return 0;
+}
+
+template <class X, class Y>
+static int solve_single(mr3_handle h, int64_t n, const X* d, const X* e, int range, double vl,
+                        double vu, int64_t il, int64_t iu, int64_t* m, X* W, X* Z, int64_t ldz,
+                        void* stream) {
+    if (!h) return -1;
+    int rc = check_single(n, d, e, range, vl, vu, il, iu, m, W, Z, ldz);
+    if (rc) return rc;
+    if (range == RANGE_INDEX && il > iu) { *m = 0; return MR3_OK; }
+    mr3_range_desc rd;
+    rd.range = range;
+    rd.vl = vl;
+    rd.vu = vu;
+    rd.il = il;
+    rd.iu = iu;
+    const int64_t nn = n, off = 0, wo = 0, zo = 0, lz = ldz;
+    // e may be NULL for n <= 1: point it at d (never read)
+    const X* ee = e ? e : d;
+    rc = solve_impl<X, Y>(h, 1, &nn, &off, d, ee, &rd, m, W, &wo, Z, &zo, &lz, (hipStream_t)stream);
+    return rc;
+}
+
+extern "C" {
+
+const char* mr3_version(void) { return "mr3-mi355x 0.1"; }
+
+int mr3_create(mr3_handle* h, int device) {
+    if (!h) return -1;
+    int nd = 0;
+    if (hipGetDeviceCount(&nd) != hipSuccess || nd <= 0) return MR3_ERR_NO_DEVICE;
+    if (device < 0 || device >= nd) return -2;
+    mr3_handle_s* x = new mr3_handle_s();
+    x->device = device;
+    *h = x;
+    return MR3_OK;
+}
+
+int mr3_destroy(mr3_handle h) {
+    if (!h) return -1;
+    (void)hipSetDevice(h->device);
+    for (auto& b : h->buf) b.release();
+    delete h;
+    return MR3_OK;
+}
+
+int mr3_default_params(mr3_params* p, int precision) {
+    if (!p) return -1;
+    if (precision != 32 && precision != 64) return -2;
+    defaults(p, precision);
+    return MR3_OK;
+}
+
+int mr3_set_params(mr3_handle h, const mr3_params* p) {
+    if (!h) return -1;
+    if (p) {
+        h->user = *p;
+        h->have_user = true;
+    } else {
+        h->have_user = false;
+    }
+    return MR3_OK;
+}
+
+int mr3_get_stats(mr3_handle h, mr3_stats* s) {
+    if (!h) return -1;
+    if (!s) return -2;
+    *s = h->stats;
+    return MR3_OK;
+}
+
+int mr3_solve_f32(mr3_handle h, int64_t n, const float* d, const float* e, int range, double vl,
+                  double vu, int64_t il, int64_t iu, int64_t* m, float* W, float* Z, int64_t ldz,
+                  void* stream) {
+    return solve_single<float, double>(h, n, d, e, range, vl, vu, il, iu, m, W, Z, ldz, stream);
+}
+
+int mr3_solve_f64(mr3_handle h, int64_t n, const double* d, const double* e, int range, double vl,
+                  double vu, int64_t il, int64_t iu, int64_t* m, double* W, double* Z, int64_t ldz,
+                  void* stream) {
+    return solve_single<double, dd>(h, n, d, e, range, vl, vu, il, iu, m, W, Z, ldz, stream);
+}
+
+int mr3_solve_batched(mr3_handle h, int64_t count, int precision, const int64_t* n,
+                      const int64_t* de_off, const void* d, const void* e,
+                      const mr3_range_desc* ranges, int64_t* m, void* W, const int64_t* w_off,
+                      void* Z, const int64_t* z_off, const int64_t* ldz, void* stream) {
+    if (!h) return -1;
+    if (count < 0) return -2;
+    if (precision != 32 && precision != 64) return -3;
+    if (count == 0) return MR3_OK;
+    if (!n) return -4;
+    if (!de_off) return -5;
+    int64_t tot = 0;
+    for (int64_t p = 0; p < count; ++p) {
+        if (n[p] < 0) return -4;
+        tot += n[p];
+        if (ranges) {
+            const mr3_range_desc& r = ranges[p];
+            if (r.range < 0 || r.range > 2) return -8;
+            if (r.range == RANGE_VALUE && !(r.vl < r.vu)) return -8;
+            if (r.range == RANGE_INDEX && (r.il < 1 || r.iu > n[p] || r.il > r.iu)) return -8;
+        }
+        if (Z && (!z_off || !ldz || ldz[p] < std::max<int64_t>(1, n[p]))) return -14;
+    }
+    if (tot > 0 && (!d || !e)) return -6;
+    if (!m) return -9;
+    if (!W || !w_off) return -10;
+    if (precision == 32)
+        return solve_impl<float, double>(h, count, n, de_off, (const float*)d, (const float*)e, ranges,
+                                         m, (float*)W, w_off, (float*)Z, z_off, ldz,
+                                         (hipStream_t)stream);
+    return solve_impl<double, dd>(h, count, n, de_off, (const double*)d, (const double*)e, ranges, m,
+                                  (double*)W, w_off, (double*)Z, z_off, ldz, (hipStream_t)stream);
+}
+
+}  // extern "C"
