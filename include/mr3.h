@@ -89,6 +89,9 @@ typedef struct {
      * is used */
     int force_rqi_fallback;
     int force_best_candidate;
+    /* 1: time every kernel launch with HIP events recorded on the launch
+     * stream; the per-stage totals appear in mr3_stats */
+    int profile;
 } mr3_params;
 
 /* Diagnostics of the last solve on a handle (Section 4.2 reports d_max and
@@ -102,7 +105,25 @@ typedef struct {
     int64_t n_rqi_iters;      /* RQI iterations summed over eigenvectors */
     int64_t n_fallbacks;      /* eigenvectors that needed the bisection fallback */
     int64_t n_best_candidate; /* shifts accepted as least-growth candidate */
+    /* with mr3_params.profile = 1: device time (ms) and launch count per
+     * stage, indexed by MR3_STAGE_* */
+    double stage_ms[8];
+    int64_t stage_launches[8];
+    /* algorithmic work of the last solve: Sturm-count row steps that plain
+     * bisection needs for the final intervals, and row steps of twisted
+     * sweeps (pre-pass and RQI iterations) */
+    double bisect_row_steps;
+    double rqi_row_steps;
+    double twist_row_steps;
 } mr3_stats;
+
+/* stage indices of mr3_stats.stage_ms */
+#define MR3_STAGE_PREP 0     /* preprocessing, root representation, products */
+#define MR3_STAGE_BISECT 1   /* multisection on Sturm counts (k_bisect) */
+#define MR3_STAGE_CLASSIFY 2 /* classification and list compaction */
+#define MR3_STAGE_RQI 3      /* twisted-factorization RQI (k_rqi) */
+#define MR3_STAGE_ZOUT 4     /* eigenvector output (k_zout) */
+#define MR3_STAGE_CHILD 5    /* cluster shifts (k_child_select, k_child_rep) */
 
 /* Create a handle on HIP device `device`.  Fails with MR3_ERR_NO_DEVICE if it
  * does not exist. */

@@ -26,6 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmr3.so")
 
 RANGE_ALL, RANGE_VALUE, RANGE_INDEX = 0, 1, 2
+STAGES = ["prep", "bisect", "classify", "rqi", "zout", "child"]
 MR3_OK, MR3_ERR_NUMERIC, MR3_ERR_HIP, MR3_ERR_NO_DEVICE = 0, 1, 2, 3
 
 
@@ -48,6 +49,7 @@ class mr3_params(ctypes.Structure):
         ("seed", ctypes.c_ulonglong),
         ("force_rqi_fallback", ctypes.c_int),
         ("force_best_candidate", ctypes.c_int),
+        ("profile", ctypes.c_int),
     ]
 
 
@@ -61,6 +63,11 @@ class mr3_stats(ctypes.Structure):
         ("n_rqi_iters", ctypes.c_int64),
         ("n_fallbacks", ctypes.c_int64),
         ("n_best_candidate", ctypes.c_int64),
+        ("stage_ms", ctypes.c_double * 8),
+        ("stage_launches", ctypes.c_int64 * 8),
+        ("bisect_row_steps", ctypes.c_double),
+        ("rqi_row_steps", ctypes.c_double),
+        ("twist_row_steps", ctypes.c_double),
     ]
 
 
@@ -167,7 +174,11 @@ class Handle:
     def stats(self) -> dict:
         s = mr3_stats()
         _check("mr3_get_stats", load_library().mr3_get_stats(self._h, ctypes.byref(s)))
-        return {f: getattr(s, f) for f, _ in mr3_stats._fields_}
+        out = {}
+        for f, _ in mr3_stats._fields_:
+            v = getattr(s, f)
+            out[f] = list(v) if hasattr(v, "__len__") else v
+        return out
 
 
 def default_params(precision: int = 64) -> mr3_params:

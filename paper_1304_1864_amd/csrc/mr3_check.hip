@@ -59,12 +59,13 @@ k_gram(const double* __restrict__ Z, int64_t ldz, int64_t n, int64_t m, double* 
         }
         __syncthreads();
     }
-    // D layout: lane holds rows 4*(ln/16) + {0..3} of column ln%16
+    // D layout of V_MFMA_F64_16X16X4F64 (checked on the device): register q of
+    // lane ln holds row ln/16 + 4q of column ln%16
     double offmax = 0.0, diagmax = 0.0;
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             for (int q = 0; q < 4; ++q) {
-                const int64_t gi = I0 + qi + a * 16 + 4 * (ln >> 4) + q;
+                const int64_t gi = I0 + qi + a * 16 + (ln >> 4) + 4 * q;
                 const int64_t gj = J0 + qj + b * 16 + (ln & 15);
                 if (gi >= m || gj >= m) continue;
                 const double v = acc[a][b][q];

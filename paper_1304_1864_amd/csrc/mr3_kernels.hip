@@ -590,7 +590,7 @@ __global__ void __launch_bounds__(256)
 k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slots,
          const Node* __restrict__ nodes, const Block* __restrict__ blocks,
          const double* __restrict__ d64, const double* __restrict__ lld64, double rtol,
-         double widen) {
+         double widen, double* __restrict__ work) {
     constexpr int G = 256 / L;
     const int g = threadIdx.x / L;
     const int q = threadIdx.x % L;
@@ -634,6 +634,7 @@ k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slo
         if (!__any(fix)) break;
     }
     // multisection until the relative width reaches rtol
+    const double lo0 = lo, hi0 = hi;
     bool busy = active;
     for (int it = 0; it < 400; ++it) {
         if (busy) {
@@ -658,9 +659,91 @@ k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slo
         }
     }
     if (active && q == 0) {
-        const double w = widen * fmax(fabs(lo), fabs(hi));
+        // algorithmic work: halvings plain bisection needs for this bracket
+        const double bits = log2(fmax((lo0 - hi0 == 0.0) ? 1.0 : (hi0 - lo0) / fmax(hi - lo, 1e-300), 1.0));
+        atomicAdd(&work[0], bits * (double)n);
+        const double w = widen * (double)n * fmax(fabs(lo), fabs(hi));
         slots[s].lo = lo - w;
         slots[s].hi = hi + w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Verification of binary64-copy intervals in working precision y (Sec. 3.2:
+// results of x-bit eigenvalue computations may be verified or refined in y).
+// Two lanes per slot count the y representation at lo and hi; a bracket that
+// does not hold for the y representation is widened until it does and then
+// refined by bisection in y to relative width rtol.
+// ---------------------------------------------------------------------------
+template <class Y>
+__global__ void __launch_bounds__(64)
+k_verify(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slots,
+         const Node* __restrict__ nodes, const Block* __restrict__ blocks,
+         const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld, double rtol,
+         unsigned long long* __restrict__ repaired) {
+    const int lane = threadIdx.x;
+    const int pair = lane >> 1;
+    const bool side = lane & 1;  // 0: count at lo, 1: count at hi
+    const int64_t idx = (int64_t)blockIdx.x * 32 + pair;
+    const bool active = idx < count;
+    int64_t s = 0, n = 0, j = 0;
+    const Y* D = rep_d;
+    const Y* LL = rep_lld;
+    double lo = 0, hi = 0;
+    if (active) {
+        s = list[idx];
+        const Slot sl = slots[s];
+        const Node nd = nodes[sl.node];
+        n = blocks[nd.block].n;
+        D = rep_d + nd.rep;
+        LL = rep_lld + nd.rep;
+        j = sl.idx;
+        lo = sl.lo;
+        hi = sl.hi;
+    }
+    bool bad = false, fix = active;
+    for (int it = 0; it < 80; ++it) {
+        int c = 0;
+        if (fix) c = negcount_y<Y>(D, LL, n, y_from(side ? hi : lo, Y()));
+        const int co = __shfl_xor(c, 1, 64);
+        const int clo = side ? co : c, chi = side ? c : co;
+        if (fix) {
+            const bool ok = (clo <= j - 1) && (chi >= j);
+            if (!ok) {
+                bad = true;
+                const double w = fmax(hi - lo, fmax(fabs(lo), fabs(hi)) * 1e-14) + 1e-300;
+                if (clo > j - 1) lo -= w;
+                if (chi < j) hi += w;
+            }
+            fix = !ok;
+        }
+        if (!__any(fix)) break;
+    }
+    // refine repaired brackets by bisection in y (two points per step)
+    bool busy = bad;
+    for (int it = 0; it < 200; ++it) {
+        if (busy) {
+            const double w = hi - lo;
+            if (!(w > rtol * fmax(fabs(lo), fabs(hi))) || w <= 1e-300) busy = false;
+        }
+        if (!__any(busy)) break;
+        const double h3 = (hi - lo) / 3.0;
+        const double x = side ? lo + 2.0 * h3 : lo + h3;
+        int c = 0;
+        if (busy) c = negcount_y<Y>(D, LL, n, y_from(x, Y()));
+        const int co = __shfl_xor(c, 1, 64);
+        if (busy) {
+            const int c1 = side ? co : c, c2 = side ? c : co;
+            const double x1 = lo + h3, x2 = lo + 2.0 * h3;
+            if (c1 >= j) hi = x1;
+            else if (c2 >= j) { lo = x1; hi = x2; }
+            else lo = x2;
+        }
+    }
+    if (active && !side && bad) {
+        slots[s].lo = lo;
+        slots[s].hi = hi;
+        atomicAdd(repaired, 1ull);
     }
 }
 
@@ -822,7 +905,8 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
       const Block* __restrict__ blocks, const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld,
       const double* __restrict__ d64, const double* __restrict__ lld64, const Y* __restrict__ P,
       const int* __restrict__ Pe, const Y* __restrict__ Q, const int* __restrict__ Qe, Params prm,
-      double eps_y, RqiResult* __restrict__ res, unsigned long long* __restrict__ counters) {
+      double eps_y, RqiResult* __restrict__ res, unsigned long long* __restrict__ counters,
+      double* __restrict__ work) {
     const int lane = threadIdx.x;
     const int pair = lane >> 1;
     const bool top = (lane & 1) == 0;
@@ -928,6 +1012,8 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
     Y lam_out = lam;
     double nz2 = 1.0;
     double zT = 1, zB = 1;
+    int64_t r_out = r;     // twist of the sweep whose vector is published
+    bool retried = false;  // one twist retry after leaving the interval
     for (int it = 0; it < prm.rqi_max_iter && !fallback; ++it) {
         if (!__any(!done)) break;
         const int64_t steps = done ? 0 : (top ? r + 1 : n - r);
@@ -953,7 +1039,19 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
         const double resid = fabs(g) / sqrt(nrm2);
         const double corr = g / nrm2;
         const Y lnew = add(lam, y_from(corr, Y()));
+        // largest stored entry relative to the twist row, per half.  The
+        // shuffles run on both lanes of the pair (a shuffle whose source lane
+        // is inactive returns 0), then each lane selects.
+        const double rel = h.zmax / fabs(top ? zrT : zrB);
+        const double relo = __shfl_xor(rel, 1, 64);
+        const int64_t ko = __shfl_xor(h.zmaxk, 1, 64);
+        const double mT = top ? rel : relo;
+        const double mB = top ? relo : rel;
+        const int64_t kT = top ? h.zmaxk : ko;
+        const int64_t kB = top ? ko : h.zmaxk;
+        const bool poor_twist = fmax(mT, mB) > 2.0;
         mine = h;
+        r_out = r;
         lam_out = lnew;
         nz2 = nrm2;
         zT = zrT;
@@ -964,17 +1062,20 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
         }
         const double lh = hi_of(lnew);
         if (!(lh >= lo && lh <= hi)) {
+            // the Rayleigh quotient left the eigenvalue's interval: with a poor
+            // twist the vector was poor, so retry at the same shift with the
+            // twist at the largest entry; otherwise fall back to bisection
+            if (poor_twist && !retried) {
+                retried = true;
+                r = (mT >= mB) ? kT : kB;
+                continue;
+            }
             fallback = true;
             break;
         }
         lam = lnew;
         // move the twist to the largest entry if the current one is poor
-        const double relT = h.zmax / fabs(zrT), relB = h.zmax / fabs(zrB);
-        const double mT = top ? relT : __shfl_xor(relT, 1, 64);
-        const double mB = top ? __shfl_xor(relB, 1, 64) : relB;
-        const int64_t kT = top ? h.zmaxk : __shfl_xor(h.zmaxk, 1, 64);
-        const int64_t kB = top ? __shfl_xor(h.zmaxk, 1, 64) : h.zmaxk;
-        if (fmax(mT, mB) > 2.0) r = (mT >= mB) ? kT : kB;
+        if (poor_twist) r = (mT >= mB) ? kT : kB;
     }
     // both lanes of a pair agree on `fallback`; a pair that did not converge
     // in rqi_max_iter iterations also falls back
@@ -983,6 +1084,25 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
         // bisection in y to relative width eps_x sqrt(n) gaptol, then one
         // RQI step (Sec. 2 "Rayleigh quotient iteration"; Sec. 3.2)
         double blo = lo, bhi = hi;
+        const int jt = (int)slots[list[active ? idx : 0]].idx;
+        // make sure [blo, bhi] brackets eigenvalue jt of the y representation
+        bool fixb = fallback;
+        for (int it = 0; it < 80; ++it) {
+            int c = 0;
+            if (fixb) c = negcount_y<Y>(D, LL, n, y_from(top ? blo : bhi, Y()));
+            const int co = __shfl_xor(c, 1, 64);
+            const int clo = top ? c : co, chi = top ? co : c;
+            if (fixb) {
+                const bool ok = (clo <= jt - 1) && (chi >= jt);
+                if (!ok) {
+                    const double w = fmax(bhi - blo, fmax(fabs(blo), fabs(bhi)) * 1e-14) + 1e-300;
+                    if (clo > jt - 1) blo -= w;
+                    if (chi < jt) bhi += w;
+                }
+                fixb = !ok;
+            }
+            if (!__any(fixb)) break;
+        }
         Y ylo = y_from(blo, Y()), yhi = y_from(bhi, Y());
         const double rt = fmax(prm.eps_x * sqn * prm.gaptol, 8.0 * eps_y);
         bool busy = fallback;
@@ -1008,26 +1128,40 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
             }
         }
         lam = mul(add(ylo, yhi), y_from(0.5, Y()));
-        const int64_t steps = fallback ? (top ? r + 1 : n - r) : 0;
-        Half<Y> h = sweep<Y>(top, D, LL, top ? P + brow : Q + brow, top ? Pe + brow : Qe + brow, n,
-                             r, lam, tile, true, steps);
-        const Y spo = shfl_y<Y>(h.sp, lane ^ 1);
-        const double zro = __shfl_xor(h.zr, 1, 64);
-        const double sso = __shfl_xor(h.ss, 1, 64);
-        if (fallback) {
-            const Y s_r = top ? h.sp : spo;
-            const Y p_r = top ? spo : h.sp;
-            const double zrT = top ? h.zr : zro, zrB = top ? zro : h.zr;
-            const double ssT = top ? h.ss : sso, ssB = top ? sso : h.ss;
-            const Y gam = add_acc(add_acc(s_r, p_r), lam);
-            const double nrm2 = 1.0 + (r > 0 ? ssT / (zrT * zrT) : 0.0) +
-                                (r < n - 1 ? ssB / (zrB * zrB) : 0.0);
-            mine = h;
-            lam_out = add(lam, y_from(to_double(gam) / nrm2, Y()));
-            nz2 = nrm2;
-            zT = zrT;
-            zB = zrB;
-            ++iters;
+        // one RQI step at the bisected value; the twist moves to the largest
+        // entry of z when the first choice was poor (at most two retries)
+        bool again = fallback;
+        for (int rep_it = 0; rep_it < 3; ++rep_it) {
+            if (!__any(again)) break;
+            const int64_t steps = again ? (top ? r + 1 : n - r) : 0;
+            Half<Y> h = sweep<Y>(top, D, LL, top ? P + brow : Q + brow, top ? Pe + brow : Qe + brow,
+                                 n, r, lam, tile, true, steps);
+            const Y spo = shfl_y<Y>(h.sp, lane ^ 1);
+            const double zro = __shfl_xor(h.zr, 1, 64);
+            const double sso = __shfl_xor(h.ss, 1, 64);
+            const double zmo = __shfl_xor(h.zmax, 1, 64);
+            const int64_t zko = __shfl_xor(h.zmaxk, 1, 64);
+            if (again) {
+                const Y s_r = top ? h.sp : spo;
+                const Y p_r = top ? spo : h.sp;
+                const double zrT = top ? h.zr : zro, zrB = top ? zro : h.zr;
+                const double ssT = top ? h.ss : sso, ssB = top ? sso : h.ss;
+                const Y gam = add_acc(add_acc(s_r, p_r), lam);
+                const double nrm2 = 1.0 + (r > 0 ? ssT / (zrT * zrT) : 0.0) +
+                                    (r < n - 1 ? ssB / (zrB * zrB) : 0.0);
+                mine = h;
+                r_out = r;
+                lam_out = add(lam, y_from(to_double(gam) / nrm2, Y()));
+                nz2 = nrm2;
+                zT = zrT;
+                zB = zrB;
+                ++iters;
+                const double mT = (top ? h.zmax : zmo) / fabs(zrT);
+                const double mB = (top ? zmo : h.zmax) / fabs(zrB);
+                const int64_t kT = top ? h.zmaxk : zko, kB = top ? zko : h.zmaxk;
+                again = (fmax(mT, mB) > 2.0) && isfinite(nrm2);
+                if (again) r = (mT >= mB) ? kT : kB;
+            }
         }
     }
     // exchange the per-lane storage bookkeeping and publish the result
@@ -1039,8 +1173,8 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
     if (active && top) {
         const double nz = sqrt(nz2);
         // sign: largest entry of the final vector positive
-        const double cT = (r > 0) ? mine.zmax / fabs(zT) : 0.0;
-        const double cB = (r < n - 1) ? zmaxo / fabs(zB) : 0.0;
+        const double cT = (r_out > 0) ? mine.zmax / fabs(zT) : 0.0;
+        const double cB = (r_out < n - 1) ? zmaxo / fabs(zB) : 0.0;
         double sgn = 1.0;
         if (cT > 1.0 && cT >= cB) sgn = ((mine.zmaxv < 0) != (zT < 0)) ? -1.0 : 1.0;
         else if (cB > 1.0) sgn = ((zmaxvo < 0) != (zB < 0)) ? -1.0 : 1.0;
@@ -1051,7 +1185,7 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
         o.fT = sgn / (zT * nz);
         o.fB = sgn / (zB * nz);
         o.rowr = sgn / nz;
-        o.r = r;
+        o.r = r_out;
         o.evT1 = mine.ev1;
         o.evT2 = mine.ev2;
         o.evT2f = mine.ev2f;
@@ -1063,6 +1197,8 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
         if (!isfinite(o.fT) || !isfinite(o.fB) || !isfinite(o.rowr)) o.status = 2;
         res[idx] = o;
         atomicAdd(&counters[0], (unsigned long long)iters);
+        atomicAdd(&work[1], (double)iters * (double)(n + 1));
+        atomicAdd(&work[2], (double)n);
         if (fallback) atomicAdd(&counters[1], 1ull);
         if (o.status == 2) atomicAdd(&counters[2], 1ull);
     }
@@ -1174,7 +1310,8 @@ struct ChildJob {
 __global__ void __launch_bounds__(64)
 k_child_select(ChildJob* __restrict__ jobs, int64_t njobs, const Slot* __restrict__ slots,
                const Node* __restrict__ nodes, const Block* __restrict__ blocks,
-               const double* __restrict__ d64, const double* __restrict__ lld64, Params prm) {
+               const double* __restrict__ d64, const double* __restrict__ lld64, Params prm,
+               double ex_over_ey) {
     const int64_t jb = blockIdx.x;
     if (jb >= njobs) return;
     const int lane = threadIdx.x;
@@ -1210,7 +1347,11 @@ k_child_select(ChildJob* __restrict__ jobs, int64_t njobs, const Slot* __restric
     }
     const int64_t want = left ? sp.idx - 1 : sq.idx;
     valid = valid && (negc == want) && isfinite(gmax);
-    const bool pass = valid && !prm.force_best_candidate && gmax <= prm.k_elg * nd.spdiam;
+    // element growth bound relaxed as the mixed precision analysis allows:
+    // k_elg <= max(k_elg, eps_x / (eps_y sqrt(n))) (Sec. 3.2, "Requirements on
+    // the representations")
+    const double kelg = fmax(prm.k_elg, ex_over_ey / sqrt((double)n));
+    const bool pass = valid && !prm.force_best_candidate && gmax <= kelg * nd.spdiam;
     // choose: per side the smallest passing step, then the side with the
     // smaller growth; if nothing passes, the valid candidate of least growth
     const unsigned long long pm = __ballot(pass);

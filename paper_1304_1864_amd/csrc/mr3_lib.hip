@@ -10,6 +10,8 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -159,6 +161,62 @@ namespace mr3 {
 
 static thread_local hipError_t last_hip_error = hipSuccess;
 
+// MR3_DEBUG=1 in the environment prints per-level counts and host-side phase
+// times to stderr (development aid; off by default)
+static bool debug_on() {
+    static const bool on = [] {
+        const char* v = std::getenv("MR3_DEBUG");
+        return v && v[0] && v[0] != '0';
+    }();
+    return on;
+}
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Per-stage device time: with params.profile set, every launch is bracketed by
+// two HIP events recorded on the launch stream; the elapsed times are summed
+// per stage once the solve has synchronised.
+struct Prof {
+    bool on = false;
+    struct Ev {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Ev> evs;
+    void begin(int stage, hipStream_t st) {
+        if (!on) return;
+        Ev e{stage, nullptr, nullptr};
+        (void)hipEventCreate(&e.a);
+        (void)hipEventCreate(&e.b);
+        (void)hipEventRecord(e.a, st);
+        evs.push_back(e);
+    }
+    void end(hipStream_t st) {
+        if (!on || evs.empty()) return;
+        (void)hipEventRecord(evs.back().b, st);
+    }
+    void collect(mr3_stats& s) {
+        for (auto& e : evs) {
+            float ms = 0.f;
+            if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+                s.stage_ms[e.stage] += ms;
+                s.stage_launches[e.stage] += 1;
+            }
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+        evs.clear();
+    }
+    ~Prof() {
+        for (auto& e : evs) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+    }
+};
+
 static void defaults(mr3_params* p, int precision) {
     std::memset(p, 0, sizeof(*p));
     p->gaptol = (precision == 32) ? 1e-5 : 1e-10;
@@ -189,6 +247,8 @@ static Params effective(const mr3_handle_s* h, int precision) {
     p.force_rqi_fallback = h->have_user ? u.force_rqi_fallback : 0;
     p.force_best_candidate = h->have_user ? u.force_best_candidate : 0;
     p.seed = (h->have_user && u.seed) ? u.seed : d.seed;
+    p.profile = h->have_user ? u.profile : 0;
+    p.debug_slot = std::getenv("MR3_DEBUG_SLOT") ? std::atoll(std::getenv("MR3_DEBUG_SLOT")) : -1;
     return p;
 }
 
@@ -210,20 +270,20 @@ static hipError_t download(std::vector<T>& v, const void* src, size_t count, hip
 
 static void launch_bisect(int L, const int64_t* list, int64_t count, Slot* slots, const Node* nodes,
                           const Block* blocks, const double* d64, const double* l64, double rtol,
-                          double widen, hipStream_t st) {
+                          double widen, double* work, hipStream_t st) {
     if (count <= 0) return;
     const int G = 256 / L;
     const dim3 grid((unsigned)((count + G - 1) / G));
 #define MR3_BIS(LL)                                                                      \
     case LL:                                                                             \
         hipLaunchKernelGGL(k_bisect<LL>, grid, dim3(256), 0, st, list, count, slots, nodes, \
-                           blocks, d64, l64, rtol, widen);                               \
+                           blocks, d64, l64, rtol, widen, work);                         \
         break;
     switch (L) {
         MR3_BIS(1) MR3_BIS(2) MR3_BIS(4) MR3_BIS(8) MR3_BIS(16) MR3_BIS(32) MR3_BIS(64)
         default:
             hipLaunchKernelGGL(k_bisect<1>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
-                               list, count, slots, nodes, blocks, d64, l64, rtol, widen);
+                               list, count, slots, nodes, blocks, d64, l64, rtol, widen, work);
     }
 #undef MR3_BIS
 }
@@ -248,6 +308,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                       hipStream_t st) {
     const int precision = sizeof(X) == 4 ? 32 : 64;
     const Params prm = effective(h, precision);
+    const double t_start = now_ms();
     const bool is_dd = sizeof(Y) == 16;
     Buf* B = h->buf;
     mr3_stats stats{};
@@ -355,10 +416,16 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(B[B_Q].ensure(sizeof(Y) * R));
     HIPCHK(B[B_PE].ensure(sizeof(int) * R));
     HIPCHK(B[B_QE].ensure(sizeof(int) * R));
-    HIPCHK(B[B_COUNTERS].ensure(sizeof(unsigned long long) * 8 + sizeof(int) * 8));
-    HIPCHK(hipMemsetAsync(B[B_COUNTERS].p, 0, sizeof(unsigned long long) * 8 + sizeof(int) * 8, st));
+    // counters: 8 x u64 (RQI iterations, fallbacks, failures), 8 x double
+    // (algorithmic row steps), 8 x int (status)
+    const size_t cnt_bytes = sizeof(unsigned long long) * 8 + sizeof(double) * 8 + sizeof(int) * 8;
+    HIPCHK(B[B_COUNTERS].ensure(cnt_bytes));
+    HIPCHK(hipMemsetAsync(B[B_COUNTERS].p, 0, cnt_bytes, st));
     unsigned long long* counters = B[B_COUNTERS].as<unsigned long long>();
-    int* status = reinterpret_cast<int*>(counters + 8);
+    double* work = reinterpret_cast<double*>(counters + 8);
+    int* status = reinterpret_cast<int*>(work + 8);
+    Prof prof;
+    prof.on = prm.profile != 0;
     // outputs
     std::vector<int64_t> w_off(w_off_h, w_off_h + count), z_off(count, 0), ldz(count, 1);
     if (Z) {
@@ -380,26 +447,29 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     Slot* dslots = B[B_SLOTS].as<Slot>();
     Node* dnodes = B[B_NODES].as<Node>();
     // ---- a2: root representations ----
+    prof.begin(MR3_STAGE_PREP, st);
     hipLaunchKernelGGL(k_root<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_TD].as<double>(),
                        B[B_TE].as<double>(), prm, B[B_REPD].as<Y>(), B[B_REPL].as<Y>(),
                        B[B_REPE].as<Y>(), B[B_D64].as<double>(), B[B_L64].as<double>(), dnodes,
                        dslots, status);
     hipLaunchKernelGGL(k_pq<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_REPE].as<Y>(),
                        B[B_P].as<Y>(), B[B_PE].as<int>(), B[B_Q].as<Y>(), B[B_QE].as<int>());
+    prof.end(st);
     HIPCHK(hipGetLastError());
     // ---- a3: bisection of every slot on its root ----
     std::vector<int64_t> all_slots((size_t)K);
     std::iota(all_slots.begin(), all_slots.end(), 0);
     HIPCHK(upload(B[B_LIST], all_slots, st));
-    const double widen0 = (is_dd ? 10.0 : 4.0) * 1.1102230246251565e-16;  // per unit of n
-    // bisection widening is relative: widen * n_block; blocks differ in n, so
-    // use the largest block (a conservative widening)
-    int64_t nmax = 0;
-    for (auto& b : blocks) nmax = std::max(nmax, b.n);
-    const double widen_root = widen0 * (double)nmax;
+    // intervals from the binary64 copy are widened by k n eps_d |lambda| before
+    // classification: k = 10 on the double-double path (relative robustness
+    // constant of the copy, Sec. 3.2 "Arithmetic used to approximate
+    // eigenvalues"), 4 when the copy is the representation itself
+    const double widen_root = (is_dd ? 10.0 : 4.0) * 1.1102230246251565e-16;  // x n_block
     int L = pick_lanes(K, prm.lanes_per_eig);
+    prof.begin(MR3_STAGE_BISECT, st);
     launch_bisect(L, B[B_LIST].as<int64_t>(), K, dslots, dnodes, dblocks, B[B_D64].as<double>(),
-                  B[B_L64].as<double>(), prm.bisect_rel, widen_root, st);
+                  B[B_L64].as<double>(), prm.bisect_rel, widen_root, work, st);
+    prof.end(st);
     HIPCHK(hipGetLastError());
     // ---- output columns of split problems: order by eigenvalue ----
     bool any_multi = false;
@@ -440,6 +510,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         stats.d_max = std::max(stats.d_max, depth);
         HIPCHK(upload(B[B_LIST], level_nodes, st));
         const int force_single = depth >= prm.max_depth;
+        prof.begin(MR3_STAGE_CLASSIFY, st);
         hipLaunchKernelGGL(k_classify, dim3((unsigned)level_nodes.size()), dim3(256), 0, st,
                            B[B_LIST].as<int64_t>(), (int64_t)level_nodes.size(), dnodes, dslots,
                            B[B_FLAGS].as<int>(), prm.gaptol, force_single);
@@ -459,9 +530,13 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         tmp_bytes = B[B_CUBTMP].cap;
         HIPCHK(hipcub::DeviceSelect::If(B[B_CUBTMP].p, tmp_bytes, iter, B[B_LIST2].as<int64_t>(),
                                         dcnt + 1, K, sel_c, st));
+        prof.end(st);
         std::vector<int64_t> cnts;
         HIPCHK(download(cnts, dcnt, 2, st));
         const int64_t S = cnts[0], C = cnts[1];
+        if (debug_on())
+            std::fprintf(stderr, "[mr3] depth %d: nodes %zu singletons %lld clusters %lld  t=%.2f ms\n",
+                         depth, level_nodes.size(), (long long)S, (long long)C, now_ms() - t_start);
         // ---- a6 + a7: singletons ----
         if (S > 0) {
             const int64_t nchunk = (S + 31) / 32;
@@ -482,18 +557,46 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             HIPCHK(download(tot, B[B_TILEOFF].as<int64_t>() + nchunk, 1, st));
             HIPCHK(B[B_TILES].ensure(sizeof(double) * std::max<int64_t>(tot[0], 1)));
             HIPCHK(B[B_RES].ensure(sizeof(RqiResult) * S));
+            prof.begin(MR3_STAGE_RQI, st);
             hipLaunchKernelGGL(k_rqi<Y>, dim3((unsigned)nchunk), dim3(64), 0, st,
                                B[B_LIST].as<int64_t>(), S, B[B_TILEOFF].as<int64_t>(),
                                B[B_TILES].as<double>(), dslots, dnodes, dblocks, B[B_REPD].as<Y>(),
                                B[B_REPL].as<Y>(), B[B_D64].as<double>(), B[B_L64].as<double>(),
                                B[B_P].as<Y>(), B[B_PE].as<int>(), B[B_Q].as<Y>(), B[B_QE].as<int>(),
-                               prm, (double)YEps<Y>::v, B[B_RES].as<RqiResult>(), counters);
+                               prm, (double)YEps<Y>::v, B[B_RES].as<RqiResult>(), counters, work);
+            prof.end(st);
+            prof.begin(MR3_STAGE_ZOUT, st);
             hipLaunchKernelGGL((k_zout<X, Y>), dim3((unsigned)nchunk), dim3(256), 0, st,
                                B[B_LIST].as<int64_t>(), S, B[B_TILEOFF].as<int64_t>(),
                                B[B_TILES].as<double>(), dslots, dnodes, dblocks,
                                B[B_PINFO].as<ProbInfo>(), B[B_RES].as<RqiResult>(), W,
                                B[B_WOFF].as<int64_t>(), Z, B[B_ZOFF].as<int64_t>(),
                                B[B_LDZ].as<int64_t>());
+            prof.end(st);
+            if (debug_on()) {
+                std::vector<unsigned long long> c;
+                HIPCHK(download(c, counters, 3, st));
+                std::fprintf(stderr, "[mr3]   after RQI: iters %llu fallbacks %llu failures %llu t=%.2f ms\n",
+                             c[0], c[1], c[2], now_ms() - t_start);
+                if (std::getenv("MR3_DEBUG")[0] == '2') {
+                    std::vector<RqiResult> rr;
+                    std::vector<int64_t> ls;
+                    std::vector<Slot> sl;
+                    HIPCHK(download(rr, B[B_RES].p, (size_t)S, st));
+                    HIPCHK(download(ls, B[B_LIST].p, (size_t)S, st));
+                    HIPCHK(download(sl, dslots, (size_t)K, st));
+                    for (int64_t i = 0; i < S; ++i)
+                        if (rr[i].status != 0 || rr[i].iters >= 6)
+                            std::fprintf(stderr,
+                                         "[mr3]   slot %lld idx %lld st %d it %d r %lld lam %.17g%+.3g "
+                                         "[%.17g, %.17g] gaps %.3g %.3g fT %.3g fB %.3g rowr %.3g ev %lld %lld / %lld %lld\n",
+                                         (long long)ls[i], (long long)sl[ls[i]].idx, rr[i].status, rr[i].iters,
+                                         (long long)rr[i].r, rr[i].lam_hi, rr[i].lam_lo, sl[ls[i]].lo, sl[ls[i]].hi,
+                                         sl[ls[i]].lgap, sl[ls[i]].rgap, rr[i].fT, rr[i].fB, rr[i].rowr,
+                                         (long long)rr[i].evT1, (long long)rr[i].evT2, (long long)rr[i].evB1,
+                                         (long long)rr[i].evB2);
+                }
+            }
             HIPCHK(hipGetLastError());
         }
         level_nodes.clear();
@@ -541,15 +644,17 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         HIPCHK(B[B_TMPC].ensure(sizeof(Y) * tmp_rows));
         HIPCHK(B[B_TMPE].ensure(sizeof(int) * tmp_rows));
         HIPCHK(upload(B[B_JOBS], jobs, st));
+        prof.begin(MR3_STAGE_CHILD, st);
         hipLaunchKernelGGL(k_child_select, dim3((unsigned)C), dim3(64), 0, st,
                            B[B_JOBS].as<ChildJob>(), C, dslots, dnodes, dblocks,
-                           B[B_D64].as<double>(), B[B_L64].as<double>(), prm);
+                           B[B_D64].as<double>(), B[B_L64].as<double>(), prm,
+                           prm.eps_x / (double)YEps<Y>::v);
         hipLaunchKernelGGL(k_child_rep<Y>, dim3((unsigned)C), dim3(64), 0, st,
                            B[B_JOBS].as<ChildJob>(), C, dslots, dnodes, dblocks, B[B_REPD].as<Y>(),
                            B[B_REPL].as<Y>(), B[B_REPE].as<Y>(), B[B_D64].as<double>(),
                            B[B_L64].as<double>(), B[B_TMPC].as<Y>(), B[B_TMPE].as<int>(),
-                           is_dd ? 10.0 * 1.1102230246251565e-16 / prm.eps_x : 4.0 * 1.1102230246251565e-16 / prm.eps_x,
-                           prm.eps_x);
+                           widen_root / prm.eps_x, prm.eps_x);
+        prof.end(st);
         HIPCHK(hipGetLastError());
         {
             std::vector<ChildJob> done_jobs;
@@ -574,8 +679,17 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         HIPCHK(download(c2, dcnt + 2, 1, st));
         const int64_t KC = c2[0];
         L = pick_lanes(KC, prm.lanes_per_eig);
+        prof.begin(MR3_STAGE_BISECT, st);
         launch_bisect(L, B[B_LIST].as<int64_t>(), KC, dslots, dnodes, dblocks, B[B_D64].as<double>(),
-                      B[B_L64].as<double>(), prm.bisect_rel, widen_root, st);
+                      B[B_L64].as<double>(), prm.bisect_rel, widen_root, work, st);
+        if (is_dd && KC > 0) {
+            // a child may have element growth, so its binary64 copy need not
+            // be relatively robust: check every bracket with counts in y
+            hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)((KC + 31) / 32)), dim3(64), 0, st,
+                               B[B_LIST].as<int64_t>(), KC, dslots, dnodes, dblocks,
+                               B[B_REPD].as<Y>(), B[B_REPL].as<Y>(), prm.bisect_rel, counters + 3);
+        }
+        prof.end(st);
         HIPCHK(hipGetLastError());
         for (int64_t c = 0; c < C; ++c) level_nodes.push_back(jobs[c].child);
     }
@@ -586,8 +700,18 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(download(sts, status, 1, st));
     stats.n_rqi_iters = (int64_t)ctr[0];
     stats.n_fallbacks = (int64_t)ctr[1];
+    std::vector<double> wk;
+    HIPCHK(download(wk, work, 4, st));
+    stats.bisect_row_steps = wk[0];
+    stats.rqi_row_steps = wk[1];
+    stats.twist_row_steps = wk[2];
+    prof.collect(stats);
     h->stats = stats;
     if (sts[0] != 0 || ctr[2] != 0) return MR3_ERR_NUMERIC;
+    if (debug_on())
+        std::fprintf(stderr, "[mr3] levels done t=%.2f ms (rqi iters %llu fallbacks %llu repaired brackets %llu)\n",
+                     now_ms() - t_start, (unsigned long long)ctr[0], (unsigned long long)ctr[1],
+                     (unsigned long long)ctr[3]);
     std::vector<int64_t> mv(m_p.begin(), m_p.end());
     HIPCHK(upload(B[B_M], mv, st));
     HIPCHK(B[B_BAD].ensure(sizeof(int) * count));
@@ -598,6 +722,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(download(bad, B[B_BAD].p, (size_t)count, st));
     for (int64_t p = 0; p < count; ++p) {
         if (!bad[p]) continue;
+        if (debug_on()) std::fprintf(stderr, "[mr3] problem %lld: eigenvalues reordered on the host\n", (long long)p);
         // rare: eigenvalues equal to working accuracy came out in the wrong
         // order; sort the pairs on the host
         const int64_t mp = m_p[p], np = probs[p].n;
@@ -610,14 +735,29 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         for (int64_t i = 0; i < mp; ++i) w2[i] = w[perm[i]];
         HIPCHK(hipMemcpy(W + w_off[p], w2.data(), sizeof(X) * mp, hipMemcpyHostToDevice));
         if (Z) {
-            std::vector<X> zc((size_t)(np * mp));
-            HIPCHK(hipMemcpy2D(zc.data(), sizeof(X) * np, Z + z_off[p], sizeof(X) * ldz[p],
-                               sizeof(X) * np, mp, hipMemcpyDeviceToHost));
-            std::vector<X> z2((size_t)(np * mp));
-            for (int64_t i = 0; i < mp; ++i)
-                std::memcpy(&z2[i * np], &zc[perm[i] * np], sizeof(X) * np);
-            HIPCHK(hipMemcpy2D(Z + z_off[p], sizeof(X) * ldz[p], z2.data(), sizeof(X) * np,
-                               sizeof(X) * np, mp, hipMemcpyHostToDevice));
+            // apply the permutation to the columns on the device, cycle by
+            // cycle through one scratch column (only misplaced columns move)
+            HIPCHK(B[B_CHECK].ensure(sizeof(X) * (size_t)std::max<int64_t>(np, 1)));
+            X* tmp = B[B_CHECK].as<X>();
+            std::vector<char> seen((size_t)mp, 0);
+            auto col = [&](int64_t c) { return Z + z_off[p] + c * ldz[p]; };
+            for (int64_t s0 = 0; s0 < mp; ++s0) {
+                if (seen[s0] || perm[s0] == s0) { seen[s0] = 1; continue; }
+                // new column i takes old column perm[i]
+                HIPCHK(hipMemcpyAsync(tmp, col(s0), sizeof(X) * np, hipMemcpyDeviceToDevice, st));
+                int64_t i = s0;
+                while (true) {
+                    seen[i] = 1;
+                    const int64_t src = perm[i];
+                    if (src == s0) {
+                        HIPCHK(hipMemcpyAsync(col(i), tmp, sizeof(X) * np, hipMemcpyDeviceToDevice, st));
+                        break;
+                    }
+                    HIPCHK(hipMemcpyAsync(col(i), col(src), sizeof(X) * np, hipMemcpyDeviceToDevice, st));
+                    i = src;
+                }
+            }
+            HIPCHK(hipStreamSynchronize(st));
         }
     }
     return MR3_OK;

@@ -112,6 +112,8 @@ struct Params {
     int lanes_per_eig;
     int force_rqi_fallback;
     int force_best_candidate;
+    int profile;
+    long long debug_slot;  // development trace (MR3_DEBUG_SLOT), -1 = off
     unsigned long long seed;
 };
 

@@ -145,3 +145,79 @@ def test_edge_sizes(mr3):
                 assert Wg.numel() == 0 and Zg.shape[1] == 0
                 continue
             run_case(mr3, d, e)
+
+
+def test_check_kernel_matches_numpy(mr3):
+    """The FP64 MFMA Gram-matrix check agrees with numpy on a small case."""
+    d, e = W.uniform(700, 12, np.float64)
+    Wg, Zg = mr3.solve(_dev(d), _dev(e))
+    (off, diag), res = mr3.check(_dev(d), _dev(e), Wg, Zg)
+    Z = Zg.cpu().numpy()
+    G = Z.T @ Z
+    off_np = np.max(np.abs(G - np.diag(np.diag(G))))
+    diag_np = np.max(np.abs(np.diag(G) - 1))
+    res_np = M.residual(d, e, Wg.cpu().numpy(), Z)
+    n = d.size
+    assert abs(off - off_np) <= 2 * n * 2.0 ** -53
+    assert abs(diag - diag_np) <= 2 * n * 2.0 ** -53
+    assert abs(res - res_np) <= 1e-3 * res_np + 1e-17
+
+
+def test_prescribed_child_clusters_regression(mr3):
+    """n=5000 prescribed spectrum: many clusters whose children needed a
+    twist move; both lanes of a pair must agree on the twist index."""
+    d, e, _ = W.prescribed_spectrum(5000, 0)
+    h = mr3.Handle(0)
+    run_case(mr3, d, e, check_angles=False, handle=h)
+    st = h.stats()
+    assert st["n_clusters"] > 0 and st["d_max"] >= 1
+
+
+@pytest.mark.slow
+def test_glued_wilkinson_4096(mr3):
+    d, e = W.glued_wilkinson(4096)
+    n = d.size
+    h = mr3.Handle(0)
+    Wg, Zg = mr3.solve(_dev(d), _dev(e), handle=h)
+    w = Wg.cpu().numpy()
+    hi, lo = oracle.eigvals(d, e)
+    tn = M.tnorm(d, e)
+    eps = 2.0 ** -53
+    assert np.max(np.abs(w - (hi + lo))) <= 4 * n * eps * tn
+    (off, diag), res = mr3.check(_dev(d), _dev(e), Wg, Zg, handle=h)
+    assert max(off, diag) <= 10 * n * eps and res <= 10 * n * eps
+    st = h.stats()
+    print("wilkinson 4096", st["n_clusters"], st["largest_cluster"], st["d_max"], off, diag, res, flush=True)
+
+
+@pytest.mark.slow
+def test_prescribed_20000_sampled(mr3):
+    """Full size of the benchmark workload: all eigenpairs and the subset
+    il=1..2000; eigenvalues at sampled indices against the oracle, residual
+    and orthogonality of everything on the device, sampled eigenvectors
+    against oracle inverse iteration."""
+    n = 20000
+    d, e, _ = W.prescribed_spectrum(n, 0)
+    tn = M.tnorm(d, e)
+    eps = 2.0 ** -53
+    h = mr3.Handle(0)
+    dg, eg = _dev(d), _dev(e)
+    for rng, il, iu in (("all", 1, n), ("index", 1, 2000)):
+        Wg, Zg = mr3.solve(dg, eg, range=rng, il=il, iu=iu, handle=h)
+        w = Wg.cpu().numpy()
+        m = iu - il + 1
+        assert w.size == m and np.all(np.diff(w) >= 0)
+        idx = np.unique(np.linspace(0, m - 1, 48).astype(int))
+        for i in idx:
+            hi, lo = oracle.eigvals(d, e, il + i, il + i)
+            assert abs(w[i] - (hi[0] + lo[0])) <= 4 * n * eps * tn, (rng, i)
+        (off, diag), res = mr3.check(dg, eg, Wg, Zg, handle=h)
+        print(rng, "O", off, diag, "R", res, "gate", 10 * n * eps, h.stats()["n_fallbacks"], flush=True)
+        assert max(off, diag) <= 10 * n * eps and res <= 10 * n * eps
+        # eigenvectors of well separated sampled eigenvalues vs the oracle
+        Z = Zg[:, torch.as_tensor(idx[:8], device=Zg.device)].cpu().numpy()
+        for k, i in enumerate(idx[:8]):
+            hi, lo = oracle.eigvals(d, e, il + i, il + i)
+            zr = oracle.eigvecs(d, e, hi, lo)[:, 0]
+            c = abs(float(zr @ Z[:, k]))
+            assert 1 - c <= 1e-8, (rng, i, c)
