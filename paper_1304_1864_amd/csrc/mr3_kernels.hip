@@ -92,29 +92,64 @@ __device__ int sturm_T(const double* __restrict__ Td, const double* __restrict__
     return cnt;
 }
 
-// Sturm count of the binary64 representation (d, lld) at x (division free)
+// Sturm count of the binary64 representation (d, lld) at x (division free).
+// Rows are read in blocks of 8 with the next block's loads issued before the
+// current block is processed (register double buffering), so the sequential
+// recurrence does not wait a full memory latency per row.
 __device__ __forceinline__ int negcount64(const double* __restrict__ D,
                                           const double* __restrict__ LL, int64_t n, double x) {
+    constexpr int U = 8;
     double a = -x, b = 1.0;
     int neg = 0;
-    int64_t i = 0;
-    for (; i + 4 <= n; i += 4) {
+    if (n <= 0) return 0;
+    // rows past the end are read from the guard rows of the array
+    double dn[U], ln[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double c = __fma_rn(D[i + u], b, a);
-            neg += sign_differs(c, b);
-            a = __fma_rn(-x, c, LL[i + u] * a);
-            b = c;
-        }
-        const int em = max(dexp(a), dexp(b));
-        a = __builtin_ldexp(a, -em);
-        b = __builtin_ldexp(b, -em);
+    for (int u = 0; u < U; ++u) {
+        dn[u] = D[u];
+        ln[u] = LL[u];
     }
-    for (; i < n; ++i) {
-        const double c = __fma_rn(D[i], b, a);
-        neg += sign_differs(c, b);
-        a = __fma_rn(-x, c, LL[i] * a);
-        b = c;
+    for (int64_t i = 0; i < n; i += U) {
+        double dc[U], lc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dc[u] = dn[u];
+            lc[u] = ln[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dn[u] = D[i + U + u];
+            ln[u] = LL[i + U + u];
+        }
+        if (i + U <= n) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double c = __fma_rn(dc[u], b, a);
+                neg += sign_differs(c, b);
+                a = __fma_rn(-x, c, lc[u] * a);
+                b = c;
+                if ((u & 3) == 3) {
+                    const int em = max(dexp(a), dexp(b));
+                    a = __builtin_ldexp(a, -em);
+                    b = __builtin_ldexp(b, -em);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (i + u < n) {
+                    const double c = __fma_rn(dc[u], b, a);
+                    neg += sign_differs(c, b);
+                    a = __fma_rn(-x, c, lc[u] * a);
+                    b = c;
+                    if ((u & 3) == 3) {
+                        const int em = max(dexp(a), dexp(b));
+                        a = __builtin_ldexp(a, -em);
+                        b = __builtin_ldexp(b, -em);
+                    }
+                }
+            }
+        }
     }
     return neg;
 }
@@ -815,10 +850,100 @@ struct Half {  // per-lane sweep output
 // 2^400 by rebasing the storage exponent; the output kernel multiplies values
 // stored before the last rebase by ev2f and zeroes those stored before the
 // one-but-last (they are below 2^-400 of the final maximum).
+// One phase of the binary64 twist search.  Step s handles row k = s (top
+// lane, stationary transform) or k = n-1-s (bottom lane, progressive
+// transform).  Without `combine` the quotient s_k = a/b (resp. p_k) is stored
+// in the tile column; with it, the value the other lane stored for row k is
+// combined into |gamma_k| = |s_k + p_k + tau| and the minimum is tracked.
+// Row data are double buffered like in negcount64.
+__device__ __forceinline__ void prepass_phase(bool top, const double* __restrict__ D,
+                                              const double* __restrict__ LL, int64_t n, double tau,
+                                              int64_t s0, int64_t cnt, double& a, double& b,
+                                              bool combine, double* __restrict__ col, double& gmin,
+                                              int64_t& rmin) {
+    constexpr int U = 8;
+    if (cnt <= 0) return;
+    double nd[U], nl[U], nt[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t sidx = s0 + u;
+        const int64_t k = top ? sidx : n - 1 - sidx;
+        const int64_t ka = top ? k : k - 1;
+        nd[u] = D[ka];
+        nl[u] = LL[ka];
+        nt[u] = combine ? col[k * 32] : 0.0;
+    }
+    for (int64_t i = 0; i < cnt; i += U) {
+        double cd[U], cl[U], ct[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cd[u] = nd[u];
+            cl[u] = nl[u];
+            ct[u] = nt[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t sidx = s0 + i + U + u;
+            const int64_t k = top ? sidx : n - 1 - sidx;
+            const int64_t ka = top ? k : k - 1;
+            nd[u] = D[ka];
+            nl[u] = LL[ka];
+            nt[u] = combine ? col[k * 32] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i + u >= cnt) continue;
+            const int64_t sidx = s0 + i + u;
+            const int64_t k = top ? sidx : n - 1 - sidx;
+            const double q = a / b;
+            if (combine) {
+                const double g = fabs(q + ct[u] + tau);
+                if (g < gmin || (g == gmin && k < rmin)) { gmin = g; rmin = k; }
+            } else {
+                col[k * 32] = q;
+            }
+            const double c = __fma_rn(top ? cd[u] : cl[u], b, a);
+            a = __fma_rn(-tau, c, (top ? cl[u] : cd[u]) * a);
+            b = c;
+            if (((i + u) & 3) == 3) {
+                const int em = max(dexp(a), dexp(b));
+                a = __builtin_ldexp(a, -em);
+                b = __builtin_ldexp(b, -em);
+            }
+        }
+    }
+}
+
+template <class Y>
+struct Row {
+    Y pq;   // P_k or Q_k mantissa
+    Y d;    // d of the row the recurrence advances over
+    Y ll;   // lld of that row
+    int pqe;
+};
+
+// data of sweep step `it`: the z row k and the row the recurrence advances
+// over (k for the top lane, k-1 for the bottom lane); prefetches past either
+// end of the representation read the arrays' guard rows
+template <class Y>
+__device__ __forceinline__ Row<Y> load_row(bool top, const Y* __restrict__ D,
+                                           const Y* __restrict__ LL, const Y* __restrict__ PQ,
+                                           const int* __restrict__ PQe, int64_t n, int64_t it) {
+    Row<Y> w;
+    const int64_t kz = top ? it : n - 1 - it;
+    const int64_t ka = top ? it : n - 2 - it;
+    w.pq = PQ[kz];
+    w.pqe = PQe[kz];
+    w.d = D[ka];
+    w.ll = LL[ka];
+    return w;
+}
+
 template <class Y>
 __device__ Half<Y> sweep(bool top, const Y* __restrict__ D, const Y* __restrict__ LL,
                          const Y* __restrict__ PQ, const int* __restrict__ PQe, int64_t n,
                          int64_t r, Y tau, double* __restrict__ col, bool store, int64_t steps) {
+    constexpr int U = 4;
     Half<Y> h;
     h.ss = 0.0;
     h.zmax = 0.0;
@@ -838,51 +963,61 @@ __device__ Half<Y> sweep(bool top, const Y* __restrict__ D, const Y* __restrict_
     }
     int eb = 0;    // binary exponent carried by b
     int eref = 0;  // storage frame exponent
-    for (int64_t it = 0; it < steps; ++it) {
-        const int64_t k = top ? it : n - 1 - it;
-        const bool last = (k == r);
-        // z_k = PQ_k * b * 2^(PQe_k + eb - eref)
-        const Y pb = mul(PQ[k], b);
-        int ex = PQe[k] + eb - eref;
-        const int ez = y_exp(pb) + ex;
-        if (ez > 400) {
-            const int dlt = ez;
-            eref += dlt;
-            ex -= dlt;
-            h.ss = __builtin_ldexp(h.ss, -2 * dlt);
-            h.zmax = __builtin_ldexp(h.zmax, -dlt);
-            h.zmaxv = __builtin_ldexp(h.zmaxv, -dlt);
-            h.ev1 = h.ev2;
-            h.ev2 = k;
-            h.ev2f = __builtin_ldexp(1.0, -dlt);
-        }
-        const double zv = __builtin_ldexp(to_double(pb), ex);
-        if (last) {
-            h.zr = zv;
-            break;
-        }
-        if (store) col[k * 32] = zv;
-        h.ss = __fma_rn(zv, zv, h.ss);
-        if (fabs(zv) > h.zmax) {
-            h.zmax = fabs(zv);
-            h.zmaxv = zv;
-            h.zmaxk = k;
-        }
-        // advance the recurrence past row k
-        Y c;
-        if (top) {
-            c = mul_add(D[k], b, a);
-            a = sub(mul(LL[k], a), mul(tau, c));
-        } else {
-            c = mul_add(LL[k - 1], b, a);
-            a = sub(mul(D[k - 1], a), mul(tau, c));
-        }
-        b = c;
-        if ((it & 3) == 3) {
-            const int em = max(y_exp(a), y_exp(b));
-            a = y_ldexp(a, -em);
-            b = y_ldexp(b, -em);
-            eb += em;
+    Row<Y> nx[U];
+    if (steps > 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) nx[u] = load_row<Y>(top, D, LL, PQ, PQe, n, u);
+    }
+    bool fin = steps <= 0;
+    for (int64_t it0 = 0; !fin; it0 += U) {
+        Row<Y> cu[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cu[u] = nx[u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) nx[u] = load_row<Y>(top, D, LL, PQ, PQe, n, it0 + U + u);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (fin) continue;
+            const int64_t it = it0 + u;
+            const int64_t k = top ? it : n - 1 - it;
+            // z_k = PQ_k * b * 2^(PQe_k + eb - eref)
+            const Y pb = mul(cu[u].pq, b);
+            int ex = cu[u].pqe + eb - eref;
+            const int ez = y_exp(pb) + ex;
+            if (ez > 400) {
+                const int dlt = ez;
+                eref += dlt;
+                ex -= dlt;
+                h.ss = __builtin_ldexp(h.ss, -2 * dlt);
+                h.zmax = __builtin_ldexp(h.zmax, -dlt);
+                h.zmaxv = __builtin_ldexp(h.zmaxv, -dlt);
+                h.ev1 = h.ev2;
+                h.ev2 = k;
+                h.ev2f = __builtin_ldexp(1.0, -dlt);
+            }
+            const double zv = __builtin_ldexp(to_double(pb), ex);
+            if (k == r || it + 1 >= steps) {
+                h.zr = zv;
+                fin = true;
+                continue;
+            }
+            if (store) col[k * 32] = zv;
+            h.ss = __fma_rn(zv, zv, h.ss);
+            if (fabs(zv) > h.zmax) {
+                h.zmax = fabs(zv);
+                h.zmaxv = zv;
+                h.zmaxk = k;
+            }
+            // advance the recurrence past row k
+            const Y c = mul_add(top ? cu[u].d : cu[u].ll, b, a);
+            a = sub(mul(top ? cu[u].ll : cu[u].d, a), mul(tau, c));
+            b = c;
+            if ((it & 3) == 3) {
+                const int em = max(y_exp(a), y_exp(b));
+                a = y_ldexp(a, -em);
+                b = y_ldexp(b, -em);
+                eb += em;
+            }
         }
     }
     h.sp = div(a, b);  // s_r = a_r / b_r  or  p_r = alpha_r / beta_r
@@ -941,49 +1076,11 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
     if (top) { a = -tau0; b = 1.0; } else if (n > 0) { a = D64[n - 1] - tau0; b = 1.0; }
     const int64_t len1 = active ? (top ? hh : n - hh) : 0;
     const int64_t len2 = active ? (top ? n - hh : hh) : 0;
-    for (int64_t it = 0; it < len1; ++it) {
-        const int64_t k = top ? it : n - 1 - it;
-        tile[k * 32] = a / b;
-        double c;
-        if (top) {
-            c = __fma_rn(D64[k], b, a);
-            a = __fma_rn(-tau0, c, LL64[k] * a);
-        } else {
-            if (k == 0) break;
-            c = __fma_rn(LL64[k - 1], b, a);
-            a = __fma_rn(-tau0, c, D64[k - 1] * a);
-        }
-        b = c;
-        if ((it & 3) == 3) {
-            const int em = max(dexp(a), dexp(b));
-            a = __builtin_ldexp(a, -em);
-            b = __builtin_ldexp(b, -em);
-        }
-    }
-    __syncthreads();
     double gmin = INFINITY;
     int64_t rmin = n / 2;
-    for (int64_t it = 0; it < len2; ++it) {
-        const int64_t k = top ? hh + it : hh - 1 - it;
-        const double g = fabs(a / b + tile[k * 32] + tau0);
-        if (g < gmin || (g == gmin && k < rmin)) { gmin = g; rmin = k; }
-        double c;
-        if (top) {
-            if (k == n - 1) break;
-            c = __fma_rn(D64[k], b, a);
-            a = __fma_rn(-tau0, c, LL64[k] * a);
-        } else {
-            if (k == 0) break;
-            c = __fma_rn(LL64[k - 1], b, a);
-            a = __fma_rn(-tau0, c, D64[k - 1] * a);
-        }
-        b = c;
-        if ((it & 3) == 3) {
-            const int em = max(dexp(a), dexp(b));
-            a = __builtin_ldexp(a, -em);
-            b = __builtin_ldexp(b, -em);
-        }
-    }
+    prepass_phase(top, D64, LL64, n, tau0, 0, len1, a, b, false, tile, gmin, rmin);
+    __syncthreads();
+    prepass_phase(top, D64, LL64, n, tau0, len1, len2, a, b, true, tile, gmin, rmin);
     {
         const double go = __shfl_xor(gmin, 1, 64);
         const int64_t ro = __shfl_xor(rmin, 1, 64);

@@ -104,6 +104,8 @@ __global__ void k_zero_cols(X* __restrict__ Z, int64_t z_off, int64_t ldz, int64
 // --------------------------------------------------------------------------
 // device buffers
 // --------------------------------------------------------------------------
+constexpr int64_t GUARD = 64;
+
 struct Buf {
     void* p = nullptr;
     size_t cap = 0;
@@ -124,6 +126,10 @@ struct Buf {
         return hipSuccess;
     }
     template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+    // per-row arrays carry GUARD rows (of `width` elements) before and after
+    // the data, so that the kernels' software prefetch may read a few rows
+    // past either end of a representation without bounds arithmetic
+    template <class T> T* rows(int64_t width = 1) const { return as<T>() + GUARD * width; }
     void release() {
         if (p) (void)hipFree(p);
         p = nullptr;
@@ -407,15 +413,15 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(B[B_NODES].ensure(sizeof(Node) * (size_t)std::max<int64_t>(node_cap, 1)));
     // representation pool: root rows first
     int64_t pool_rows = R;
-    HIPCHK(B[B_REPD].ensure(sizeof(Y) * R));
-    HIPCHK(B[B_REPL].ensure(sizeof(Y) * R));
-    HIPCHK(B[B_D64].ensure(sizeof(double) * R));
-    HIPCHK(B[B_L64].ensure(sizeof(double) * R));
+    HIPCHK(B[B_REPD].ensure(sizeof(Y) * (R + 2 * GUARD)));
+    HIPCHK(B[B_REPL].ensure(sizeof(Y) * (R + 2 * GUARD)));
+    HIPCHK(B[B_D64].ensure(sizeof(double) * (R + 2 * GUARD)));
+    HIPCHK(B[B_L64].ensure(sizeof(double) * (R + 2 * GUARD)));
     HIPCHK(B[B_REPE].ensure(sizeof(Y) * R));
-    HIPCHK(B[B_P].ensure(sizeof(Y) * R));
-    HIPCHK(B[B_Q].ensure(sizeof(Y) * R));
-    HIPCHK(B[B_PE].ensure(sizeof(int) * R));
-    HIPCHK(B[B_QE].ensure(sizeof(int) * R));
+    HIPCHK(B[B_P].ensure(sizeof(Y) * (R + 2 * GUARD)));
+    HIPCHK(B[B_Q].ensure(sizeof(Y) * (R + 2 * GUARD)));
+    HIPCHK(B[B_PE].ensure(sizeof(int) * (R + 2 * GUARD)));
+    HIPCHK(B[B_QE].ensure(sizeof(int) * (R + 2 * GUARD)));
     // counters: 8 x u64 (RQI iterations, fallbacks, failures), 8 x double
     // (algorithmic row steps), 8 x int (status)
     const size_t cnt_bytes = sizeof(unsigned long long) * 8 + sizeof(double) * 8 + sizeof(int) * 8;
@@ -449,11 +455,11 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     // ---- a2: root representations ----
     prof.begin(MR3_STAGE_PREP, st);
     hipLaunchKernelGGL(k_root<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_TD].as<double>(),
-                       B[B_TE].as<double>(), prm, B[B_REPD].as<Y>(), B[B_REPL].as<Y>(),
-                       B[B_REPE].as<Y>(), B[B_D64].as<double>(), B[B_L64].as<double>(), dnodes,
+                       B[B_TE].as<double>(), prm, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
+                       B[B_REPE].as<Y>(), B[B_D64].rows<double>(), B[B_L64].rows<double>(), dnodes,
                        dslots, status);
     hipLaunchKernelGGL(k_pq<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_REPE].as<Y>(),
-                       B[B_P].as<Y>(), B[B_PE].as<int>(), B[B_Q].as<Y>(), B[B_QE].as<int>());
+                       B[B_P].rows<Y>(), B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>());
     prof.end(st);
     HIPCHK(hipGetLastError());
     // ---- a3: bisection of every slot on its root ----
@@ -467,8 +473,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     const double widen_root = (is_dd ? 10.0 : 4.0) * 1.1102230246251565e-16;  // x n_block
     int L = pick_lanes(K, prm.lanes_per_eig);
     prof.begin(MR3_STAGE_BISECT, st);
-    launch_bisect(L, B[B_LIST].as<int64_t>(), K, dslots, dnodes, dblocks, B[B_D64].as<double>(),
-                  B[B_L64].as<double>(), prm.bisect_rel, widen_root, work, st);
+    launch_bisect(L, B[B_LIST].as<int64_t>(), K, dslots, dnodes, dblocks, B[B_D64].rows<double>(),
+                  B[B_L64].rows<double>(), prm.bisect_rel, widen_root, work, st);
     prof.end(st);
     HIPCHK(hipGetLastError());
     // ---- output columns of split problems: order by eigenvalue ----
@@ -555,20 +561,20 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                                                     B[B_TILEOFF].as<int64_t>(), nchunk + 1, st));
             std::vector<int64_t> tot;
             HIPCHK(download(tot, B[B_TILEOFF].as<int64_t>() + nchunk, 1, st));
-            HIPCHK(B[B_TILES].ensure(sizeof(double) * std::max<int64_t>(tot[0], 1)));
+            HIPCHK(B[B_TILES].ensure(sizeof(double) * (std::max<int64_t>(tot[0], 1) + 2 * 32 * GUARD)));
             HIPCHK(B[B_RES].ensure(sizeof(RqiResult) * S));
             prof.begin(MR3_STAGE_RQI, st);
             hipLaunchKernelGGL(k_rqi<Y>, dim3((unsigned)nchunk), dim3(64), 0, st,
                                B[B_LIST].as<int64_t>(), S, B[B_TILEOFF].as<int64_t>(),
-                               B[B_TILES].as<double>(), dslots, dnodes, dblocks, B[B_REPD].as<Y>(),
-                               B[B_REPL].as<Y>(), B[B_D64].as<double>(), B[B_L64].as<double>(),
-                               B[B_P].as<Y>(), B[B_PE].as<int>(), B[B_Q].as<Y>(), B[B_QE].as<int>(),
+                               B[B_TILES].rows<double>(32), dslots, dnodes, dblocks, B[B_REPD].rows<Y>(),
+                               B[B_REPL].rows<Y>(), B[B_D64].rows<double>(), B[B_L64].rows<double>(),
+                               B[B_P].rows<Y>(), B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>(),
                                prm, (double)YEps<Y>::v, B[B_RES].as<RqiResult>(), counters, work);
             prof.end(st);
             prof.begin(MR3_STAGE_ZOUT, st);
             hipLaunchKernelGGL((k_zout<X, Y>), dim3((unsigned)nchunk), dim3(256), 0, st,
                                B[B_LIST].as<int64_t>(), S, B[B_TILEOFF].as<int64_t>(),
-                               B[B_TILES].as<double>(), dslots, dnodes, dblocks,
+                               B[B_TILES].rows<double>(32), dslots, dnodes, dblocks,
                                B[B_PINFO].as<ProbInfo>(), B[B_RES].as<RqiResult>(), W,
                                B[B_WOFF].as<int64_t>(), Z, B[B_ZOFF].as<int64_t>(),
                                B[B_LDZ].as<int64_t>());
@@ -637,22 +643,22 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             dnodes = B[B_NODES].as<Node>();
         }
         const int64_t need = pool_rows + new_rows;
-        HIPCHK(B[B_REPD].ensure(sizeof(Y) * need, true, st));
-        HIPCHK(B[B_REPL].ensure(sizeof(Y) * need, true, st));
-        HIPCHK(B[B_D64].ensure(sizeof(double) * need, true, st));
-        HIPCHK(B[B_L64].ensure(sizeof(double) * need, true, st));
+        HIPCHK(B[B_REPD].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
+        HIPCHK(B[B_REPL].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
+        HIPCHK(B[B_D64].ensure(sizeof(double) * (need + 2 * GUARD), true, st));
+        HIPCHK(B[B_L64].ensure(sizeof(double) * (need + 2 * GUARD), true, st));
         HIPCHK(B[B_TMPC].ensure(sizeof(Y) * tmp_rows));
         HIPCHK(B[B_TMPE].ensure(sizeof(int) * tmp_rows));
         HIPCHK(upload(B[B_JOBS], jobs, st));
         prof.begin(MR3_STAGE_CHILD, st);
         hipLaunchKernelGGL(k_child_select, dim3((unsigned)C), dim3(64), 0, st,
                            B[B_JOBS].as<ChildJob>(), C, dslots, dnodes, dblocks,
-                           B[B_D64].as<double>(), B[B_L64].as<double>(), prm,
+                           B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm,
                            prm.eps_x / (double)YEps<Y>::v);
         hipLaunchKernelGGL(k_child_rep<Y>, dim3((unsigned)C), dim3(64), 0, st,
-                           B[B_JOBS].as<ChildJob>(), C, dslots, dnodes, dblocks, B[B_REPD].as<Y>(),
-                           B[B_REPL].as<Y>(), B[B_REPE].as<Y>(), B[B_D64].as<double>(),
-                           B[B_L64].as<double>(), B[B_TMPC].as<Y>(), B[B_TMPE].as<int>(),
+                           B[B_JOBS].as<ChildJob>(), C, dslots, dnodes, dblocks, B[B_REPD].rows<Y>(),
+                           B[B_REPL].rows<Y>(), B[B_REPE].as<Y>(), B[B_D64].rows<double>(),
+                           B[B_L64].rows<double>(), B[B_TMPC].as<Y>(), B[B_TMPE].as<int>(),
                            widen_root / prm.eps_x, prm.eps_x);
         prof.end(st);
         HIPCHK(hipGetLastError());
@@ -680,14 +686,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         const int64_t KC = c2[0];
         L = pick_lanes(KC, prm.lanes_per_eig);
         prof.begin(MR3_STAGE_BISECT, st);
-        launch_bisect(L, B[B_LIST].as<int64_t>(), KC, dslots, dnodes, dblocks, B[B_D64].as<double>(),
-                      B[B_L64].as<double>(), prm.bisect_rel, widen_root, work, st);
+        launch_bisect(L, B[B_LIST].as<int64_t>(), KC, dslots, dnodes, dblocks, B[B_D64].rows<double>(),
+                      B[B_L64].rows<double>(), prm.bisect_rel, widen_root, work, st);
         if (is_dd && KC > 0) {
             // a child may have element growth, so its binary64 copy need not
             // be relatively robust: check every bracket with counts in y
             hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)((KC + 31) / 32)), dim3(64), 0, st,
                                B[B_LIST].as<int64_t>(), KC, dslots, dnodes, dblocks,
-                               B[B_REPD].as<Y>(), B[B_REPL].as<Y>(), prm.bisect_rel, counters + 3);
+                               B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(), prm.bisect_rel, counters + 3);
         }
         prof.end(st);
         HIPCHK(hipGetLastError());
