@@ -154,6 +154,52 @@ __device__ __forceinline__ int negcount64(const double* __restrict__ D,
     return neg;
 }
 
+// Sturm count of the scaled tridiagonal (Td, Te) rows [0, n) at x, division
+// free: the leading minors p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2} change
+// sign once per negative pivot of T - x I.  Same double buffering as
+// negcount64 (guard rows behind the arrays).
+__device__ __forceinline__ int negcount_T(const double* __restrict__ Td,
+                                          const double* __restrict__ Te, int64_t n, double x) {
+    constexpr int U = 8;
+    if (n <= 0) return 0;
+    double pm = 0.0, p = 1.0;  // p_{i-2}, p_{i-1} (p_0 = 1, p_{-1} unused)
+    int neg = 0;
+    double dn[U], en[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        dn[u] = Td[u];
+        en[u] = (u > 0) ? Te[u - 1] : 0.0;
+    }
+    for (int64_t i = 0; i < n; i += U) {
+        double dc[U], ec[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dc[u] = dn[u];
+            ec[u] = en[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dn[u] = Td[i + U + u];
+            en[u] = Te[i + U + u - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (i + u < n) {
+                const double pn = __fma_rn(dc[u] - x, p, -(ec[u] * ec[u]) * pm);
+                neg += sign_differs(pn, p);
+                pm = p;
+                p = pn;
+                if ((u & 3) == 3) {
+                    const int em = max(dexp(p), dexp(pm));
+                    p = __builtin_ldexp(p, -em);
+                    pm = __builtin_ldexp(pm, -em);
+                }
+            }
+        }
+    }
+    return neg;
+}
+
 // the same count in working precision y
 template <class Y>
 __device__ int negcount_y(const Y* __restrict__ D, const Y* __restrict__ LL, int64_t n, Y x) {
@@ -327,6 +373,39 @@ k_prep(const ProbDesc* __restrict__ probs, const X* __restrict__ din, const X* _
         if (i == 0 || te[i - 1] == 0.0) bi[pos++].start = i;
     __syncthreads();
     const int nb = info[p].nblocks;
+    if (nb == 1) {
+        // one block: Gerschgorin bounds by a workgroup reduction, the two
+        // value-range counts on two threads
+        double gl = MR3_BIG, gu = -MR3_BIG;
+        for (int64_t i = t; i < n; i += blockDim.x) {
+            const double off = ((i > 0) ? fabs(te[i - 1]) : 0.0) + ((i + 1 < n) ? fabs(te[i]) : 0.0);
+            gl = fmin(gl, td[i] - off);
+            gu = fmax(gu, td[i] + off);
+        }
+        gl = -block_reduce_max(-gl, sh);
+        gu = block_reduce_max(gu, sh);
+        if (pd.range == RANGE_VALUE && t < 2) {
+            const double v = __builtin_ldexp(t == 0 ? pd.vl : pd.vu, sexp);
+            shi[t] = negcount_T(td, te, n, v);
+        }
+        __syncthreads();
+        if (t == 0) {
+            bi[0].n = n;
+            if (pd.range == RANGE_VALUE) {
+                bi[0].il = shi[0] + 1;
+                bi[0].iu = shi[1];
+            } else if (pd.range == RANGE_INDEX) {
+                bi[0].il = pd.il;
+                bi[0].iu = pd.iu;
+            } else {
+                bi[0].il = 1;
+                bi[0].iu = n;
+            }
+            bi[0].gl = gl;
+            bi[0].gu = gu;
+        }
+        return;
+    }
     for (int b = t; b < nb; b += blockDim.x) {
         const int64_t s = bi[b].start;
         const int64_t en = (b + 1 < nb) ? bi[b + 1].start : n;
@@ -405,15 +484,14 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
     const double spd = fmax(gu - gl, 1e-300);
     // which end: all eigenvalues -> the more populated end; a subset -> the
     // end nearer to the requested indices
+    if (blk.il == 1 && blk.iu == n) {
+        if (t < 2) sc[t] = negcount_T(td, te, n, t == 0 ? gl + 0.25 * spd : gu - 0.25 * spd);
+    }
+    __syncthreads();
     if (t == 0) {
         int right;
-        if (blk.il == 1 && blk.iu == n) {
-            const int c1 = sturm_T(td, te, n, gl + 0.25 * spd);
-            const int c3 = sturm_T(td, te, n, gu - 0.25 * spd);
-            right = ((int64_t)n - c3 > c1) ? 1 : 0;
-        } else {
-            right = (blk.il + blk.iu > n + 1) ? 1 : 0;
-        }
+        if (blk.il == 1 && blk.iu == n) right = ((int64_t)n - sc[1] > sc[0]) ? 1 : 0;
+        else right = (blk.il + blk.iu > n + 1) ? 1 : 0;
         s_right = right;
         s_lo = gl - 1e-3 * spd;
         s_hi = gu + 1e-3 * spd;
@@ -426,7 +504,7 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
         const double lo = s_lo, hi = s_hi;
         const double x = lo + (hi - lo) * ((double)(t + 1) / 256.0);
         sx[t] = x;
-        sc[t] = (t < 255) ? sturm_T(td, te, n, x) : (int)n;
+        sc[t] = (t < 255) ? negcount_T(td, te, n, x) : (int)n;
         __syncthreads();
         if (t == 0) {
             int f = 255;
@@ -448,18 +526,43 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
             double qm = 1.0, q = td[0] - mu;
             d64[blk.row0] = q;
             ok &= right ? (q < 0.0) : (q > 0.0);
-            for (int64_t i = 1; i < n; ++i) {
-                const double ee = te[i - 1];
-                const double qn = __fma_rn(td[i] - mu, q, -(ee * ee) * qm);
-                const double di = qn / q;
-                d64[blk.row0 + i] = di;
-                ok &= right ? (di < 0.0) : (di > 0.0);
-                qm = q;
-                q = qn;
-                if ((i & 3) == 0) {
-                    const int em = max(dexp(q), dexp(qm));
-                    q = __builtin_ldexp(q, -em);
-                    qm = __builtin_ldexp(qm, -em);
+            // rows in blocks of 8, the next block's loads issued first (the
+            // arrays have guard rows behind them)
+            constexpr int U = 8;
+            double dn[U], en[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                dn[u] = td[1 + u];
+                en[u] = te[u];
+            }
+            for (int64_t i0 = 1; i0 < n; i0 += U) {
+                double dc[U], ec[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    dc[u] = dn[u];
+                    ec[u] = en[u];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    dn[u] = td[i0 + U + u];
+                    en[u] = te[i0 + U + u - 1];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t i = i0 + u;
+                    if (i < n) {
+                        const double qn = __fma_rn(dc[u] - mu, q, -(ec[u] * ec[u]) * qm);
+                        const double di = qn / q;
+                        d64[blk.row0 + i] = di;
+                        ok &= right ? (di < 0.0) : (di > 0.0);
+                        qm = q;
+                        q = qn;
+                        if ((u & 3) == 3) {
+                            const int em = max(dexp(q), dexp(qm));
+                            q = __builtin_ldexp(q, -em);
+                            qm = __builtin_ldexp(qm, -em);
+                        }
+                    }
                 }
             }
             s_ok = ok;
@@ -480,7 +583,7 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
     const Y one = y_from(1.0, Y());
     for (int64_t i = t; i < n; i += blockDim.x) {
         const unsigned long long row = (unsigned long long)(blk.start + i);
-        const unsigned long long key = prm.seed + 0x9E37ull * (unsigned long long)blk.prob;
+        const unsigned long long key = prm.seed;
         const double xi_d = prm.xi * urand_pm1(key, row, 0);
         const Y dt = mul(y_from(d64[blk.row0 + i], Y()), add_acc(one, y_from(xi_d, Y())));
         rep_d[blk.row0 + i] = dt;
@@ -488,7 +591,7 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
     __syncthreads();
     for (int64_t i = t; i < n; i += blockDim.x) {
         const unsigned long long row = (unsigned long long)(blk.start + i);
-        const unsigned long long key = prm.seed + 0x9E37ull * (unsigned long long)blk.prob;
+        const unsigned long long key = prm.seed;
         const Y dt = rep_d[blk.row0 + i];
         Y ll = y_from(0.0, Y());
         Y et = y_from(0.0, Y());

@@ -83,12 +83,13 @@ template <class X>
 __global__ void k_check_sorted(const ProbDesc* __restrict__ probs, const int64_t* __restrict__ m,
                                const X* __restrict__ W, const int64_t* __restrict__ w_off,
                                int* __restrict__ bad, int count) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    // one workgroup per problem; bad[p] is cleared by the caller
+    const int p = blockIdx.x;
     if (p >= count) return;
     const X* w = W + w_off[p];
     int b = 0;
-    for (int64_t i = 1; i < m[p]; ++i) b |= !(w[i - 1] <= w[i]);
-    bad[p] = b;
+    for (int64_t i = 1 + threadIdx.x; i < m[p]; i += blockDim.x) b |= !(w[i - 1] <= w[i]);
+    if (b) atomicOr(&bad[p], 1);
 }
 
 template <class X>
@@ -339,11 +340,11 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     if (R == 0) { h->stats = stats; return MR3_OK; }
     HIPCHK(upload(B[B_PROBS], probs, st));
     HIPCHK(B[B_PINFO].ensure(sizeof(ProbInfo) * count));
-    HIPCHK(B[B_TD].ensure(sizeof(double) * R));
-    HIPCHK(B[B_TE].ensure(sizeof(double) * R));
+    HIPCHK(B[B_TD].ensure(sizeof(double) * (R + 2 * GUARD)));
+    HIPCHK(B[B_TE].ensure(sizeof(double) * (R + 2 * GUARD)));
     HIPCHK(B[B_BINFO].ensure(sizeof(BlockInfo) * R));
     hipLaunchKernelGGL(k_prep<X>, dim3((unsigned)count), dim3(256), 0, st, B[B_PROBS].as<ProbDesc>(),
-                       d, e, prm.eps_x, B[B_TD].as<double>(), B[B_TE].as<double>(),
+                       d, e, prm.eps_x, B[B_TD].rows<double>(), B[B_TE].rows<double>(),
                        B[B_PINFO].as<ProbInfo>(), B[B_BINFO].as<BlockInfo>());
     HIPCHK(hipGetLastError());
     std::vector<ProbInfo> pinfo;
@@ -454,8 +455,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     Node* dnodes = B[B_NODES].as<Node>();
     // ---- a2: root representations ----
     prof.begin(MR3_STAGE_PREP, st);
-    hipLaunchKernelGGL(k_root<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_TD].as<double>(),
-                       B[B_TE].as<double>(), prm, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
+    hipLaunchKernelGGL(k_root<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_TD].rows<double>(),
+                       B[B_TE].rows<double>(), prm, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
                        B[B_REPE].as<Y>(), B[B_D64].rows<double>(), B[B_L64].rows<double>(), dnodes,
                        dslots, status);
     hipLaunchKernelGGL(k_pq<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_REPE].as<Y>(),
@@ -721,7 +722,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     std::vector<int64_t> mv(m_p.begin(), m_p.end());
     HIPCHK(upload(B[B_M], mv, st));
     HIPCHK(B[B_BAD].ensure(sizeof(int) * count));
-    hipLaunchKernelGGL(k_check_sorted<X>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+    HIPCHK(hipMemsetAsync(B[B_BAD].p, 0, sizeof(int) * count, st));
+    hipLaunchKernelGGL(k_check_sorted<X>, dim3((unsigned)count), dim3(256), 0, st,
                        B[B_PROBS].as<ProbDesc>(), B[B_M].as<int64_t>(), W, B[B_WOFF].as<int64_t>(),
                        B[B_BAD].as<int>(), (int)count);
     std::vector<int> bad;
