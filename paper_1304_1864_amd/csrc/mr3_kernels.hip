@@ -154,6 +154,78 @@ __device__ __forceinline__ int negcount64(const double* __restrict__ D,
     return neg;
 }
 
+// Sturm counts at P shifts in one pass over the rows: the row loads are shared
+// and the P recurrences are independent chains that fill the FP64 pipeline.
+template <int P>
+__device__ __forceinline__ void negcount64_multi(const double* __restrict__ D,
+                                                 const double* __restrict__ LL, int64_t n,
+                                                 const double (&x)[P], int (&neg)[P]) {
+    constexpr int U = 8;
+    double a[P], b[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        a[p] = -x[p];
+        b[p] = 1.0;
+        neg[p] = 0;
+    }
+    if (n <= 0) return;
+    double dn[U], ln[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        dn[u] = D[u];
+        ln[u] = LL[u];
+    }
+    int64_t i = 0;
+    // full blocks: straight-line code, the next block's loads in flight
+    for (; i + U <= n; i += U) {
+        double dc[U], lc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dc[u] = dn[u];
+            lc[u] = ln[u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dn[u] = D[i + U + u];
+            ln[u] = LL[i + U + u];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const double c = __fma_rn(dc[u], b[p], a[p]);
+                neg[p] += sign_differs(c, b[p]);
+                a[p] = __fma_rn(-x[p], c, lc[u] * a[p]);
+                b[p] = c;
+            }
+            if ((u & 3) == 3) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const int em = max(dexp(a[p]), dexp(b[p]));
+                    a[p] = __builtin_ldexp(a[p], -em);
+                    b[p] = __builtin_ldexp(b[p], -em);
+                }
+            }
+        }
+    }
+    // tail (fewer than U rows), already loaded in dn/ln
+    for (int u = 0; u < U && i + u < n; ++u) {
+        const double du = dn[0], lu = ln[0];
+#pragma unroll
+        for (int v = 0; v + 1 < U; ++v) {
+            dn[v] = dn[v + 1];
+            ln[v] = ln[v + 1];
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double c = __fma_rn(du, b[p], a[p]);
+            neg[p] += sign_differs(c, b[p]);
+            a[p] = __fma_rn(-x[p], c, lu * a[p]);
+            b[p] = c;
+        }
+    }
+}
+
 // Sturm count of the scaled tridiagonal (Td, Te) rows [0, n) at x, division
 // free: the leading minors p_i = (d_i - x) p_{i-1} - e_{i-1}^2 p_{i-2} change
 // sign once per negative pivot of T - x I.  Same double buffering as
@@ -781,16 +853,32 @@ k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slo
             if (w <= rtol * scale || w <= 1e-300 || !(w > 0.0)) busy = false;
         }
         if (!__any(busy)) break;
-        const double h = (hi - lo) / (double)(L + 1);
-        const double x = lo + h * (double)(q + 1);
-        int c = 0;
-        if (busy) c = negcount64(D, LL, n, x);
-        const unsigned long long m = __ballot(busy && c >= j);
+        // L lanes x PTS points: point t = q*PTS + p sits at lo + (t+1) h
+        constexpr int PTS = 4;
+        constexpr int NP = L * PTS;
+        const double h = (hi - lo) / (double)(NP + 1);
+        double xs[PTS];
+        int cs[PTS];
+#pragma unroll
+        for (int p = 0; p < PTS; ++p) xs[p] = lo + h * (double)(q * PTS + p + 1);
         if (busy) {
-            const unsigned long long gm = (m >> gbase) & ((L == 64) ? ~0ull : ((1ull << L) - 1ull));
-            const int f = gm ? __builtin_ctzll(gm) : L;  // first point with count >= j
+            negcount64_multi<PTS>(D, LL, n, xs, cs);
+        } else {
+#pragma unroll
+            for (int p = 0; p < PTS; ++p) cs[p] = 0;
+        }
+        int fp = PTS;  // first of this lane's points with count >= j
+#pragma unroll
+        for (int p = PTS - 1; p >= 0; --p)
+            if (cs[p] >= j) fp = p;
+        const unsigned long long m = __ballot(busy && fp < PTS);
+        const unsigned long long gm = (m >> gbase) & ((L == 64) ? ~0ull : ((1ull << L) - 1ull));
+        const int fq = gm ? __builtin_ctzll(gm) : L;      // first lane with a crossing
+        const int fpo = __shfl(fp, gbase + (fq < L ? fq : 0), 64);  // all lanes take part
+        if (busy) {
+            const int f = (fq < L) ? fq * PTS + fpo : NP;  // first point with count >= j
             const double nlo = (f > 0) ? lo + h * (double)f : lo;
-            const double nhi = (f < L) ? lo + h * (double)(f + 1) : hi;
+            const double nhi = (f < NP) ? lo + h * (double)(f + 1) : hi;
             if (nlo == lo && nhi == hi) busy = false;
             lo = nlo;
             hi = nhi;
@@ -950,9 +1038,9 @@ struct Half {  // per-lane sweep output
 // (top == true) runs the stationary transform over rows 0..r, the bottom lane
 // the progressive one over rows n-1..r, and each stores its part of z
 // (rows < r resp. > r) into its tile column.  Stored values are kept below
-// 2^400 by rebasing the storage exponent; the output kernel multiplies values
-// stored before the last rebase by ev2f and zeroes those stored before the
-// one-but-last (they are below 2^-400 of the final maximum).
+// about 2^300 by rebasing the storage exponent; the output kernel multiplies
+// values stored before the last rebase by ev2f and zeroes those stored before
+// the one-but-last (they are below 2^-250 of the final maximum).
 // One phase of the binary64 twist search.  Step s handles row k = s (top
 // lane, stationary transform) or k = n-1-s (bottom lane, progressive
 // transform).  Without `combine` the quotient s_k = a/b (resp. p_k) is stored
@@ -976,7 +1064,28 @@ __device__ __forceinline__ void prepass_phase(bool top, const double* __restrict
         nl[u] = LL[ka];
         nt[u] = combine ? col[k * 32] : 0.0;
     }
-    for (int64_t i = 0; i < cnt; i += U) {
+    auto body = [&](double dd, double ll, double tt, int64_t sidx, int u) {
+        const int64_t k = top ? sidx : n - 1 - sidx;
+        const double q = a / b;
+        if (combine) {
+            const double g = fabs(q + tt + tau);
+            const bool take = g < gmin || (g == gmin && k < rmin);
+            gmin = take ? g : gmin;
+            rmin = take ? k : rmin;
+        } else {
+            col[k * 32] = q;
+        }
+        const double c = __fma_rn(top ? dd : ll, b, a);
+        a = __fma_rn(-tau, c, (top ? ll : dd) * a);
+        b = c;
+        if ((u & 3) == 3) {
+            const int em = max(dexp(a), dexp(b));
+            a = __builtin_ldexp(a, -em);
+            b = __builtin_ldexp(b, -em);
+        }
+    };
+    int64_t i = 0;
+    for (; i + U <= cnt; i += U) {
         double cd[U], cl[U], ct[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -994,27 +1103,11 @@ __device__ __forceinline__ void prepass_phase(bool top, const double* __restrict
             nt[u] = combine ? col[k * 32] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (i + u >= cnt) continue;
-            const int64_t sidx = s0 + i + u;
-            const int64_t k = top ? sidx : n - 1 - sidx;
-            const double q = a / b;
-            if (combine) {
-                const double g = fabs(q + ct[u] + tau);
-                if (g < gmin || (g == gmin && k < rmin)) { gmin = g; rmin = k; }
-            } else {
-                col[k * 32] = q;
-            }
-            const double c = __fma_rn(top ? cd[u] : cl[u], b, a);
-            a = __fma_rn(-tau, c, (top ? cl[u] : cd[u]) * a);
-            b = c;
-            if (((i + u) & 3) == 3) {
-                const int em = max(dexp(a), dexp(b));
-                a = __builtin_ldexp(a, -em);
-                b = __builtin_ldexp(b, -em);
-            }
-        }
+        for (int u = 0; u < U; ++u) body(cd[u], cl[u], ct[u], s0 + i + u, u);
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (i + u < cnt) body(nd[u], nl[u], nt[u], s0 + i + u, u);
 }
 
 template <class Y>
@@ -1071,55 +1164,68 @@ __device__ Half<Y> sweep(bool top, const Y* __restrict__ D, const Y* __restrict_
 #pragma unroll
         for (int u = 0; u < U; ++u) nx[u] = load_row<Y>(top, D, LL, PQ, PQe, n, u);
     }
-    bool fin = steps <= 0;
-    for (int64_t it0 = 0; !fin; it0 += U) {
+    // z value of row k in the storage frame.  The frame is rebased when the
+    // stored exponent would pass 300 (checked every second row, branch free;
+    // |z| grows by |d+_k / e_k| per row, so values and their squares stay in
+    // range between checks).
+    auto zvalue = [&](const Row<Y>& w, int64_t k, bool check) -> double {
+        const Y pb = mul(w.pq, b);
+        int ex = w.pqe + eb - eref;
+        if (check) {
+            const int ez = y_exp(pb) + ex;
+            const bool rb = ez > 300;
+            const int dlt = rb ? ez : 0;
+            eref += dlt;
+            ex -= dlt;
+            h.ss = __builtin_ldexp(h.ss, -2 * dlt);
+            h.zmax = __builtin_ldexp(h.zmax, -dlt);
+            h.zmaxv = __builtin_ldexp(h.zmaxv, -dlt);
+            h.ev1 = rb ? h.ev2 : h.ev1;
+            h.ev2 = rb ? k : h.ev2;
+            h.ev2f = rb ? __builtin_ldexp(1.0, -dlt) : h.ev2f;
+        }
+        return __builtin_ldexp(to_double(pb), ex);
+    };
+    // one step before the twist row: store z_k, then advance past row k
+    auto body = [&](const Row<Y>& w, int64_t it, int u) {
+        const int64_t k = top ? it : n - 1 - it;
+        const double zv = zvalue(w, k, (u & 1) == 1);
+        if (store) col[k * 32] = zv;
+        h.ss = __fma_rn(zv, zv, h.ss);
+        const bool bigger = fabs(zv) > h.zmax;
+        h.zmax = bigger ? fabs(zv) : h.zmax;
+        h.zmaxv = bigger ? zv : h.zmaxv;
+        h.zmaxk = bigger ? k : h.zmaxk;
+        const Y c = mul_add(top ? w.d : w.ll, b, a);
+        a = sub(mul(top ? w.ll : w.d, a), mul(tau, c));
+        b = c;
+        if ((u & 3) == 3) {
+            const int em = max(y_exp(a), y_exp(b));
+            a = y_ldexp(a, -em);
+            b = y_ldexp(b, -em);
+            eb += em;
+        }
+    };
+    int64_t it0 = 0;
+    // full blocks (the twist row, step steps-1, lies beyond them)
+    for (; it0 + U < steps; it0 += U) {
         Row<Y> cu[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) cu[u] = nx[u];
 #pragma unroll
         for (int u = 0; u < U; ++u) nx[u] = load_row<Y>(top, D, LL, PQ, PQe, n, it0 + U + u);
 #pragma unroll
+        for (int u = 0; u < U; ++u) body(cu[u], it0 + u, u);
+    }
+    // last block: up to U - 1 more steps, then the twist row
+    if (steps > 0) {
+#pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (fin) continue;
             const int64_t it = it0 + u;
-            const int64_t k = top ? it : n - 1 - it;
-            // z_k = PQ_k * b * 2^(PQe_k + eb - eref)
-            const Y pb = mul(cu[u].pq, b);
-            int ex = cu[u].pqe + eb - eref;
-            const int ez = y_exp(pb) + ex;
-            if (ez > 400) {
-                const int dlt = ez;
-                eref += dlt;
-                ex -= dlt;
-                h.ss = __builtin_ldexp(h.ss, -2 * dlt);
-                h.zmax = __builtin_ldexp(h.zmax, -dlt);
-                h.zmaxv = __builtin_ldexp(h.zmaxv, -dlt);
-                h.ev1 = h.ev2;
-                h.ev2 = k;
-                h.ev2f = __builtin_ldexp(1.0, -dlt);
-            }
-            const double zv = __builtin_ldexp(to_double(pb), ex);
-            if (k == r || it + 1 >= steps) {
-                h.zr = zv;
-                fin = true;
-                continue;
-            }
-            if (store) col[k * 32] = zv;
-            h.ss = __fma_rn(zv, zv, h.ss);
-            if (fabs(zv) > h.zmax) {
-                h.zmax = fabs(zv);
-                h.zmaxv = zv;
-                h.zmaxk = k;
-            }
-            // advance the recurrence past row k
-            const Y c = mul_add(top ? cu[u].d : cu[u].ll, b, a);
-            a = sub(mul(top ? cu[u].ll : cu[u].d, a), mul(tau, c));
-            b = c;
-            if ((it & 3) == 3) {
-                const int em = max(y_exp(a), y_exp(b));
-                a = y_ldexp(a, -em);
-                b = y_ldexp(b, -em);
-                eb += em;
+            if (it + 1 < steps) {
+                body(nx[u], it, u);
+            } else if (it + 1 == steps) {
+                h.zr = zvalue(nx[u], top ? it : n - 1 - it, true);
             }
         }
     }
