@@ -65,6 +65,156 @@ def cpu_baseline(d, e, n, budget_s=20.0):
                       f"of the same n={n} matrix, {dt:.1f} s"}
 
 
+def batched_c3(mr3, h, steps, warmup, plain_sample=512, seed=0):
+    """4096 independent problems, n log-uniform in [32, 1024], d, e ~ N(0, 1),
+    FP32 I/O, all eigenpairs: one mr3_solve_batched call per step (batched)
+    against one mr3_solve_f32 per problem in sequence (plain, timed on the
+    first ``plain_sample`` problems)."""
+    import torch
+    import workloads as W
+
+    probs = W.batch_normal(4096, 32, 1024, seed=seed, dtype=np.float32)
+    count = len(probs)
+    n = [int(p[0].size) for p in probs]
+    de_off = np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+    total = int(sum(n))
+    dcat = np.concatenate([p[0] for p in probs])
+    ecat = np.zeros(total, np.float32)
+    for p, o in zip(probs, de_off):
+        ecat[o:o + p[1].size] = p[1]
+    dev = torch.device("cuda:0")
+    dg = torch.from_numpy(dcat).to(dev)
+    eg = torch.from_numpy(ecat).to(dev)
+    w_off = de_off.tolist()
+    z_off = np.concatenate([[0], np.cumsum(np.array(n, np.int64) ** 2)[:-1]]).astype(np.int64).tolist()
+    Wb = torch.empty(total, dtype=torch.float32, device=dev)
+    Zb = torch.empty(int(sum(k * k for k in n)), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return mr3.mr3_solve_batched(h, count, 32, n, de_off.tolist(), dg, eg, None, Wb, w_off, Zb,
+                                     z_off, n, stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(steps):
+        ts = time.perf_counter()
+        m = step()
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - ts) * 1e3)
+    assert sum(m) == total
+    # plain: one solve per problem, sequentially on one stream
+    k = min(plain_sample, count)
+    Wp = torch.empty(1024, dtype=torch.float32, device=dev)
+    Zp = torch.empty((1024, 1024), dtype=torch.float32, device=dev)
+    for i in range(min(8, k)):  # warm-up of the single-solve path
+        mr3.mr3_solve_f32(h, n[i], dg[de_off[i]:], eg[de_off[i]:], mr3.RANGE_ALL, 0.0, 0.0, 1, n[i],
+                          Wp, Zp, n[i], stream)
+    torch.cuda.synchronize()
+    pm = []
+    t0 = time.perf_counter()
+    for i in range(k):
+        ts = time.perf_counter()
+        mr3.mr3_solve_f32(h, n[i], dg[de_off[i]:], eg[de_off[i]:], mr3.RANGE_ALL, 0.0, 0.0, 1, n[i],
+                          Wp, Zp, n[i], stream)
+        torch.cuda.synchronize()
+        pm.append((time.perf_counter() - ts) * 1e3)
+    plain_s = time.perf_counter() - t0
+    pairs_k = int(sum(n[:k]))
+    med = float(np.median(ms))
+    return {
+        "workload": "4096 tridiagonals, n log-uniform in [32, 1024] (sum n = %d), d, e ~ N(0,1), "
+                    "fp32 I/O, fp64 internal, all eigenpairs, seed %d" % (total, seed),
+        "batched": {"eigenpairs_per_s": round(total / (med / 1e3), 1), "p50_ms": round(med, 3),
+                    "p99_ms": round(float(np.percentile(ms, 99)), 3), "steps": steps},
+        "plain": {"eigenpairs_per_s": round(pairs_k / plain_s, 1),
+                  "p50_ms_per_problem": round(float(np.median(pm)), 3),
+                  "p99_ms_per_problem": round(float(np.percentile(pm, 99)), 3),
+                  "sample": f"first {k} problems ({pairs_k} eigenpairs), one mr3_solve_f32 each"},
+    }
+
+
+def served_c5(mr3, n_req=2000, seed=0, window=64, calib=600):
+    """Served stream: requests with n log-uniform in [64, 8192], half FP32 /
+    half FP64, 30% INDEX ranges of ceil(0.1 n), half U(-1,1) and half 1-2-1
+    plus N(0, (1e-6)^2) noise, all vectors.  Saturation S from a closed loop
+    (``window`` requests in flight), then Poisson arrivals at 0.5 S and
+    0.8 S; latency = completion - arrival, including queueing."""
+    import threading
+    import torch
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    reqs = W.served_requests(n_req, seed=seed)
+    inputs = [(torch.from_numpy(r["d"]).to(dev), torch.from_numpy(r["e"]).to(dev)) for r in reqs]
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info(0)
+    srv = mr3.Server(mr3.Handle(0), hbm_budget_bytes=free // 2, max_batch=256)
+
+    def submit(i):
+        kind, il, iu = reqs[i]["range"]
+        return srv.submit(inputs[i][0], inputs[i][1], range=kind, il=il, iu=iu)
+
+    # closed loop: keep `window` requests in flight
+    done, t_first = [], None
+    inflight = []
+    k = 0
+    t0 = time.perf_counter()
+    while k < calib or inflight:
+        while k < calib and len(inflight) < window:
+            inflight.append(submit(k))
+            k += 1
+        res, _, _ = srv.wait(inflight.pop(0))
+        done.append(res)
+    t_closed = time.perf_counter() - t0
+    sat = calib / t_closed
+
+    def open_loop(rate, rs):
+        gaps = rs.exponential(1.0 / rate, n_req)
+        arrive = np.cumsum(gaps)
+        tickets = [None] * n_req
+        lag = np.zeros(n_req)
+        ready = threading.Semaphore(0)
+        base = time.monotonic()
+
+        def producer():
+            for i in range(n_req):
+                dt = base + arrive[i] - time.monotonic()
+                if dt > 0:
+                    time.sleep(dt)
+                lag[i] = max(0.0, time.monotonic() - (base + arrive[i]))
+                tickets[i] = submit(i)
+                ready.release()
+
+        th = threading.Thread(target=producer)
+        th.start()
+        lat, bs = [], []
+        for i in range(n_req):
+            ready.acquire()
+            res, _, _ = srv.wait(tickets[i])
+            lat.append(res["done_ms"] - res["submit_ms"] + lag[i] * 1e3)
+            bs.append(res["batch_size"])
+        th.join()
+        span = time.monotonic() - base
+        return {"offered_req_per_s": round(rate, 1), "achieved_req_per_s": round(n_req / span, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_batch": round(float(np.mean(bs)), 2)}
+
+    rs = np.random.default_rng(seed + 101)
+    out = {"workload": f"{n_req} requests, n log-uniform in [64, 8192], 50/50 fp32/fp64 I/O, "
+                       "30% index range of ceil(0.1 n), 50/50 U(-1,1) or 1-2-1 + N(0,(1e-6)^2), "
+                       f"seed {seed}; HBM budget 50% of free",
+           "saturation_req_per_s": round(sat, 1),
+           "saturation_eigenpairs_per_s": round(sum(r["m"] for r in done) / t_closed, 1),
+           "load_0.5": open_loop(0.5 * sat, rs),
+           "load_0.8": open_loop(0.8 * sat, rs)}
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +224,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-subset", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -155,6 +307,13 @@ def main():
         extra["subset_il1_iu2000"] = {"eigenpairs_per_s": round(2000 / (np.median(ms) / 1e3), 1),
                                       "p50_ms": round(float(np.median(ms)), 3)}
 
+    if not args.no_batched:
+        hb = mr3.Handle(0)
+        extra["batched_vs_plain"] = batched_c3(mr3, hb, max(3, args.steps), 1)
+        hb.close()
+    if not args.no_served:
+        extra["served"] = served_c5(mr3)
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(d, e, n)
     out = {
         "metric": "eigenpairs/s (n=20000, fp64 I/O, dd internal) batched vs plain; p50/p99 solve ms",
@@ -169,7 +328,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 I/O, double-double internal",
+        "dtype": "f64+dd",
         "data": "synthetic",
         "config": {"workload": f"prescribed-spectrum tridiagonal n={n} (geometric |lambda| 1..1e-8, "
                                f"random signs, seed {args.seed}), fp64 I/O, dd internal, all eigenpairs",

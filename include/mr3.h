@@ -92,6 +92,8 @@ typedef struct {
     /* 1: time every kernel launch with HIP events recorded on the launch
      * stream; the per-stage totals appear in mr3_stats */
     int profile;
+    int points_per_lane;   /* bisection points per lane and pass: 1, 2 or 4;
+                              0 = chosen with lanes_per_eig from the size */
 } mr3_params;
 
 /* Diagnostics of the last solve on a handle (Section 4.2 reports d_max and
@@ -124,6 +126,8 @@ typedef struct {
 #define MR3_STAGE_RQI 3      /* twisted-factorization RQI (k_rqi) */
 #define MR3_STAGE_ZOUT 4     /* eigenvector output (k_zout) */
 #define MR3_STAGE_CHILD 5    /* cluster shifts (k_child_select, k_child_rep) */
+#define MR3_STAGE_CBISECT 6  /* multisection of child eigenvalues (k_bisect) */
+#define MR3_STAGE_VERIFY 7   /* check of child brackets in working precision (k_verify) */
 
 /* Create a handle on HIP device `device`.  Fails with MR3_ERR_NO_DEVICE if it
  * does not exist. */
@@ -181,6 +185,71 @@ int mr3_solve_batched(mr3_handle h, int64_t count, int precision, const int64_t 
 int mr3_check_f64(mr3_handle h, int64_t n, int64_t m, const double *d, const double *e,
                   const double *W, const double *Z, int64_t ldz, double *orth_out,
                   double *resid_out, void *stream);
+
+/* ---- Serving: continuous batching of independent requests ----
+ *
+ * A server owns a worker thread and a stream on the handle's device.
+ * Requests queue in arrival order; whenever the device is free the worker
+ * takes the oldest request and every later queued request of the same
+ * precision that fits (at most max_batch requests whose estimated workspace,
+ * mr3_request_bytes, sums to at most hbm_budget_bytes) and solves them as one
+ * batch, exactly like mr3_solve_batched.  Requests of the other precision
+ * wait for a later batch.  The paper's eigenpairs are independent (Section
+ * 3.1), so a batch's results equal those of solving each request alone. */
+typedef struct mr3_server_s *mr3_server;
+
+typedef struct {
+    int precision;        /* 32 or 64: element type of d, e, W, Z */
+    int64_t n;            /* order of T */
+    const void *d;        /* device, n elements */
+    const void *e;        /* device, n-1 elements (may be NULL for n <= 1) */
+    mr3_range_desc range; /* which eigenpairs */
+    void *W;              /* device output, room for every requested eigenvalue */
+    void *Z;              /* device output, column-major ldz x m, or NULL */
+    int64_t ldz;
+} mr3_request;
+
+typedef struct {
+    int status;         /* 0, or the error code of the batch solve */
+    int64_t m;          /* eigenpairs computed */
+    double submit_ms;   /* host steady clock (ms) at submit */
+    double start_ms;    /* ... when its batch was launched */
+    double done_ms;     /* ... when its batch had completed on the device */
+    int64_t batch_id;   /* batches are numbered from 0 */
+    int batch_size;     /* requests in that batch */
+} mr3_result;
+
+/* Device workspace a request of order n with k wanted eigenpairs is budgeted
+ * at (eigenvector tiles, representations, per-row arrays). */
+size_t mr3_request_bytes(int64_t n, int64_t k, int precision);
+
+/* Create a server that takes over handle h (the caller must not use h until
+ * mr3_server_destroy returns).  Arguments: 1 s (output), 2 h, 3
+ * hbm_budget_bytes (> 0), 4 max_batch (>= 1). */
+int mr3_server_create(mr3_server *s, mr3_handle h, size_t hbm_budget_bytes, int max_batch);
+
+/* Host-side scheduler tests: batches go to fn(ctx, count, reqs, m) instead of
+ * the device solver; fn returns a status and fills m[count]. */
+typedef int (*mr3_executor_fn)(void *ctx, int64_t count, const mr3_request *reqs, int64_t *m);
+int mr3_server_create_with_executor(mr3_server *s, mr3_executor_fn fn, void *ctx,
+                                    size_t hbm_budget_bytes, int max_batch);
+
+/* Queue a request (copied; its device buffers must stay valid until the
+ * request completes).  Returns a ticket.  Arguments: 1 s, 2 r, 3 ticket.
+ * Errors: -2 r NULL or invalid (precision, n, pointers, range, ldz); -3 the
+ * request alone exceeds the HBM budget; -4 ticket NULL. */
+int mr3_server_submit(mr3_server s, const mr3_request *r, uint64_t *ticket);
+
+/* *done = 1 once the request's batch has completed, else 0; -2 unknown ticket. */
+int mr3_server_poll(mr3_server s, uint64_t ticket, int *done);
+
+/* Block until the request has completed, copy its result to *out (may be
+ * NULL) and release the ticket.  Returns the request's status. */
+int mr3_server_wait(mr3_server s, uint64_t ticket, mr3_result *out);
+
+/* Finish every queued request, stop the worker and free the server (not the
+ * handle, which the caller may use again). */
+int mr3_server_destroy(mr3_server s);
 
 /* Library version string. */
 const char *mr3_version(void);

@@ -26,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmr3.so")
 
 RANGE_ALL, RANGE_VALUE, RANGE_INDEX = 0, 1, 2
-STAGES = ["prep", "bisect", "classify", "rqi", "zout", "child"]
+STAGES = ["prep", "bisect", "classify", "rqi", "zout", "child", "cbisect", "verify"]
 MR3_OK, MR3_ERR_NUMERIC, MR3_ERR_HIP, MR3_ERR_NO_DEVICE = 0, 1, 2, 3
 
 
@@ -50,6 +50,7 @@ class mr3_params(ctypes.Structure):
         ("force_rqi_fallback", ctypes.c_int),
         ("force_best_candidate", ctypes.c_int),
         ("profile", ctypes.c_int),
+        ("points_per_lane", ctypes.c_int),
     ]
 
 
@@ -81,9 +82,40 @@ class mr3_range_desc(ctypes.Structure):
     ]
 
 
+class mr3_request(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("n", ctypes.c_int64),
+        ("d", ctypes.c_void_p),
+        ("e", ctypes.c_void_p),
+        ("range", mr3_range_desc),
+        ("W", ctypes.c_void_p),
+        ("Z", ctypes.c_void_p),
+        ("ldz", ctypes.c_int64),
+    ]
+
+
+class mr3_result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("m", ctypes.c_int64),
+        ("submit_ms", ctypes.c_double),
+        ("start_ms", ctypes.c_double),
+        ("done_ms", ctypes.c_double),
+        ("batch_id", ctypes.c_int64),
+        ("batch_size", ctypes.c_int),
+    ]
+
+
+# int fn(void* ctx, int64_t count, const mr3_request* reqs, int64_t* m)
+EXECUTOR_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                               ctypes.POINTER(mr3_request), ctypes.POINTER(ctypes.c_int64))
+
 EXPORTS = [
     "mr3_create", "mr3_destroy", "mr3_default_params", "mr3_set_params", "mr3_get_stats",
     "mr3_solve_f32", "mr3_solve_f64", "mr3_solve_batched", "mr3_check_f64", "mr3_version",
+    "mr3_request_bytes", "mr3_server_create", "mr3_server_create_with_executor",
+    "mr3_server_submit", "mr3_server_poll", "mr3_server_wait", "mr3_server_destroy",
 ]
 
 _lib = None
@@ -112,10 +144,19 @@ def load_library(path: str | None = None):
                                       pi64, vp]
     lib.mr3_check_f64.argtypes = [vp, i64, i64, vp, vp, vp, vp, i64,
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
+    lib.mr3_request_bytes.argtypes = [i64, i64, i32]
+    lib.mr3_server_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_size_t, i32]
+    lib.mr3_server_create_with_executor.argtypes = [ctypes.POINTER(vp), EXECUTOR_FN, vp,
+                                                    ctypes.c_size_t, i32]
+    lib.mr3_server_submit.argtypes = [vp, ctypes.POINTER(mr3_request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.mr3_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+    lib.mr3_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(mr3_result)]
+    lib.mr3_server_destroy.argtypes = [vp]
     lib.mr3_version.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name != "mr3_version":
             getattr(lib, name).restype = ctypes.c_int
+    lib.mr3_request_bytes.restype = ctypes.c_size_t
     if path is None:
         _lib = lib
     return lib
@@ -330,3 +371,121 @@ def check(d: torch.Tensor, e: torch.Tensor, W: torch.Tensor, Z: torch.Tensor,
 
 def version() -> str:
     return load_library().mr3_version().decode()
+
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
+def mr3_request_bytes(n: int, k: int, precision: int) -> int:
+    return int(load_library().mr3_request_bytes(n, k, precision))
+
+
+def mr3_server_create(h, hbm_budget_bytes: int, max_batch: int):
+    s = ctypes.c_void_p()
+    _check("mr3_server_create",
+           load_library().mr3_server_create(ctypes.byref(s), h.ptr, hbm_budget_bytes, max_batch))
+    return s
+
+
+def mr3_server_create_with_executor(fn, ctx, hbm_budget_bytes: int, max_batch: int):
+    s = ctypes.c_void_p()
+    _check("mr3_server_create_with_executor",
+           load_library().mr3_server_create_with_executor(ctypes.byref(s), fn, ctx,
+                                                          hbm_budget_bytes, max_batch))
+    return s
+
+
+def mr3_server_submit(s, req: mr3_request) -> int:
+    t = ctypes.c_uint64(0)
+    _check("mr3_server_submit", load_library().mr3_server_submit(s, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def mr3_server_poll(s, ticket: int) -> bool:
+    done = ctypes.c_int(0)
+    _check("mr3_server_poll", load_library().mr3_server_poll(s, ticket, ctypes.byref(done)))
+    return bool(done.value)
+
+
+def mr3_server_wait(s, ticket: int) -> dict:
+    r = mr3_result()
+    rc = load_library().mr3_server_wait(s, ticket, ctypes.byref(r))
+    if rc < 0:
+        raise MR3Error("mr3_server_wait", rc)
+    return {f: getattr(r, f) for f, _ in mr3_result._fields_}
+
+
+def mr3_server_destroy(s) -> None:
+    _check("mr3_server_destroy", load_library().mr3_server_destroy(s))
+
+
+def make_request(d, e, W, Z=None, range: str = "all", vl: float = 0.0, vu: float = 0.0,
+                 il: int = 1, iu: int | None = None) -> mr3_request:
+    """Request for tensors d, e (inputs) and W, Z (outputs, Z an (m, n)
+    row-major == n x m column-major buffer or None)."""
+    n = d.numel()
+    r = mr3_request()
+    r.precision = 32 if d.dtype == torch.float32 else 64
+    r.n = n
+    r.d = d.data_ptr()
+    r.e = e.data_ptr() if (e is not None and n > 1) else None
+    r.range.range = _RANGES[range]
+    r.range.vl, r.range.vu = vl, vu
+    r.range.il, r.range.iu = il, (n if iu is None else iu)
+    r.W = W.data_ptr()
+    r.Z = Z.data_ptr() if Z is not None else None
+    r.ldz = max(n, 1)
+    return r
+
+
+class Server:
+    """Continuous-batching server over a handle (which it takes over while it
+    lives).  submit() returns a ticket; the tensors of a request are kept
+    alive by the server until wait() has returned for it."""
+
+    def __init__(self, handle: Handle | None = None, hbm_budget_bytes: int | None = None,
+                 max_batch: int = 256):
+        self.handle = handle or Handle()
+        if hbm_budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info(self.handle.device)
+            hbm_budget_bytes = free // 2
+        self.budget = int(hbm_budget_bytes)
+        self._s = mr3_server_create(self.handle, self.budget, max_batch)
+        self._keep = {}
+
+    def submit(self, d, e, range: str = "all", vl: float = 0.0, vu: float = 0.0, il: int = 1,
+               iu: int | None = None, vectors: bool = True):
+        n = d.numel()
+        if iu is None:
+            iu = n
+        cap = n if range != "index" else max(iu - il + 1, 0)
+        W = torch.empty(max(cap, 1), dtype=d.dtype, device=d.device)
+        Z = torch.empty((max(cap, 1), max(n, 1)), dtype=d.dtype, device=d.device) if vectors else None
+        req = make_request(d, e, W, Z, range, vl, vu, il, iu)
+        t = mr3_server_submit(self._s, req)
+        self._keep[t] = (d, e, W, Z)
+        return t
+
+    def poll(self, ticket: int) -> bool:
+        return mr3_server_poll(self._s, ticket)
+
+    def wait(self, ticket: int):
+        """-> (result dict, W[m], Z[n, m] or None)"""
+        res = mr3_server_wait(self._s, ticket)
+        d, e, W, Z = self._keep.pop(ticket)
+        if res["status"] != MR3_OK:
+            raise MR3Error("mr3_server_wait", res["status"])
+        m = res["m"]
+        return res, W[:m], (Z[:m].T if Z is not None else None)
+
+    def close(self):
+        if self._s:
+            mr3_server_destroy(self._s)
+            self._s = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmr3.so")
-SOURCES = ["mr3_lib.hip", "mr3_check.hip"]
-HEADERS = ["dd.hpp", "mr3_types.hpp", "mr3_kernels.hip"]
+SOURCES = ["mr3_lib.hip", "mr3_check.hip", "mr3_server.cpp"]
+HEADERS = ["dd.hpp", "mr3_types.hpp", "mr3_kernels.hip", "mr3_internal.h"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -92,75 +92,15 @@ __device__ int sturm_T(const double* __restrict__ Td, const double* __restrict__
     return cnt;
 }
 
-// Sturm count of the binary64 representation (d, lld) at x (division free).
-// Rows are read in blocks of 8 with the next block's loads issued before the
-// current block is processed (register double buffering), so the sequential
-// recurrence does not wait a full memory latency per row.
-__device__ __forceinline__ int negcount64(const double* __restrict__ D,
-                                          const double* __restrict__ LL, int64_t n, double x) {
-    constexpr int U = 8;
-    double a = -x, b = 1.0;
-    int neg = 0;
-    if (n <= 0) return 0;
-    // rows past the end are read from the guard rows of the array
-    double dn[U], ln[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        dn[u] = D[u];
-        ln[u] = LL[u];
-    }
-    for (int64_t i = 0; i < n; i += U) {
-        double dc[U], lc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            dc[u] = dn[u];
-            lc[u] = ln[u];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            dn[u] = D[i + U + u];
-            ln[u] = LL[i + U + u];
-        }
-        if (i + U <= n) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const double c = __fma_rn(dc[u], b, a);
-                neg += sign_differs(c, b);
-                a = __fma_rn(-x, c, lc[u] * a);
-                b = c;
-                if ((u & 3) == 3) {
-                    const int em = max(dexp(a), dexp(b));
-                    a = __builtin_ldexp(a, -em);
-                    b = __builtin_ldexp(b, -em);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (i + u < n) {
-                    const double c = __fma_rn(dc[u], b, a);
-                    neg += sign_differs(c, b);
-                    a = __fma_rn(-x, c, lc[u] * a);
-                    b = c;
-                    if ((u & 3) == 3) {
-                        const int em = max(dexp(a), dexp(b));
-                        a = __builtin_ldexp(a, -em);
-                        b = __builtin_ldexp(b, -em);
-                    }
-                }
-            }
-        }
-    }
-    return neg;
-}
-
 // Sturm counts at P shifts in one pass over the rows: the row loads are shared
 // and the P recurrences are independent chains that fill the FP64 pipeline.
 template <int P>
 __device__ __forceinline__ void negcount64_multi(const double* __restrict__ D,
                                                  const double* __restrict__ LL, int64_t n,
                                                  const double (&x)[P], int (&neg)[P]) {
-    constexpr int U = 8;
+    // rows per block: the next block's loads are in flight while a block is
+    // processed, so fewer chains get longer blocks to cover memory latency
+    constexpr int U = (P == 1) ? 16 : 8;
     double a[P], b[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -224,6 +164,15 @@ __device__ __forceinline__ void negcount64_multi(const double* __restrict__ D,
             b[p] = c;
         }
     }
+}
+
+// Sturm count of the binary64 representation (d, lld) at one shift x
+__device__ __forceinline__ int negcount64(const double* __restrict__ D,
+                                          const double* __restrict__ LL, int64_t n, double x) {
+    const double xs[1] = {x};
+    int c[1];
+    negcount64_multi<1>(D, LL, n, xs, c);
+    return c[0];
 }
 
 // Sturm count of the scaled tridiagonal (Td, Te) rows [0, n) at x, division
@@ -375,8 +324,7 @@ __device__ void index_boundary(const double* Td, const double* Te, int64_t n, do
 
 template <class X>
 __global__ void __launch_bounds__(256)
-k_prep(const ProbDesc* __restrict__ probs, const X* __restrict__ din, const X* __restrict__ ein,
-       double eps_x, double* __restrict__ Td, double* __restrict__ Te, ProbInfo* __restrict__ info,
+k_prep(const ProbDesc* __restrict__ probs, double eps_x, double* __restrict__ Td, double* __restrict__ Te, ProbInfo* __restrict__ info,
        BlockInfo* __restrict__ binfo) {
     __shared__ double sh[256];
     __shared__ int shi[256];
@@ -384,8 +332,8 @@ k_prep(const ProbDesc* __restrict__ probs, const X* __restrict__ din, const X* _
     const int t = threadIdx.x;
     const ProbDesc pd = probs[p];
     const int64_t n = pd.n;
-    const X* d = din + pd.in_off;
-    const X* e = ein + pd.in_off;
+    const X* d = reinterpret_cast<const X*>(pd.din);
+    const X* e = reinterpret_cast<const X*>(pd.ein);
     double* td = Td + pd.row0;
     double* te = Te + pd.row0;
     BlockInfo* bi = binfo + pd.row0;
@@ -795,7 +743,7 @@ k_pq(const Block* __restrict__ blocks, const Y* __restrict__ rep_e, Y* __restric
 // ---------------------------------------------------------------------------
 // a3: multisection on Sturm counts (L lanes per slot, groups inside a wave)
 // ---------------------------------------------------------------------------
-template <int L>
+template <int L, int PTS>
 __global__ void __launch_bounds__(256)
 k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slots,
          const Node* __restrict__ nodes, const Block* __restrict__ blocks,
@@ -854,7 +802,6 @@ k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slo
         }
         if (!__any(busy)) break;
         // L lanes x PTS points: point t = q*PTS + p sits at lo + (t+1) h
-        constexpr int PTS = 4;
         constexpr int NP = L * PTS;
         const double h = (hi - lo) / (double)(NP + 1);
         double xs[PTS];
@@ -1519,9 +1466,8 @@ __global__ void __launch_bounds__(256)
 k_zout(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict__ tile_off,
        const double* __restrict__ tiles, const Slot* __restrict__ slots,
        const Node* __restrict__ nodes, const Block* __restrict__ blocks,
-       const ProbInfo* __restrict__ pinfo, const RqiResult* __restrict__ res, X* __restrict__ W,
-       const int64_t* __restrict__ w_off, X* __restrict__ Z, const int64_t* __restrict__ z_off,
-       const int64_t* __restrict__ ldz) {
+       const ProbInfo* __restrict__ pinfo, const RqiResult* __restrict__ res,
+       const ProbDesc* __restrict__ probs, bool any_z) {
     __shared__ double buf[64][33];
     __shared__ int64_t s_n[32], s_r[32], s_col[32], s_evT1[32], s_evT2[32], s_evB1[32], s_evB2[32];
     __shared__ double s_fT[32], s_fB[32], s_rowr[32], s_evT2f[32], s_evB2f[32];
@@ -1542,7 +1488,8 @@ k_zout(const int64_t* __restrict__ list, int64_t count, const int64_t* __restric
             const int sexp = pinfo[p].sexp;
             // eigenvalue of T: lambda[M] + sigma, rounded to x, unscaled
             Y lam = add_acc(mk_y<Y>(o.lam_hi, o.lam_lo), mk_y<Y>(nd.sigma_hi, nd.sigma_lo));
-            W[w_off[p] + sl.out] = (X)__builtin_ldexp(to_double(lam), -sexp);
+            const ProbDesc pd = probs[p];
+            reinterpret_cast<X*>(pd.wout)[sl.out] = (X)__builtin_ldexp(to_double(lam), -sexp);
             s_n[t] = bk.n;
             s_r[t] = o.r;
             s_fT[t] = o.fT;
@@ -1554,7 +1501,7 @@ k_zout(const int64_t* __restrict__ list, int64_t count, const int64_t* __restric
             s_evB1[t] = o.evB1;
             s_evB2[t] = o.evB2;
             s_evB2f[t] = o.evB2f;
-            s_z[t] = Z ? Z + z_off[p] + sl.out * ldz[p] + bk.start : nullptr;
+            s_z[t] = pd.zout ? reinterpret_cast<X*>(pd.zout) + sl.out * pd.ldz + bk.start : nullptr;
         }
     }
     __syncthreads();
@@ -1564,7 +1511,7 @@ k_zout(const int64_t* __restrict__ list, int64_t count, const int64_t* __restric
         s_rows = m;
     }
     __syncthreads();
-    if (Z == nullptr) return;
+    if (!any_z) return;
     const int64_t rows = s_rows;
     const int wv = t >> 6, ln = t & 63;
     for (int64_t r0 = 0; r0 < rows; r0 += 64) {

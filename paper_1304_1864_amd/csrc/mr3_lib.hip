@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/mr3.h"
+#include "mr3_internal.h"
 #include "mr3_kernels.hip"
 
 namespace mr3 {
@@ -81,24 +82,23 @@ __global__ void k_cluster_recs(const int64_t* __restrict__ heads, int64_t count,
 
 template <class X>
 __global__ void k_check_sorted(const ProbDesc* __restrict__ probs, const int64_t* __restrict__ m,
-                               const X* __restrict__ W, const int64_t* __restrict__ w_off,
                                int* __restrict__ bad, int count) {
     // one workgroup per problem; bad[p] is cleared by the caller
     const int p = blockIdx.x;
     if (p >= count) return;
-    const X* w = W + w_off[p];
+    const X* w = reinterpret_cast<const X*>(probs[p].wout);
     int b = 0;
     for (int64_t i = 1 + threadIdx.x; i < m[p]; i += blockDim.x) b |= !(w[i - 1] <= w[i]);
     if (b) atomicOr(&bad[p], 1);
 }
 
 template <class X>
-__global__ void k_zero_cols(X* __restrict__ Z, int64_t z_off, int64_t ldz, int64_t n, int64_t m) {
+__global__ void k_zero_cols(X* __restrict__ Z, int64_t ldz, int64_t n, int64_t m) {
     const int64_t total = n * m;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t col = t / n, row = t % n;
-        Z[z_off + col * ldz + row] = (X)0;
+        Z[col * ldz + row] = (X)0;
     }
 }
 
@@ -141,9 +141,17 @@ struct Buf {
 enum BufId {
     B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BLOCKS, B_SLOTS, B_NODES, B_REPD, B_REPL, B_REPE,
     B_D64, B_L64, B_P, B_PE, B_Q, B_QE, B_LIST, B_LIST2, B_CNT, B_TILEOFF, B_TILES, B_RES,
-    B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_WOFF, B_ZOFF, B_LDZ, B_M, B_BAD, B_COUNTERS,
-    B_BOFF, B_CREC, B_CHECK, B_NBUF
+    B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_M, B_BAD, B_COUNTERS,
+    B_BOFF, B_CREC, B_CHECK, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
 };
+
+// singleton work of tree level d runs on the handle's side stream with the
+// buffers of parity d & 1, so that it overlaps the cluster work of the same
+// level (which only depends on the classification)
+constexpr int B_SIDE_LIST[2] = {B_SLIST0, B_SLIST1};
+constexpr int B_SIDE_TOFF[2] = {B_TILEOFF, B_TILEOFF1};
+constexpr int B_SIDE_TILES[2] = {B_TILES, B_TILES1};
+constexpr int B_SIDE_RES[2] = {B_RES, B_RES1};
 
 }  // namespace mr3
 
@@ -153,6 +161,11 @@ struct mr3_handle_s {
     bool have_user = false;
     mr3::Buf buf[mr3::B_NBUF];
     mr3_stats stats{};
+    // side stream (default priority) for singleton work, and its events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_side[2] = {nullptr, nullptr};
+    bool side_pending[2] = {false, false};
 };
 
 namespace mr3 {
@@ -251,6 +264,7 @@ static Params effective(const mr3_handle_s* h, int precision) {
     p.max_depth = (h->have_user && u.max_depth > 0) ? u.max_depth : d.max_depth;
     p.rqi_max_iter = (h->have_user && u.rqi_max_iter > 0) ? u.rqi_max_iter : d.rqi_max_iter;
     p.lanes_per_eig = h->have_user ? u.lanes_per_eig : 0;
+    p.points_per_lane = h->have_user ? u.points_per_lane : 0;
     p.force_rqi_fallback = h->have_user ? u.force_rqi_fallback : 0;
     p.force_best_candidate = h->have_user ? u.force_best_candidate : 0;
     p.seed = (h->have_user && u.seed) ? u.seed : d.seed;
@@ -275,44 +289,56 @@ static hipError_t download(std::vector<T>& v, const void* src, size_t count, hip
     return hipStreamSynchronize(st);
 }
 
-static void launch_bisect(int L, const int64_t* list, int64_t count, Slot* slots, const Node* nodes,
-                          const Block* blocks, const double* d64, const double* l64, double rtol,
-                          double widen, double* work, hipStream_t st) {
+// multisection shape: L lanes per eigenvalue, P points per lane and pass
+struct BisectShape {
+    int L, P;
+};
+
+static void launch_bisect(BisectShape sh, const int64_t* list, int64_t count, Slot* slots,
+                          const Node* nodes, const Block* blocks, const double* d64,
+                          const double* l64, double rtol, double widen, double* work,
+                          hipStream_t st) {
     if (count <= 0) return;
-    const int G = 256 / L;
+    const int G = 256 / sh.L;
     const dim3 grid((unsigned)((count + G - 1) / G));
-#define MR3_BIS(LL)                                                                      \
-    case LL:                                                                             \
-        hipLaunchKernelGGL(k_bisect<LL>, grid, dim3(256), 0, st, list, count, slots, nodes, \
-                           blocks, d64, l64, rtol, widen, work);                         \
-        break;
-    switch (L) {
-        MR3_BIS(1) MR3_BIS(2) MR3_BIS(4) MR3_BIS(8) MR3_BIS(16) MR3_BIS(32) MR3_BIS(64)
-        default:
-            hipLaunchKernelGGL(k_bisect<1>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
-                               list, count, slots, nodes, blocks, d64, l64, rtol, widen, work);
+#define MR3_BIS(LL, PP)                                                                        \
+    if (sh.L == LL && sh.P == PP) {                                                            \
+        hipLaunchKernelGGL((k_bisect<LL, PP>), grid, dim3(256), 0, st, list, count, slots,     \
+                           nodes, blocks, d64, l64, rtol, widen, work);                        \
+        return;                                                                                \
     }
+    MR3_BIS(1, 1) MR3_BIS(1, 2) MR3_BIS(1, 4)
+    MR3_BIS(2, 1) MR3_BIS(2, 2) MR3_BIS(2, 4)
+    MR3_BIS(4, 1) MR3_BIS(4, 2) MR3_BIS(4, 4)
+    MR3_BIS(8, 1) MR3_BIS(8, 2) MR3_BIS(8, 4)
+    MR3_BIS(16, 1) MR3_BIS(16, 2) MR3_BIS(16, 4)
+    MR3_BIS(32, 1) MR3_BIS(32, 2) MR3_BIS(32, 4)
+    MR3_BIS(64, 1) MR3_BIS(64, 2) MR3_BIS(64, 4)
 #undef MR3_BIS
+    hipLaunchKernelGGL((k_bisect<1, 4>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                       list, count, slots, nodes, blocks, d64, l64, rtol, widen, work);
 }
 
-// lanes per eigenvalue: enough lanes to give the device ~64K concurrent
-// counts, at most 64 (one wave), at least 1
-static int pick_lanes(int64_t count, int user) {
-    if (user > 0) {
-        int L = 1;
-        while (L * 2 <= user && L < 64) L *= 2;
-        return L;
+// lanes per eigenvalue and points per lane.  Measured on the device: the
+// counts are latency bound, so L doubles until ~32K lanes are busy (at most
+// 64 lanes, one wave, per eigenvalue); two independent chains per lane pay
+// off while L is small, one chain is the least work once lanes are plentiful.
+static BisectShape pick_shape(int64_t count, int user_lanes, int user_points) {
+    BisectShape sh{1, 1};
+    if (user_lanes > 0) {
+        while (sh.L * 2 <= user_lanes && sh.L < 64) sh.L *= 2;
+    } else {
+        while (sh.L < 64 && count * sh.L < 32768) sh.L *= 2;
     }
-    int L = 1;
-    while (L < 64 && count * L * 2 <= 65536) L *= 2;
-    return L;
+    if (user_points == 1 || user_points == 2 || user_points == 4) sh.P = user_points;
+    else sh.P = (count * sh.L >= 262144 || sh.L > 4) ? 1 : 2;
+    return sh;
 }
 
 template <class X, class Y>
-static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const int64_t* de_off,
-                      const X* d, const X* e, const mr3_range_desc* ranges, int64_t* m_out, X* W,
-                      const int64_t* w_off_h, X* Z, const int64_t* z_off_h, const int64_t* ldz_h,
-                      hipStream_t st) {
+static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const X* const* d_p,
+                      const X* const* e_p, const mr3_range_desc* ranges, int64_t* m_out,
+                      X* const* W_p, X* const* Z_p, const int64_t* ldz_h, hipStream_t st) {
     const int precision = sizeof(X) == 4 ? 32 : 64;
     const Params prm = effective(h, precision);
     const double t_start = now_ms();
@@ -320,13 +346,47 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     Buf* B = h->buf;
     mr3_stats stats{};
     HIPCHK(hipSetDevice(h->device));
+    if (!h->side) {
+        HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_side[0], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->ev_side[1], hipEventDisableTiming));
+    }
+    // work a failed earlier call left on the side stream must end before
+    // buffers are reused
+    if (h->side_pending[0] || h->side_pending[1]) {
+        HIPCHK(hipStreamSynchronize(h->side));
+        h->side_pending[0] = h->side_pending[1] = false;
+    }
+    hipStream_t side = h->side;
+    // every exit makes `st` wait for the side stream, so that synchronizing
+    // the caller's stream covers all of this call's work
+    struct SideJoin {
+        mr3_handle_s* h;
+        hipStream_t st;
+        ~SideJoin() {
+            for (int q = 0; q < 2; ++q)
+                if (h->side_pending[q]) (void)hipStreamWaitEvent(st, h->ev_side[q], 0);
+        }
+    } side_join{h, st};
+    // synchronizes the side stream before a buffer it may read is reallocated
+    auto quiesce = [&]() -> hipError_t {
+        if (!h->side_pending[0] && !h->side_pending[1]) return hipSuccess;
+        hipError_t e = hipStreamSynchronize(side);
+        h->side_pending[0] = h->side_pending[1] = false;
+        return e;
+    };
     // ---- problems ----
     std::vector<ProbDesc> probs((size_t)count);
     int64_t R = 0;
     for (int64_t p = 0; p < count; ++p) {
         ProbDesc& pd = probs[p];
         pd.n = n_h[p];
-        pd.in_off = de_off ? de_off[p] : 0;
+        pd.din = d_p[p];
+        pd.ein = e_p[p] ? e_p[p] : d_p[p];  // never read for n <= 1
+        pd.wout = W_p[p];
+        pd.zout = Z_p ? Z_p[p] : nullptr;
+        pd.ldz = (Z_p && Z_p[p]) ? ldz_h[p] : 1;
         pd.row0 = R;
         pd.range = ranges ? ranges[p].range : RANGE_ALL;
         pd.vl = ranges ? ranges[p].vl : 0.0;
@@ -344,7 +404,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(B[B_TE].ensure(sizeof(double) * (R + 2 * GUARD)));
     HIPCHK(B[B_BINFO].ensure(sizeof(BlockInfo) * R));
     hipLaunchKernelGGL(k_prep<X>, dim3((unsigned)count), dim3(256), 0, st, B[B_PROBS].as<ProbDesc>(),
-                       d, e, prm.eps_x, B[B_TD].rows<double>(), B[B_TE].rows<double>(),
+                       prm.eps_x, B[B_TD].rows<double>(), B[B_TE].rows<double>(),
                        B[B_PINFO].as<ProbInfo>(), B[B_BINFO].as<BlockInfo>());
     HIPCHK(hipGetLastError());
     std::vector<ProbInfo> pinfo;
@@ -433,22 +493,17 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     int* status = reinterpret_cast<int*>(work + 8);
     Prof prof;
     prof.on = prm.profile != 0;
-    // outputs
-    std::vector<int64_t> w_off(w_off_h, w_off_h + count), z_off(count, 0), ldz(count, 1);
-    if (Z) {
-        for (int64_t p = 0; p < count; ++p) { z_off[p] = z_off_h[p]; ldz[p] = ldz_h[p]; }
-    }
-    HIPCHK(upload(B[B_WOFF], w_off, st));
-    HIPCHK(upload(B[B_ZOFF], z_off, st));
-    HIPCHK(upload(B[B_LDZ], ldz, st));
-    if (Z) {
-        for (int64_t p = 0; p < count; ++p)
-            if (multi[p] && m_p[p] > 0) {
-                const int64_t tot = probs[p].n * m_p[p];
-                const unsigned g = (unsigned)std::min<int64_t>((tot + 255) / 256, 4096);
-                hipLaunchKernelGGL(k_zero_cols<X>, dim3(g), dim3(256), 0, st, Z, z_off[p], ldz[p],
-                                   probs[p].n, m_p[p]);
-            }
+    // outputs: columns of split problems are zeroed outside their blocks
+    bool any_z = false;
+    for (int64_t p = 0; p < count; ++p) {
+        X* Zp = reinterpret_cast<X*>(probs[p].zout);
+        any_z |= Zp != nullptr;
+        if (Zp && multi[p] && m_p[p] > 0) {
+            const int64_t tot = probs[p].n * m_p[p];
+            const unsigned g = (unsigned)std::min<int64_t>((tot + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_zero_cols<X>, dim3(g), dim3(256), 0, st, Zp, probs[p].ldz,
+                               probs[p].n, m_p[p]);
+        }
     }
     Block* dblocks = B[B_BLOCKS].as<Block>();
     Slot* dslots = B[B_SLOTS].as<Slot>();
@@ -472,7 +527,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     // constant of the copy, Sec. 3.2 "Arithmetic used to approximate
     // eigenvalues"), 4 when the copy is the representation itself
     const double widen_root = (is_dd ? 10.0 : 4.0) * 1.1102230246251565e-16;  // x n_block
-    int L = pick_lanes(K, prm.lanes_per_eig);
+    BisectShape L = pick_shape(K, prm.lanes_per_eig, prm.points_per_lane);
     prof.begin(MR3_STAGE_BISECT, st);
     launch_bisect(L, B[B_LIST].as<int64_t>(), K, dslots, dnodes, dblocks, B[B_D64].rows<double>(),
                   B[B_L64].rows<double>(), prm.bisect_rel, widen_root, work, st);
@@ -522,17 +577,28 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                            B[B_LIST].as<int64_t>(), (int64_t)level_nodes.size(), dnodes, dslots,
                            B[B_FLAGS].as<int>(), prm.gaptol, force_single);
         HIPCHK(hipGetLastError());
-        // compact the singletons and cluster heads of this level
+        // compact the singletons (into the side list of this level's parity)
+        // and the cluster heads of this level
+        const int par = depth & 1;
+        if (h->side_pending[par]) {  // level depth-2 still owns these buffers
+            HIPCHK(hipEventSynchronize(h->ev_side[par]));
+            h->side_pending[par] = false;
+        }
+        Buf& SL = B[B_SIDE_LIST[par]];
+        Buf& STO = B[B_SIDE_TOFF[par]];
+        Buf& STI = B[B_SIDE_TILES[par]];
+        Buf& SRE = B[B_SIDE_RES[par]];
+        HIPCHK(SL.ensure(sizeof(int64_t) * K));
         size_t tmp_bytes = 0, tb2 = 0;
         SelectKind sel_s{dslots, dnodes, KIND_SINGLETON, depth};
         SelectKind sel_c{dslots, dnodes, KIND_CLUSTER_HEAD, depth};
-        HIPCHK(hipcub::DeviceSelect::If(nullptr, tmp_bytes, iter, B[B_LIST].as<int64_t>(), dcnt, K,
+        HIPCHK(hipcub::DeviceSelect::If(nullptr, tmp_bytes, iter, SL.as<int64_t>(), dcnt, K,
                                         sel_s, st));
         HIPCHK(hipcub::DeviceSelect::If(nullptr, tb2, iter, B[B_LIST2].as<int64_t>(), dcnt + 1, K,
                                         sel_c, st));
         HIPCHK(B[B_CUBTMP].ensure(std::max(tmp_bytes, tb2) + 256));
         tmp_bytes = B[B_CUBTMP].cap;
-        HIPCHK(hipcub::DeviceSelect::If(B[B_CUBTMP].p, tmp_bytes, iter, B[B_LIST].as<int64_t>(),
+        HIPCHK(hipcub::DeviceSelect::If(B[B_CUBTMP].p, tmp_bytes, iter, SL.as<int64_t>(),
                                         dcnt, K, sel_s, st));
         tmp_bytes = B[B_CUBTMP].cap;
         HIPCHK(hipcub::DeviceSelect::If(B[B_CUBTMP].p, tmp_bytes, iter, B[B_LIST2].as<int64_t>(),
@@ -544,53 +610,66 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         if (debug_on())
             std::fprintf(stderr, "[mr3] depth %d: nodes %zu singletons %lld clusters %lld  t=%.2f ms\n",
                          depth, level_nodes.size(), (long long)S, (long long)C, now_ms() - t_start);
-        // ---- a6 + a7: singletons ----
+        // ---- a6 + a7: singletons, on the side stream ----
         if (S > 0) {
             const int64_t nchunk = (S + 31) / 32;
-            HIPCHK(B[B_TILEOFF].ensure(sizeof(int64_t) * (nchunk + 1)));
+            HIPCHK(STO.ensure(sizeof(int64_t) * (nchunk + 1)));
             HIPCHK(B[B_FLAGS].ensure(sizeof(int64_t) * (nchunk + 1)));
             int64_t* rows = reinterpret_cast<int64_t*>(B[B_FLAGS].p);
             hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)((nchunk + 255) / 256)), dim3(256), 0, st,
-                               B[B_LIST].as<int64_t>(), S, dslots, dnodes, dblocks, rows, nchunk);
+                               SL.as<int64_t>(), S, dslots, dnodes, dblocks, rows, nchunk);
             size_t sb = 0;
-            HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, sb, rows, B[B_TILEOFF].as<int64_t>(),
-                                                    nchunk + 1, st));
+            HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, sb, rows, STO.as<int64_t>(), nchunk + 1,
+                                                    st));
             HIPCHK(B[B_CUBTMP].ensure(sb + 256));
             sb = B[B_CUBTMP].cap;
             HIPCHK(hipMemsetAsync(rows + nchunk, 0, sizeof(int64_t), st));
-            HIPCHK(hipcub::DeviceScan::ExclusiveSum(B[B_CUBTMP].p, sb, rows,
-                                                    B[B_TILEOFF].as<int64_t>(), nchunk + 1, st));
+            HIPCHK(hipcub::DeviceScan::ExclusiveSum(B[B_CUBTMP].p, sb, rows, STO.as<int64_t>(),
+                                                    nchunk + 1, st));
             std::vector<int64_t> tot;
-            HIPCHK(download(tot, B[B_TILEOFF].as<int64_t>() + nchunk, 1, st));
-            HIPCHK(B[B_TILES].ensure(sizeof(double) * (std::max<int64_t>(tot[0], 1) + 2 * 32 * GUARD)));
-            HIPCHK(B[B_RES].ensure(sizeof(RqiResult) * S));
-            prof.begin(MR3_STAGE_RQI, st);
-            hipLaunchKernelGGL(k_rqi<Y>, dim3((unsigned)nchunk), dim3(64), 0, st,
-                               B[B_LIST].as<int64_t>(), S, B[B_TILEOFF].as<int64_t>(),
-                               B[B_TILES].rows<double>(32), dslots, dnodes, dblocks, B[B_REPD].rows<Y>(),
-                               B[B_REPL].rows<Y>(), B[B_D64].rows<double>(), B[B_L64].rows<double>(),
-                               B[B_P].rows<Y>(), B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>(),
-                               prm, (double)YEps<Y>::v, B[B_RES].as<RqiResult>(), counters, work);
-            prof.end(st);
-            prof.begin(MR3_STAGE_ZOUT, st);
-            hipLaunchKernelGGL((k_zout<X, Y>), dim3((unsigned)nchunk), dim3(256), 0, st,
-                               B[B_LIST].as<int64_t>(), S, B[B_TILEOFF].as<int64_t>(),
-                               B[B_TILES].rows<double>(32), dslots, dnodes, dblocks,
-                               B[B_PINFO].as<ProbInfo>(), B[B_RES].as<RqiResult>(), W,
-                               B[B_WOFF].as<int64_t>(), Z, B[B_ZOFF].as<int64_t>(),
-                               B[B_LDZ].as<int64_t>());
-            prof.end(st);
+            HIPCHK(download(tot, STO.as<int64_t>() + nchunk, 1, st));
+            HIPCHK(STI.ensure(sizeof(double) * (std::max<int64_t>(tot[0], 1) + 2 * 32 * GUARD)));
+            HIPCHK(SRE.ensure(sizeof(RqiResult) * S));
+            HIPCHK(hipEventRecord(h->ev_fork, st));
+            HIPCHK(hipStreamWaitEvent(side, h->ev_fork, 0));
+            prof.begin(MR3_STAGE_RQI, side);
+            hipLaunchKernelGGL(k_rqi<Y>, dim3((unsigned)nchunk), dim3(64), 0, side,
+                               SL.as<int64_t>(), S, STO.as<int64_t>(), STI.rows<double>(32), dslots,
+                               dnodes, dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
+                               B[B_D64].rows<double>(), B[B_L64].rows<double>(), B[B_P].rows<Y>(),
+                               B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>(), prm,
+                               (double)YEps<Y>::v, SRE.as<RqiResult>(), counters, work);
+            prof.end(side);
+            prof.begin(MR3_STAGE_ZOUT, side);
+            hipLaunchKernelGGL((k_zout<X, Y>), dim3((unsigned)nchunk), dim3(256), 0, side,
+                               SL.as<int64_t>(), S, STO.as<int64_t>(), STI.rows<double>(32), dslots,
+                               dnodes, dblocks, B[B_PINFO].as<ProbInfo>(), SRE.as<RqiResult>(),
+                               B[B_PROBS].as<ProbDesc>(), any_z);
+            prof.end(side);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipEventRecord(h->ev_side[par], side));
+            h->side_pending[par] = true;
             if (debug_on()) {
+                HIPCHK(hipStreamSynchronize(side));
                 std::vector<unsigned long long> c;
                 HIPCHK(download(c, counters, 3, st));
                 std::fprintf(stderr, "[mr3]   after RQI: iters %llu fallbacks %llu failures %llu t=%.2f ms\n",
                              c[0], c[1], c[2], now_ms() - t_start);
+                if (std::getenv("MR3_DEBUG")[0] == '3') {
+                    std::vector<RqiResult> rr;
+                    HIPCHK(download(rr, SRE.p, (size_t)S, st));
+                    int64_t hist[12] = {0};
+                    for (int64_t i = 0; i < S; ++i) hist[std::min(std::max(rr[i].iters, 0), 11)]++;
+                    std::fprintf(stderr, "[mr3]   iteration histogram:");
+                    for (int k = 0; k < 12; ++k) std::fprintf(stderr, " %d:%lld", k, (long long)hist[k]);
+                    std::fprintf(stderr, "\n");
+                }
                 if (std::getenv("MR3_DEBUG")[0] == '2') {
                     std::vector<RqiResult> rr;
                     std::vector<int64_t> ls;
                     std::vector<Slot> sl;
-                    HIPCHK(download(rr, B[B_RES].p, (size_t)S, st));
-                    HIPCHK(download(ls, B[B_LIST].p, (size_t)S, st));
+                    HIPCHK(download(rr, SRE.p, (size_t)S, st));
+                    HIPCHK(download(ls, SL.p, (size_t)S, st));
                     HIPCHK(download(sl, dslots, (size_t)K, st));
                     for (int64_t i = 0; i < S; ++i)
                         if (rr[i].status != 0 || rr[i].iters >= 6)
@@ -604,7 +683,6 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                                          (long long)rr[i].evB2);
                 }
             }
-            HIPCHK(hipGetLastError());
         }
         level_nodes.clear();
         if (C == 0) break;
@@ -638,12 +716,19 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             }
         }
         stats.n_clusters += C;
+        // the side stream reads nodes and representations: it must be idle
+        // before any of these buffers is reallocated
+        const int64_t need = pool_rows + new_rows;
+        if (n_nodes + C > node_cap || B[B_REPD].cap < sizeof(Y) * (need + 2 * GUARD) ||
+            B[B_REPL].cap < sizeof(Y) * (need + 2 * GUARD) ||
+            B[B_D64].cap < sizeof(double) * (need + 2 * GUARD) ||
+            B[B_L64].cap < sizeof(double) * (need + 2 * GUARD))
+            HIPCHK(quiesce());
         if (n_nodes + C > node_cap) {
             node_cap = n_nodes + C + K;
             HIPCHK(B[B_NODES].ensure(sizeof(Node) * node_cap, true, st));
             dnodes = B[B_NODES].as<Node>();
         }
-        const int64_t need = pool_rows + new_rows;
         HIPCHK(B[B_REPD].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
         HIPCHK(B[B_REPL].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
         HIPCHK(B[B_D64].ensure(sizeof(double) * (need + 2 * GUARD), true, st));
@@ -685,10 +770,16 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         std::vector<int64_t> c2;
         HIPCHK(download(c2, dcnt + 2, 1, st));
         const int64_t KC = c2[0];
-        L = pick_lanes(KC, prm.lanes_per_eig);
-        prof.begin(MR3_STAGE_BISECT, st);
+        L = pick_shape(KC, prm.lanes_per_eig, prm.points_per_lane);
+        if (const char* cs = std::getenv("MR3_CHILD_SHAPE")) {  // development aid: "L,P"
+            int l = 0, q = 0;
+            if (std::sscanf(cs, "%d,%d", &l, &q) == 2) L = pick_shape(KC, l, q);
+        }
+        prof.begin(MR3_STAGE_CBISECT, st);
         launch_bisect(L, B[B_LIST].as<int64_t>(), KC, dslots, dnodes, dblocks, B[B_D64].rows<double>(),
                       B[B_L64].rows<double>(), prm.bisect_rel, widen_root, work, st);
+        prof.end(st);
+        prof.begin(MR3_STAGE_VERIFY, st);
         if (is_dd && KC > 0) {
             // a child may have element growth, so its binary64 copy need not
             // be relatively robust: check every bracket with counts in y
@@ -700,7 +791,12 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         HIPCHK(hipGetLastError());
         for (int64_t c = 0; c < C; ++c) level_nodes.push_back(jobs[c].child);
     }
-    // ---- diagnostics and the ascending-order check ----
+    // ---- join the side stream; diagnostics and the ascending-order check ----
+    for (int q = 0; q < 2; ++q)
+        if (h->side_pending[q]) {
+            HIPCHK(hipStreamWaitEvent(st, h->ev_side[q], 0));
+            h->side_pending[q] = false;
+        }
     std::vector<unsigned long long> ctr;
     HIPCHK(download(ctr, counters, 8, st));
     std::vector<int> sts;
@@ -724,8 +820,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(B[B_BAD].ensure(sizeof(int) * count));
     HIPCHK(hipMemsetAsync(B[B_BAD].p, 0, sizeof(int) * count, st));
     hipLaunchKernelGGL(k_check_sorted<X>, dim3((unsigned)count), dim3(256), 0, st,
-                       B[B_PROBS].as<ProbDesc>(), B[B_M].as<int64_t>(), W, B[B_WOFF].as<int64_t>(),
-                       B[B_BAD].as<int>(), (int)count);
+                       B[B_PROBS].as<ProbDesc>(), B[B_M].as<int64_t>(), B[B_BAD].as<int>(),
+                       (int)count);
     std::vector<int> bad;
     HIPCHK(download(bad, B[B_BAD].p, (size_t)count, st));
     for (int64_t p = 0; p < count; ++p) {
@@ -735,20 +831,22 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         // order; sort the pairs on the host
         const int64_t mp = m_p[p], np = probs[p].n;
         std::vector<X> w((size_t)mp);
-        HIPCHK(hipMemcpy(w.data(), W + w_off[p], sizeof(X) * mp, hipMemcpyDeviceToHost));
+        X* Wp = reinterpret_cast<X*>(probs[p].wout);
+        X* Zp = reinterpret_cast<X*>(probs[p].zout);
+        HIPCHK(hipMemcpy(w.data(), Wp, sizeof(X) * mp, hipMemcpyDeviceToHost));
         std::vector<int64_t> perm((size_t)mp);
         std::iota(perm.begin(), perm.end(), 0);
         std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return w[a] < w[b]; });
         std::vector<X> w2((size_t)mp);
         for (int64_t i = 0; i < mp; ++i) w2[i] = w[perm[i]];
-        HIPCHK(hipMemcpy(W + w_off[p], w2.data(), sizeof(X) * mp, hipMemcpyHostToDevice));
-        if (Z) {
+        HIPCHK(hipMemcpy(Wp, w2.data(), sizeof(X) * mp, hipMemcpyHostToDevice));
+        if (Zp) {
             // apply the permutation to the columns on the device, cycle by
             // cycle through one scratch column (only misplaced columns move)
             HIPCHK(B[B_CHECK].ensure(sizeof(X) * (size_t)std::max<int64_t>(np, 1)));
             X* tmp = B[B_CHECK].as<X>();
             std::vector<char> seen((size_t)mp, 0);
-            auto col = [&](int64_t c) { return Z + z_off[p] + c * ldz[p]; };
+            auto col = [&](int64_t c) { return Zp + c * probs[p].ldz; };
             for (int64_t s0 = 0; s0 < mp; ++s0) {
                 if (seen[s0] || perm[s0] == s0) { seen[s0] = 1; continue; }
                 // new column i takes old column perm[i]
@@ -807,12 +905,58 @@ static int solve_single(mr3_handle h, int64_t n, const X* d, const X* e, int ran
     rd.vu = vu;
     rd.il = il;
     rd.iu = iu;
-    const int64_t nn = n, off = 0, wo = 0, zo = 0, lz = ldz;
-    // e may be NULL for n <= 1: point it at d (never read)
-    const X* ee = e ? e : d;
-    rc = solve_impl<X, Y>(h, 1, &nn, &off, d, ee, &rd, m, W, &wo, Z, &zo, &lz, (hipStream_t)stream);
+    const int64_t nn = n, lz = ldz;
+    rc = solve_impl<X, Y>(h, 1, &nn, &d, &e, &rd, m, &W, &Z, &lz, (hipStream_t)stream);
     return rc;
 }
+
+// base pointers + element offsets -> per-problem pointers
+template <class X, class Y>
+static int batched_ptrs(mr3_handle h, int64_t count, const int64_t* n, const int64_t* de_off,
+                        const X* d, const X* e, const mr3_range_desc* ranges, int64_t* m, X* W,
+                        const int64_t* w_off, X* Z, const int64_t* z_off, const int64_t* ldz,
+                        hipStream_t st) {
+    std::vector<const X*> dp((size_t)count), ep((size_t)count);
+    std::vector<X*> wp((size_t)count), zp((size_t)count, nullptr);
+    for (int64_t p = 0; p < count; ++p) {
+        dp[p] = d + de_off[p];
+        ep[p] = e + de_off[p];
+        wp[p] = W + w_off[p];
+        if (Z) zp[p] = Z + z_off[p];
+    }
+    return solve_impl<X, Y>(h, count, n, dp.data(), ep.data(), ranges, m, wp.data(),
+                            Z ? zp.data() : nullptr, ldz, st);
+}
+
+template <class X, class Y>
+static int solve_ptrs_typed(mr3_handle h, int64_t count, const int64_t* n, const void* const* d,
+                            const void* const* e, const mr3_range_desc* ranges, int64_t* m,
+                            void* const* W, void* const* Z, const int64_t* ldz, hipStream_t st) {
+    std::vector<const X*> dp((size_t)count), ep((size_t)count);
+    std::vector<X*> wp((size_t)count), zp((size_t)count, nullptr);
+    for (int64_t p = 0; p < count; ++p) {
+        dp[p] = static_cast<const X*>(d[p]);
+        ep[p] = static_cast<const X*>(e[p]);
+        wp[p] = static_cast<X*>(W[p]);
+        if (Z) zp[p] = static_cast<X*>(Z[p]);
+    }
+    return solve_impl<X, Y>(h, count, n, dp.data(), ep.data(), ranges, m, wp.data(),
+                            Z ? zp.data() : nullptr, ldz, st);
+}
+
+int mr3_solve_ptrs(mr3_handle h, int precision, int64_t count, const int64_t* n,
+                   const void* const* d, const void* const* e, const mr3_range_desc* ranges,
+                   int64_t* m, void* const* W, void* const* Z, const int64_t* ldz, void* stream) {
+    if (!h) return -1;
+    if (count <= 0) return MR3_OK;
+    if (precision == 32)
+        return solve_ptrs_typed<float, double>(h, count, n, d, e, ranges, m, W, Z, ldz,
+                                               (hipStream_t)stream);
+    return solve_ptrs_typed<double, dd>(h, count, n, d, e, ranges, m, W, Z, ldz,
+                                        (hipStream_t)stream);
+}
+
+int mr3_handle_device(mr3_handle h) { return h ? h->device : -1; }
 
 extern "C" {
 
@@ -832,7 +976,12 @@ int mr3_create(mr3_handle* h, int device) {
 int mr3_destroy(mr3_handle h) {
     if (!h) return -1;
     (void)hipSetDevice(h->device);
+    if (h->side) (void)hipStreamSynchronize(h->side);
     for (auto& b : h->buf) b.release();
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    for (auto& ev : h->ev_side)
+        if (ev) (void)hipEventDestroy(ev);
+    if (h->side) (void)hipStreamDestroy(h->side);
     delete h;
     return MR3_OK;
 }
@@ -900,11 +1049,12 @@ int mr3_solve_batched(mr3_handle h, int64_t count, int precision, const int64_t*
     if (!m) return -9;
     if (!W || !w_off) return -10;
     if (precision == 32)
-        return solve_impl<float, double>(h, count, n, de_off, (const float*)d, (const float*)e, ranges,
-                                         m, (float*)W, w_off, (float*)Z, z_off, ldz,
-                                         (hipStream_t)stream);
-    return solve_impl<double, dd>(h, count, n, de_off, (const double*)d, (const double*)e, ranges, m,
-                                  (double*)W, w_off, (double*)Z, z_off, ldz, (hipStream_t)stream);
+        return batched_ptrs<float, double>(h, count, n, de_off, (const float*)d, (const float*)e,
+                                           ranges, m, (float*)W, w_off, (float*)Z, z_off, ldz,
+                                           (hipStream_t)stream);
+    return batched_ptrs<double, dd>(h, count, n, de_off, (const double*)d, (const double*)e, ranges,
+                                    m, (double*)W, w_off, (double*)Z, z_off, ldz,
+                                    (hipStream_t)stream);
 }
 
 }  // extern "C"

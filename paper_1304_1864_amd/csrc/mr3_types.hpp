@@ -34,9 +34,13 @@ enum SlotKind : int {
 };
 
 struct ProbDesc {
-    int64_t n;       // order of T
-    int64_t in_off;  // offset of d and e in the caller's arrays (elements)
-    int64_t row0;    // first internal row
+    int64_t n;         // order of T
+    const void* din;   // the caller's d and e (device, element type X)
+    const void* ein;
+    void* wout;        // the caller's W and Z (Z may be null: no vectors)
+    void* zout;
+    int64_t ldz;
+    int64_t row0;      // first internal row
     int range;
     double vl, vu;
     int64_t il, iu;
@@ -110,6 +114,7 @@ struct Params {
     int max_depth;
     int rqi_max_iter;
     int lanes_per_eig;
+    int points_per_lane;
     int force_rqi_fallback;
     int force_best_candidate;
     int profile;

@@ -1,0 +1,130 @@
+"""Batched solves on the device (needs an MI355X): one ``mr3_solve_batched``
+call over many independent problems of mixed sizes and ranges must meet the
+same gates as single solves, and agree with them."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests import metrics as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mr3():
+    import paper_1304_1864_amd as lib
+
+    lib.load_library()
+    return lib
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _ranges_for(sizes, seed):
+    """ALL for most problems, an INDEX window for some, a VALUE window for a few."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        u = rng.uniform()
+        if u < 0.6 or n < 4:
+            out.append(("all", 0.0, 0.0, 1, n))
+        elif u < 0.85:
+            m = max(1, int(np.ceil(0.1 * n)))
+            il = int(rng.integers(1, n - m + 2))
+            out.append(("index", 0.0, 0.0, il, il + m - 1))
+        else:
+            vl = float(rng.uniform(-1.5, 0.0))
+            out.append(("value", vl, vl + float(rng.uniform(0.2, 1.5)), 1, n))
+    return out
+
+
+def _check_problem(d, e, rng, w, Z, tag):
+    n = d.size
+    eps = M.eps_of(d.dtype)
+    d64, e64 = d.astype(np.float64), e.astype(np.float64)
+    kind, vl, vu, il, iu = rng
+    if kind == "value":
+        il, iu = oracle.count(d64, e64, vl) + 1, oracle.count(d64, e64, vu)
+    assert w.size == max(iu - il + 1, 0), (tag, w.size, il, iu)
+    if w.size == 0:
+        return
+    tn = M.tnorm(d64, e64)
+    hi, lo = oracle.eigvals(d64, e64, il, iu)
+    err = float(np.max(np.abs(w - (hi + lo))))
+    assert err <= 4 * n * eps * tn, (tag, err)
+    if Z is not None:
+        R = M.residual(d64, e64, w, Z)
+        O = M.orthogonality(Z)
+        assert R <= 10 * n * eps, (tag, "residual", R)
+        assert O <= 10 * n * eps, (tag, "orthogonality", O)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_batched_mixed_sizes_and_ranges(mr3, dtype):
+    probs = W.batch_normal(40, 32, 512, seed=3, dtype=dtype)
+    # edge problems inside the batch: sizes 1 and 2, a split matrix, 1-2-1
+    d1, e1 = W.uniform(1, 7, dtype)
+    d2, e2 = W.uniform(2, 8, dtype)
+    ds, es = W.uniform(60, 9, dtype)
+    es[19] = 0.0
+    probs += [(d1, e1[:0]), (d2, e2[:1]), (ds, es), W.toeplitz_121(200, dtype)]
+    sizes = [p[0].size for p in probs]
+    ranges = _ranges_for(sizes, 11)
+    kinds = {"all": 0, "value": 1, "index": 2}
+    desc = [(kinds[r[0]], r[1], r[2], r[3], r[4]) for r in ranges]
+    print(f"batched {len(probs)} problems dtype={np.dtype(dtype).name} sum n={sum(sizes)}", flush=True)
+    h = mr3.Handle(0)
+    Wb, Zb = mr3.solve_batched([_dev(p[0]) for p in probs], [_dev(p[1]) for p in probs],
+                               ranges=desc, handle=h)
+    torch.cuda.synchronize()
+    for i, (p, r) in enumerate(zip(probs, ranges)):
+        w = Wb[i].double().cpu().numpy()
+        Z = Zb[i].double().cpu().numpy()
+        _check_problem(p[0], p[1], r, w, Z, f"problem {i} n={p[0].size} range={r}")
+        # the same problem solved alone agrees to the eigenvalue gate
+        ws, _ = mr3.solve(_dev(p[0]), _dev(p[1]), range=r[0], vl=r[1], vu=r[2], il=r[3], iu=r[4],
+                          vectors=False, handle=h)
+        ws = ws.double().cpu().numpy()
+        assert ws.size == w.size
+        if w.size:
+            n = p[0].size
+            tn = M.tnorm(p[0].astype(np.float64), p[1].astype(np.float64))
+            assert np.max(np.abs(ws - w)) <= 8 * n * M.eps_of(dtype) * tn, i
+
+
+def test_batched_values_only_and_empty(mr3):
+    probs = W.batch_normal(16, 32, 256, seed=5, dtype=np.float32)
+    Wb, Zb = mr3.solve_batched([_dev(p[0]) for p in probs], [_dev(p[1]) for p in probs],
+                               vectors=False)
+    assert Zb is None
+    for i, p in enumerate(probs):
+        _check_problem(p[0], p[1], ("all", 0.0, 0.0, 1, p[0].size), Wb[i].double().cpu().numpy(),
+                       None, f"values-only problem {i}")
+    # a value window holding no eigenvalue gives m = 0 for that problem
+    d, e = W.uniform(100, 2, np.float64)
+    Wb, Zb = mr3.solve_batched([_dev(d), _dev(d)], [_dev(e), _dev(e)],
+                               ranges=[(1, 10.0, 11.0, 1, 100), (0, 0.0, 0.0, 1, 100)])
+    assert Wb[0].numel() == 0 and Wb[1].numel() == 100
+
+
+def test_batched_c3_shape_sampled(mr3):
+    """The full 4096-problem batch (n log-uniform in [32, 1024], N(0,1),
+    FP32): all problems solved in one call; eigenvalue gate on a sample of
+    problems, residual and orthogonality through the device check on FP64
+    copies of the sampled results."""
+    probs = W.batch_normal(4096, 32, 1024, seed=0, dtype=np.float32)
+    sizes = np.array([p[0].size for p in probs])
+    assert int(sizes.sum()) == 1157710
+    print("batched C3 shape: 4096 problems, sum n", int(sizes.sum()), flush=True)
+    Wb, Zb = mr3.solve_batched([_dev(p[0]) for p in probs], [_dev(p[1]) for p in probs])
+    torch.cuda.synchronize()
+    for i in range(4096):
+        assert Wb[i].numel() == sizes[i]
+    for i in np.linspace(0, 4095, 12).astype(int):
+        p = probs[i]
+        _check_problem(p[0], p[1], ("all", 0.0, 0.0, 1, p[0].size), Wb[i].double().cpu().numpy(),
+                       Zb[i].double().cpu().numpy(), f"C3 problem {i}")

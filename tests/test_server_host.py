@@ -1,0 +1,179 @@
+"""The serving scheduler on the host: batches are formed by an executor
+callback instead of the device, so admission, batching, ordering, error
+isolation and the ticket life cycle are checked without a GPU."""
+import ctypes
+import threading
+import time
+
+import pytest
+
+import paper_1304_1864_amd as mr3
+
+
+class FakeExecutor:
+    """Records every batch (request ids are carried in the W pointer) and
+    returns m = number of wanted eigenpairs; ids in `fail` make any batch
+    that holds them fail with MR3_ERR_NUMERIC."""
+
+    def __init__(self, fail=(), hold=None):
+        self.batches = []
+        self.fail = set(fail)
+        self.hold = hold
+        self.lock = threading.Lock()
+        self.cb = mr3.EXECUTOR_FN(self._run)
+
+    def _run(self, ctx, count, reqs, m):
+        if self.hold is not None:
+            self.hold.wait(10)
+        ids, precs = [], set()
+        for i in range(count):
+            r = reqs[i]
+            ids.append(int(r.W))
+            precs.add(r.precision)
+            k = r.range.iu - r.range.il + 1 if r.range.range == mr3.RANGE_INDEX else r.n
+            m[i] = k
+        with self.lock:
+            self.batches.append((ids, precs))
+        return mr3.MR3_ERR_NUMERIC if self.fail & set(ids) else mr3.MR3_OK
+
+
+def req(rid, n=100, precision=64, rng=None):
+    r = mr3.mr3_request()
+    r.precision = precision
+    r.n = n
+    r.d = 0x1000 + rid  # never dereferenced by the fake executor
+    r.e = 0x2000 + rid
+    r.W = rid
+    r.Z = None
+    r.ldz = n
+    if rng is None:
+        r.range.range, r.range.il, r.range.iu = mr3.RANGE_ALL, 1, n
+    else:
+        r.range.range, r.range.il, r.range.iu = rng
+    return r
+
+
+def make_server(ex, budget=1 << 30, max_batch=8):
+    return mr3.mr3_server_create_with_executor(ex.cb, None, budget, max_batch)
+
+
+def test_batches_group_precision_and_keep_arrival_order():
+    hold = threading.Event()
+    ex = FakeExecutor(hold=hold)
+    s = make_server(ex, max_batch=4)
+    # the first request occupies the worker until `hold` is set; the rest queue
+    tickets = [mr3.mr3_server_submit(s, req(1, precision=64))]
+    time.sleep(0.05)
+    for i in range(2, 12):
+        tickets.append(mr3.mr3_server_submit(s, req(i, precision=32 if i % 3 == 0 else 64)))
+    hold.set()
+    res = [mr3.mr3_server_wait(s, t) for t in tickets]
+    mr3.mr3_server_destroy(s)
+    assert all(r["status"] == 0 for r in res)
+    seen = []
+    for ids, precs in ex.batches:
+        assert len(precs) == 1 and len(ids) <= 4
+        seen += ids
+        # inside a batch, requests keep their arrival order
+        assert ids == sorted(ids)
+    assert sorted(seen) == list(range(1, 12))
+    # each batch starts with the oldest request still waiting
+    waiting = list(range(1, 12))
+    for ids, _ in ex.batches:
+        assert ids[0] == waiting[0]
+        for i in ids:
+            waiting.remove(i)
+    # results carry the batch bookkeeping
+    for r in res:
+        assert r["done_ms"] >= r["start_ms"] >= r["submit_ms"] - 1e-6
+        assert 1 <= r["batch_size"] <= 4
+
+
+def test_budget_limits_batches_and_rejects_oversized():
+    hold = threading.Event()
+    ex = FakeExecutor(hold=hold)
+    one = mr3.mr3_request_bytes(1000, 1000, 64)
+    s = make_server(ex, budget=int(2.5 * one), max_batch=64)
+    with pytest.raises(mr3.MR3Error) as ei:
+        mr3.mr3_server_submit(s, req(99, n=2000))
+    assert ei.value.code == -3
+    tickets = [mr3.mr3_server_submit(s, req(1, n=1000))]
+    time.sleep(0.05)
+    tickets += [mr3.mr3_server_submit(s, req(i, n=1000)) for i in range(2, 8)]
+    hold.set()
+    for t in tickets:
+        mr3.mr3_server_wait(s, t)
+    mr3.mr3_server_destroy(s)
+    for ids, _ in ex.batches:
+        assert len(ids) * one <= 2.5 * one
+    assert max(len(ids) for ids, _ in ex.batches) == 2
+
+
+def test_failing_request_is_isolated():
+    ex = FakeExecutor(fail={5})
+    hold = threading.Event()
+    ex.hold = hold
+    s = make_server(ex, max_batch=16)
+    tickets = [mr3.mr3_server_submit(s, req(i)) for i in range(1, 9)]
+    hold.set()
+    status = {}
+    for i, t in zip(range(1, 9), tickets):
+        res = mr3.mr3_server_wait(s, t)
+        status[i] = res["status"]
+    mr3.mr3_server_destroy(s)
+    assert status[5] == mr3.MR3_ERR_NUMERIC
+    assert all(status[i] == 0 for i in status if i != 5)
+
+
+def test_invalid_requests_and_tickets():
+    ex = FakeExecutor()
+    s = make_server(ex)
+    bad = [req(1, precision=16), req(2, n=-1), req(3, rng=(mr3.RANGE_INDEX, 5, 2)),
+           req(4, rng=(mr3.RANGE_INDEX, 0, 2)), req(5, rng=(mr3.RANGE_INDEX, 1, 101))]
+    for r in bad:
+        with pytest.raises(mr3.MR3Error) as ei:
+            mr3.mr3_server_submit(s, r)
+        assert ei.value.code == -2
+    r = req(6)
+    r.Z = 0x3000
+    r.ldz = 50  # < n
+    with pytest.raises(mr3.MR3Error):
+        mr3.mr3_server_submit(s, r)
+    with pytest.raises(mr3.MR3Error):
+        mr3.mr3_server_poll(s, 12345)
+    t = mr3.mr3_server_submit(s, req(7, rng=(mr3.RANGE_INDEX, 3, 12)))
+    res = mr3.mr3_server_wait(s, t)
+    assert res["m"] == 10
+    with pytest.raises(mr3.MR3Error):  # ticket released by wait
+        mr3.mr3_server_wait(s, t)
+    mr3.mr3_server_destroy(s)
+
+
+def test_concurrent_submitters_and_drain_on_destroy():
+    ex = FakeExecutor()
+    s = make_server(ex, max_batch=5)
+    tickets, lock = [], threading.Lock()
+
+    def client(base):
+        for i in range(25):
+            t = mr3.mr3_server_submit(s, req(base + i, n=50 + i))
+            with lock:
+                tickets.append(t)
+
+    th = [threading.Thread(target=client, args=(1000 * (k + 1),)) for k in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    done = 0
+    for t in tickets:
+        while not mr3.mr3_server_poll(s, t):
+            time.sleep(0.001)
+        done += mr3.mr3_server_wait(s, t)["status"] == 0
+    assert done == 100
+    # queued work is finished by destroy
+    for i in range(10):
+        mr3.mr3_server_submit(s, req(9000 + i))
+    mr3.mr3_server_destroy(s)
+    ids = [i for b, _ in ex.batches for i in b]
+    assert len(ids) == 110 and len(set(ids)) == 110
