@@ -36,6 +36,24 @@ FLOPS_TWIST = 7.0
 FLOPS_RQI = {"dd": 64.0, "f64": 8.0}
 
 
+def profiled_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel source has changed since it was taken."""
+    import hashlib
+
+    prof = os.path.join(ROOT, "profiles", "counters_prescribed_n20000_fp64.md")
+    src = os.path.join(ROOT, "paper_1304_1864_amd", "csrc", "mr3_kernels.hip")
+    if not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(prof):
+        f = line.split()
+        if len(f) == 4 and f[0] == "traffic" and f[1] == kernel:
+            kv = dict(x.split("=", 1) for x in f[2:])
+            return float(kv["bytes_per_launch"]) if kv["source_sha256"] == sha else None
+    return None
+
+
 def build_workload(n: int, seed: int):
     import workloads as W
 
@@ -226,7 +244,20 @@ def main():
     ap.add_argument("--no-subset", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes three times (calibrates "
+                         "hardware byte counters against a known traffic) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+
+        x = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 8, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the solver runs on a single device)", file=sys.stderr)
@@ -288,7 +319,7 @@ def main():
         "peak": FP64_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-        "traffic": None,
+        "traffic": profiled_traffic("k_rqi<dd>" if dom == "rqi" else "k_bisect<2,2>"),
         "launches": int(stage_launch[idx[dom]]),
         "avg_launch_ms": round(dom_ms / max(stage_launch[idx[dom]], 1), 3),
     }
