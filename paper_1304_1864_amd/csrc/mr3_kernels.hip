@@ -58,6 +58,9 @@ namespace mr3 {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int dexp(double x) { return __builtin_amdgcn_frexp_exp(x); }
 
+// rows per LDS window of the staged sweeps = threads per workgroup
+constexpr int STAGE_ROWS = 256;
+
 __device__ __forceinline__ int sign_differs(double c, double b) {
     return (int)(((unsigned)__double2hiint(c) ^ (unsigned)__double2hiint(b)) >> 31);
 }
@@ -491,6 +494,7 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
        Node* __restrict__ nodes, Slot* __restrict__ slots, int* __restrict__ status) {
     __shared__ double sx[256];
     __shared__ int sc[256];
+    __shared__ double2 wT[2][STAGE_ROWS];
     __shared__ double s_lo, s_hi, s_mu;
     __shared__ int s_ok, s_right;
     const int bidx = blockIdx.x;
@@ -502,10 +506,58 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
     const double* te = Te + blk.row0;
     const double gl = blk.gl, gu = blk.gu;
     const double spd = fmax(gu - gl, 1e-300);
+    // The block's rows (d_i, e_{i-1}^2) stream through an LDS window shared by
+    // the workgroup, so the sequential loops below read LDS, not memory.
+    // Every thread calls these helpers (they synchronise the workgroup).
+    auto load_row = [&](int64_t i) -> double2 {
+        if (i >= n) return make_double2(0.0, 0.0);
+        const double ei = (i > 0) ? te[i - 1] : 0.0;
+        return make_double2(td[i], ei * ei);
+    };
+    // Sturm count of T - x I (division free: leading minors p_i change sign
+    // once per negative pivot), for threads with on == true
+    auto tcount = [&](double x, bool on) -> int {
+        double pm = 0.0, p = 1.0;
+        int neg = 0;
+        wT[0][t] = load_row(t);
+        __syncthreads();
+        for (int64_t c0 = 0; c0 < n; c0 += STAGE_ROWS) {
+            const int cur = (int)((c0 / STAGE_ROWS) & 1);
+            const double2 nx = load_row(c0 + STAGE_ROWS + t);
+            const int cnt = (int)min<int64_t>(STAGE_ROWS, n - c0);
+            if (on) {
+                auto row = [&](const double2& r, int i) {
+                    const double pn = __fma_rn(r.x - x, p, -r.y * pm);
+                    neg += sign_differs(pn, p);
+                    pm = p;
+                    p = pn;
+                    if ((i & 3) == 3) {
+                        const int em = max(dexp(p), dexp(pm));
+                        p = __builtin_ldexp(p, -em);
+                        pm = __builtin_ldexp(pm, -em);
+                    }
+                };
+                int i = 0;
+                for (; i + 8 <= cnt; i += 8) {
+                    double2 r[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) r[u] = wT[cur][i + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) row(r[u], i + u);
+                }
+                for (; i < cnt; ++i) row(wT[cur][i], i);
+            }
+            wT[cur ^ 1][t] = nx;
+            __syncthreads();
+        }
+        return neg;
+    };
     // which end: all eigenvalues -> the more populated end; a subset -> the
     // end nearer to the requested indices
-    if (blk.il == 1 && blk.iu == n) {
-        if (t < 2) sc[t] = negcount_T(td, te, n, t == 0 ? gl + 0.25 * spd : gu - 0.25 * spd);
+    {
+        const bool all = blk.il == 1 && blk.iu == n;
+        const int c = tcount(t == 0 ? gl + 0.25 * spd : gu - 0.25 * spd, all && t < 2);
+        if (t < 2) sc[t] = c;
     }
     __syncthreads();
     if (t == 0) {
@@ -524,7 +576,8 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
         const double lo = s_lo, hi = s_hi;
         const double x = lo + (hi - lo) * ((double)(t + 1) / 256.0);
         sx[t] = x;
-        sc[t] = (t < 255) ? negcount_T(td, te, n, x) : (int)n;
+        const int c = tcount(x, t < 255);
+        sc[t] = (t < 255) ? c : (int)n;
         __syncthreads();
         if (t == 0) {
             int f = 255;
@@ -536,55 +589,48 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
         __syncthreads();
     }
     // shift and factor T - mu I = L D L^T in binary64 (continuant form:
-    // q_i = (a_i - mu) q_{i-1} - e_{i-1}^2 q_{i-2},  d_i = q_i / q_{i-1})
+    // q_i = (a_i - mu) q_{i-1} - e_{i-1}^2 q_{i-2},  d_i = q_i / q_{i-1}) by
+    // thread 0, rows from the LDS window
     double delta = fmax(2.0 * (s_hi - s_lo), 8.0 * (double)n * 1.1102230246251565e-16);
     for (int attempt = 0; attempt < 40; ++attempt) {
-        if (t == 0) {
-            const double mu = right ? s_hi + delta : s_lo - delta;
-            s_mu = mu;
-            int ok = 1;
-            double qm = 1.0, q = td[0] - mu;
-            d64[blk.row0] = q;
-            ok &= right ? (q < 0.0) : (q > 0.0);
-            // rows in blocks of 8, the next block's loads issued first (the
-            // arrays have guard rows behind them)
-            constexpr int U = 8;
-            double dn[U], en[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                dn[u] = td[1 + u];
-                en[u] = te[u];
-            }
-            for (int64_t i0 = 1; i0 < n; i0 += U) {
-                double dc[U], ec[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    dc[u] = dn[u];
-                    ec[u] = en[u];
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    dn[u] = td[i0 + U + u];
-                    en[u] = te[i0 + U + u - 1];
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t i = i0 + u;
-                    if (i < n) {
-                        const double qn = __fma_rn(dc[u] - mu, q, -(ec[u] * ec[u]) * qm);
-                        const double di = qn / q;
-                        d64[blk.row0 + i] = di;
-                        ok &= right ? (di < 0.0) : (di > 0.0);
-                        qm = q;
-                        q = qn;
-                        if ((u & 3) == 3) {
-                            const int em = max(dexp(q), dexp(qm));
-                            q = __builtin_ldexp(q, -em);
-                            qm = __builtin_ldexp(qm, -em);
-                        }
+        const double mu = right ? s_hi + delta : s_lo - delta;
+        int ok = 1;
+        double qm = 1.0, q = 1.0;
+        wT[0][t] = load_row(t);
+        __syncthreads();
+        for (int64_t c0 = 0; c0 < n; c0 += STAGE_ROWS) {
+            const int cur = (int)((c0 / STAGE_ROWS) & 1);
+            const double2 nx = load_row(c0 + STAGE_ROWS + t);
+            const int cnt = (int)min<int64_t>(STAGE_ROWS, n - c0);
+            if (t == 0) {
+                auto row = [&](const double2& r, int i) {
+                    const double qn = __fma_rn(r.x - mu, q, -r.y * qm);
+                    const double di = qn / q;
+                    d64[blk.row0 + c0 + i] = di;
+                    ok &= right ? (di < 0.0) : (di > 0.0);
+                    qm = q;
+                    q = qn;
+                    if ((i & 3) == 3) {
+                        const int em = max(dexp(q), dexp(qm));
+                        q = __builtin_ldexp(q, -em);
+                        qm = __builtin_ldexp(qm, -em);
                     }
+                };
+                int i = 0;
+                for (; i + 8 <= cnt; i += 8) {
+                    double2 r[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) r[u] = wT[cur][i + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) row(r[u], i + u);
                 }
+                for (; i < cnt; ++i) row(wT[cur][i], i);
             }
+            wT[cur ^ 1][t] = nx;
+            __syncthreads();
+        }
+        if (t == 0) {
+            s_mu = mu;
             s_ok = ok;
         }
         __syncthreads();
@@ -842,68 +888,305 @@ k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slo
 }
 
 // ---------------------------------------------------------------------------
+// a3 with the representation staged through LDS.  Every workgroup serves
+// intervals of one node; the node's rows stream through a double-buffered LDS
+// window (one coalesced row load per thread per window, issued a whole window
+// ahead), and all counts of the workgroup read each row from LDS as a
+// broadcast.  The sequential recurrences then never wait on memory.
+// ---------------------------------------------------------------------------
+struct BisWG {
+    int64_t begin;  // first position in the slot list
+    int count;      // intervals served (<= 256 / L)
+    int node;
+};
+
+
+// Sturm counts at P shifts for every thread of the workgroup.  All threads
+// call it (it synchronises the workgroup); threads with on == false only load.
+template <int P>
+__device__ __forceinline__ void staged_counts(const double* __restrict__ D,
+                                              const double* __restrict__ LL, int64_t n,
+                                              const double (&x)[P], int (&neg)[P], bool on,
+                                              double2 (*win)[STAGE_ROWS]) {
+    const int t = threadIdx.x;
+    double a[P], b[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        a[p] = -x[p];
+        b[p] = 1.0;
+        neg[p] = 0;
+    }
+    if (t < n) win[0][t] = make_double2(D[t], LL[t]);
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < n; c0 += STAGE_ROWS) {
+        const int cur = (int)((c0 / STAGE_ROWS) & 1);
+        // next window: loaded now, stored after this window is processed
+        const int64_t nr = c0 + STAGE_ROWS + t;
+        double2 nx = make_double2(0.0, 0.0);
+        if (nr < n) nx = make_double2(D[nr], LL[nr]);
+        const int64_t left = n - c0;
+        if (on) {
+            if (left >= STAGE_ROWS) {
+                for (int i = 0; i < STAGE_ROWS; i += 8) {
+                    double2 r[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) r[u] = win[cur][i + u];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            const double c = __fma_rn(r[u].x, b[p], a[p]);
+                            neg[p] += sign_differs(c, b[p]);
+                            a[p] = __fma_rn(-x[p], c, r[u].y * a[p]);
+                            b[p] = c;
+                        }
+                        if ((u & 3) == 3) {
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const int em = max(dexp(a[p]), dexp(b[p]));
+                                a[p] = __builtin_ldexp(a[p], -em);
+                                b[p] = __builtin_ldexp(b[p], -em);
+                            }
+                        }
+                    }
+                }
+            } else {
+                for (int i = 0; i < (int)left; ++i) {
+                    const double2 r = win[cur][i];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const double c = __fma_rn(r.x, b[p], a[p]);
+                        neg[p] += sign_differs(c, b[p]);
+                        a[p] = __fma_rn(-x[p], c, r.y * a[p]);
+                        b[p] = c;
+                    }
+                    if ((i & 3) == 3) {
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            const int em = max(dexp(a[p]), dexp(b[p]));
+                            a[p] = __builtin_ldexp(a[p], -em);
+                            b[p] = __builtin_ldexp(b[p], -em);
+                        }
+                    }
+                }
+            }
+        }
+        win[cur ^ 1][t] = nx;
+        __syncthreads();
+    }
+}
+
+template <int L, int PTS>
+__global__ void __launch_bounds__(256)
+k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
+                Slot* __restrict__ slots, const Node* __restrict__ nodes,
+                const Block* __restrict__ blocks, const double* __restrict__ d64,
+                const double* __restrict__ lld64, double rtol, double widen,
+                double* __restrict__ work) {
+    __shared__ double2 win[2][STAGE_ROWS];
+    const BisWG w = wgs[blockIdx.x];
+    const int g = threadIdx.x / L;
+    const int q = threadIdx.x % L;
+    const bool active = g < w.count;
+    const Node nd = nodes[w.node];
+    const int64_t n = blocks[nd.block].n;
+    const double* D = d64 + nd.rep;
+    const double* LL = lld64 + nd.rep;
+    int64_t s = 0, j = 0;
+    double lo = 0.0, hi = 0.0;
+    if (active) {
+        s = list[w.begin + g];
+        const Slot sl = slots[s];
+        j = sl.idx;
+        lo = sl.lo;
+        hi = sl.hi;
+    }
+    const int lane = threadIdx.x & 63;
+    const int gbase = lane - q;
+    // make sure the bracket holds: count(lo) <= j-1 < count(hi)
+    bool fix = active;
+    for (int it = 0; it < 64; ++it) {
+        if (!__syncthreads_or(fix)) break;
+        const double xs2[2] = {lo, hi};
+        int c2[2];
+        staged_counts<2>(D, LL, n, xs2, c2, fix && q == 0, win);
+        const int cl0 = __shfl(c2[0], gbase, 64);
+        const int ch0 = __shfl(c2[1], gbase, 64);
+        const bool okb = !fix || (cl0 <= j - 1 && ch0 >= j);
+        if (fix && !okb) {
+            const double wd = fmax(hi - lo, fmax(fabs(lo), fabs(hi)) * 1e-15) + 1e-300;
+            if (cl0 > j - 1) lo -= wd;
+            if (ch0 < j) hi += wd;
+        }
+        fix = fix && !okb;
+    }
+    const double lo0 = lo, hi0 = hi;
+    bool busy = active;
+    for (int it = 0; it < 400; ++it) {
+        if (busy) {
+            const double wd = hi - lo;
+            const double scale = fmax(fabs(lo), fabs(hi));
+            if (wd <= rtol * scale || wd <= 1e-300 || !(wd > 0.0)) busy = false;
+        }
+        if (!__syncthreads_or(busy)) break;
+        constexpr int NP = L * PTS;
+        const double h = (hi - lo) / (double)(NP + 1);
+        double xs[PTS];
+        int cs[PTS];
+#pragma unroll
+        for (int p = 0; p < PTS; ++p) xs[p] = lo + h * (double)(q * PTS + p + 1);
+        staged_counts<PTS>(D, LL, n, xs, cs, busy, win);
+        int fp = PTS;
+#pragma unroll
+        for (int p = PTS - 1; p >= 0; --p)
+            if (cs[p] >= j) fp = p;
+        const unsigned long long m = __ballot(busy && fp < PTS);
+        const unsigned long long gm = (m >> gbase) & ((L == 64) ? ~0ull : ((1ull << L) - 1ull));
+        const int fq = gm ? __builtin_ctzll(gm) : L;
+        const int fpo = __shfl(fp, gbase + (fq < L ? fq : 0), 64);
+        if (busy) {
+            const int f = (fq < L) ? fq * PTS + fpo : NP;
+            const double nlo = (f > 0) ? lo + h * (double)f : lo;
+            const double nhi = (f < NP) ? lo + h * (double)(f + 1) : hi;
+            if (nlo == lo && nhi == hi) busy = false;
+            lo = nlo;
+            hi = nhi;
+        }
+    }
+    if (active && q == 0) {
+        const double bits = log2(fmax((lo0 - hi0 == 0.0) ? 1.0 : (hi0 - lo0) / fmax(hi - lo, 1e-300), 1.0));
+        atomicAdd(&work[0], bits * (double)n);
+        const double wd = widen * (double)n * fmax(fabs(lo), fabs(hi));
+        slots[s].lo = lo - wd;
+        slots[s].hi = hi + wd;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Verification of binary64-copy intervals in working precision y (Sec. 3.2:
 // results of x-bit eigenvalue computations may be verified or refined in y).
 // Two lanes per slot count the y representation at lo and hi; a bracket that
 // does not hold for the y representation is widened until it does and then
 // refined by bisection in y to relative width rtol.
 // ---------------------------------------------------------------------------
+// Sturm count in y at x for threads with on == true; the node's rows stream
+// through an LDS window filled by the 64 threads of the workgroup (all call).
+template <class Y>
+__device__ int staged_count_y(const Y* __restrict__ D, const Y* __restrict__ LL, int64_t n, Y x,
+                              bool on, Y (*wd)[STAGE_ROWS], Y (*wl)[STAGE_ROWS]) {
+    constexpr int PER = STAGE_ROWS / 64;
+    const int t = threadIdx.x;
+    Y a = neg(x), b = y_from(1.0, Y());
+    int negc = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = t + 64 * k;
+        if (i < n) {
+            wd[0][t + 64 * k] = D[i];
+            wl[0][t + 64 * k] = LL[i];
+        }
+    }
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < n; c0 += STAGE_ROWS) {
+        const int cur = (int)((c0 / STAGE_ROWS) & 1);
+        Y nd[PER], nl[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t i = c0 + STAGE_ROWS + t + 64 * k;
+            nd[k] = (i < n) ? D[i] : y_from(0.0, Y());
+            nl[k] = (i < n) ? LL[i] : y_from(0.0, Y());
+        }
+        if (on) {
+            const int cnt = (int)min<int64_t>(STAGE_ROWS, n - c0);
+            auto row = [&](const Y& dv, const Y& lv, int i) {
+                const Y c = mul_add(dv, b, a);
+                negc += sign_differs(hi_of(c), hi_of(b));
+                a = sub(mul(lv, a), mul(x, c));
+                b = c;
+                if ((i & 3) == 3) {
+                    const int em = max(y_exp(a), y_exp(b));
+                    a = y_ldexp(a, -em);
+                    b = y_ldexp(b, -em);
+                }
+            };
+            int i = 0;
+            for (; i + 8 <= cnt; i += 8) {
+                Y dv[8], lv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    dv[u] = wd[cur][i + u];
+                    lv[u] = wl[cur][i + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) row(dv[u], lv[u], i + u);
+            }
+            for (; i < cnt; ++i) row(wd[cur][i], wl[cur][i], i);
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            wd[cur ^ 1][t + 64 * k] = nd[k];
+            wl[cur ^ 1][t + 64 * k] = nl[k];
+        }
+        __syncthreads();
+    }
+    return negc;
+}
+
+// One workgroup of 64 threads serves up to 32 slots of one node (wgs[]); two
+// lanes per slot count at lo and at hi.
 template <class Y>
 __global__ void __launch_bounds__(64)
-k_verify(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slots,
+k_verify(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list, Slot* __restrict__ slots,
          const Node* __restrict__ nodes, const Block* __restrict__ blocks,
          const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld, double rtol,
          unsigned long long* __restrict__ repaired) {
+    __shared__ Y wd[2][STAGE_ROWS], wl[2][STAGE_ROWS];
+    const BisWG w = wgs[blockIdx.x];
     const int lane = threadIdx.x;
     const int pair = lane >> 1;
     const bool side = lane & 1;  // 0: count at lo, 1: count at hi
-    const int64_t idx = (int64_t)blockIdx.x * 32 + pair;
-    const bool active = idx < count;
-    int64_t s = 0, n = 0, j = 0;
-    const Y* D = rep_d;
-    const Y* LL = rep_lld;
+    const bool active = pair < w.count;
+    const Node nd = nodes[w.node];
+    const int64_t n = blocks[nd.block].n;
+    const Y* D = rep_d + nd.rep;
+    const Y* LL = rep_lld + nd.rep;
+    int64_t s = 0, j = 0;
     double lo = 0, hi = 0;
     if (active) {
-        s = list[idx];
+        s = list[w.begin + pair];
         const Slot sl = slots[s];
-        const Node nd = nodes[sl.node];
-        n = blocks[nd.block].n;
-        D = rep_d + nd.rep;
-        LL = rep_lld + nd.rep;
         j = sl.idx;
         lo = sl.lo;
         hi = sl.hi;
     }
     bool bad = false, fix = active;
     for (int it = 0; it < 80; ++it) {
-        int c = 0;
-        if (fix) c = negcount_y<Y>(D, LL, n, y_from(side ? hi : lo, Y()));
+        if (!__syncthreads_or(fix)) break;
+        const int c = staged_count_y<Y>(D, LL, n, y_from(side ? hi : lo, Y()), fix, wd, wl);
         const int co = __shfl_xor(c, 1, 64);
         const int clo = side ? co : c, chi = side ? c : co;
         if (fix) {
             const bool ok = (clo <= j - 1) && (chi >= j);
             if (!ok) {
                 bad = true;
-                const double w = fmax(hi - lo, fmax(fabs(lo), fabs(hi)) * 1e-14) + 1e-300;
-                if (clo > j - 1) lo -= w;
-                if (chi < j) hi += w;
+                const double wdt = fmax(hi - lo, fmax(fabs(lo), fabs(hi)) * 1e-14) + 1e-300;
+                if (clo > j - 1) lo -= wdt;
+                if (chi < j) hi += wdt;
             }
             fix = !ok;
         }
-        if (!__any(fix)) break;
     }
     // refine repaired brackets by bisection in y (two points per step)
     bool busy = bad;
     for (int it = 0; it < 200; ++it) {
         if (busy) {
-            const double w = hi - lo;
-            if (!(w > rtol * fmax(fabs(lo), fabs(hi))) || w <= 1e-300) busy = false;
+            const double wdt = hi - lo;
+            if (!(wdt > rtol * fmax(fabs(lo), fabs(hi))) || wdt <= 1e-300) busy = false;
         }
-        if (!__any(busy)) break;
+        if (!__syncthreads_or(busy)) break;
         const double h3 = (hi - lo) / 3.0;
         const double x = side ? lo + 2.0 * h3 : lo + h3;
-        int c = 0;
-        if (busy) c = negcount_y<Y>(D, LL, n, y_from(x, Y()));
+        const int c = staged_count_y<Y>(D, LL, n, y_from(x, Y()), busy, wd, wl);
         const int co = __shfl_xor(c, 1, 64);
         if (busy) {
             const int c1 = side ? co : c, c2 = side ? c : co;
@@ -1557,7 +1840,7 @@ struct ChildJob {
     int64_t tmp;      // first row of the scratch rows
     double tau;       // chosen shift (parent frame), written by k_child_select
     int best;         // 1 if no candidate passed the growth test
-    int pad;
+    int strict;       // 1 if the growth stayed within k_elg * spdiam
 };
 
 __global__ void __launch_bounds__(64)
@@ -1583,20 +1866,52 @@ k_child_select(ChildJob* __restrict__ jobs, int64_t njobs, const Slot* __restric
     const double gapo = left ? sp.lgap : sq.rgap;
     bool valid = !(gapo >= 0.0 && delta > 0.5 * gapo);
     const double tau = left ? sp.lo - delta : sq.hi + delta;
-    // stationary transform at tau with element growth and inertia
+    // stationary transform at tau with element growth max |d+_i| = |c_i / b_i|
+    // (approximate reciprocal: the growth only ranks candidates) and inertia;
+    // the parent's rows stream through an LDS window filled by the workgroup
+    __shared__ double2 win[2][STAGE_ROWS];
     double a = -tau, b = 1.0, gmax = 0.0;
     int negc = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        const double c = __fma_rn(D[i], b, a);
-        negc += sign_differs(c, b);
-        gmax = fmax(gmax, fabs(c / b));
-        a = __fma_rn(-tau, c, LL[i] * a);
-        b = c;
-        if ((i & 3) == 3) {
-            const int em = max(dexp(a), dexp(b));
-            a = __builtin_ldexp(a, -em);
-            b = __builtin_ldexp(b, -em);
+    constexpr int PER = STAGE_ROWS / 64;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = lane + 64 * k;
+        if (i < n) win[0][lane + 64 * k] = make_double2(D[i], LL[i]);
+    }
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < n; c0 += STAGE_ROWS) {
+        const int cur = (int)((c0 / STAGE_ROWS) & 1);
+        double2 nx[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t i = c0 + STAGE_ROWS + lane + 64 * k;
+            nx[k] = (i < n) ? make_double2(D[i], LL[i]) : make_double2(0.0, 0.0);
         }
+        const int cnt = (int)min<int64_t>(STAGE_ROWS, n - c0);
+        auto row = [&](const double2& r, int i) {
+            const double c = __fma_rn(r.x, b, a);
+            negc += sign_differs(c, b);
+            gmax = fmax(gmax, fabs(c) * __builtin_amdgcn_rcp(fabs(b)));
+            a = __fma_rn(-tau, c, r.y * a);
+            b = c;
+            if ((i & 3) == 3) {
+                const int em = max(dexp(a), dexp(b));
+                a = __builtin_ldexp(a, -em);
+                b = __builtin_ldexp(b, -em);
+            }
+        };
+        int i = 0;
+        for (; i + 8 <= cnt; i += 8) {
+            double2 r[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) r[u] = win[cur][i + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) row(r[u], i + u);
+        }
+        for (; i < cnt; ++i) row(win[cur][i], i);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) win[cur ^ 1][lane + 64 * k] = nx[k];
+        __syncthreads();
     }
     const int64_t want = left ? sp.idx - 1 : sq.idx;
     valid = valid && (negc == want) && isfinite(gmax);
@@ -1629,6 +1944,7 @@ k_child_select(ChildJob* __restrict__ jobs, int64_t njobs, const Slot* __restric
         }
         jobs[jb].tau = (pick >= 0) ? st[pick] : sp.lo - delta0;
         jobs[jb].best = (pick >= 0) ? best : 2;
+        jobs[jb].strict = (pick >= 0 && !best && sg[pick] <= prm.k_elg * nd.spdiam) ? 1 : 0;
     }
 }
 
@@ -1652,25 +1968,68 @@ k_child_rep(const ChildJob* __restrict__ jobs, int64_t njobs, Slot* __restrict__
     Y* C = tmpc + job.tmp;
     int* CE = tmpe + job.tmp;
     const Y tau = y_from(job.tau, Y());
-    if (t == 0) {
-        // sequential stationary transform in y: c_i = d+_i b_i
+    {
+        // sequential stationary transform in y by thread 0: c_i = d+_i b_i;
+        // the parent's rows stream through an LDS window filled by the
+        // workgroup
+        __shared__ Y wd[2][STAGE_ROWS], wl[2][STAGE_ROWS];
+        constexpr int PER = STAGE_ROWS / 64;
         Y a = neg(tau), b = y_from(1.0, Y());
         int eb = 0;
-        for (int64_t i = 0; i < n; ++i) {
-            const Y c = mul_add(D[i], b, a);
-            C[i] = c;
-            CE[i] = eb;
-            a = sub(mul(LL[i], a), mul(tau, c));
-            b = c;
-            if ((i & 3) == 3) {
-                const int em = max(y_exp(a), y_exp(b));
-                a = y_ldexp(a, -em);
-                b = y_ldexp(b, -em);
-                eb += em;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t i = t + 64 * k;
+            if (i < n) {
+                wd[0][t + 64 * k] = D[i];
+                wl[0][t + 64 * k] = LL[i];
             }
         }
+        __syncthreads();
+        for (int64_t c0 = 0; c0 < n; c0 += STAGE_ROWS) {
+            const int cur = (int)((c0 / STAGE_ROWS) & 1);
+            Y nd[PER], nl[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int64_t i = c0 + STAGE_ROWS + t + 64 * k;
+                nd[k] = (i < n) ? D[i] : y_from(0.0, Y());
+                nl[k] = (i < n) ? LL[i] : y_from(0.0, Y());
+            }
+            if (t == 0) {
+                const int cnt = (int)min<int64_t>(STAGE_ROWS, n - c0);
+                auto row = [&](const Y& dv, const Y& lv, int i) {
+                    const Y c = mul_add(dv, b, a);
+                    C[c0 + i] = c;
+                    CE[c0 + i] = eb;
+                    a = sub(mul(lv, a), mul(tau, c));
+                    b = c;
+                    if ((i & 3) == 3) {
+                        const int em = max(y_exp(a), y_exp(b));
+                        a = y_ldexp(a, -em);
+                        b = y_ldexp(b, -em);
+                        eb += em;
+                    }
+                };
+                int i = 0;
+                for (; i + 8 <= cnt; i += 8) {  // LDS reads of a block issued first
+                    Y dv[8], lv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        dv[u] = wd[cur][i + u];
+                        lv[u] = wl[cur][i + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) row(dv[u], lv[u], i + u);
+                }
+                for (; i < cnt; ++i) row(wd[cur][i], wl[cur][i], i);
+            }
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                wd[cur ^ 1][t + 64 * k] = nd[k];
+                wl[cur ^ 1][t + 64 * k] = nl[k];
+            }
+            __syncthreads();
+        }
     }
-    __syncthreads();
     Y* cd = rep_d + job.rep;
     Y* cl = rep_lld + job.rep;
     for (int64_t i = t; i < n; i += blockDim.x) {

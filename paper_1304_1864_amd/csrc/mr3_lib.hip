@@ -142,7 +142,7 @@ enum BufId {
     B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BLOCKS, B_SLOTS, B_NODES, B_REPD, B_REPL, B_REPE,
     B_D64, B_L64, B_P, B_PE, B_Q, B_QE, B_LIST, B_LIST2, B_CNT, B_TILEOFF, B_TILES, B_RES,
     B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_M, B_BAD, B_COUNTERS,
-    B_BOFF, B_CREC, B_CHECK, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
+    B_BOFF, B_CREC, B_CHECK, B_BWG, B_VLIST, B_VWG, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
 };
 
 // singleton work of tree level d runs on the handle's side stream with the
@@ -319,19 +319,64 @@ static void launch_bisect(BisectShape sh, const int64_t* list, int64_t count, Sl
                        list, count, slots, nodes, blocks, d64, l64, rtol, widen, work);
 }
 
-// lanes per eigenvalue and points per lane.  Measured on the device: the
-// counts are latency bound, so L doubles until ~32K lanes are busy (at most
-// 64 lanes, one wave, per eigenvalue); two independent chains per lane pay
-// off while L is small, one chain is the least work once lanes are plentiful.
+static void launch_bisect_staged(BisectShape sh, const BisWG* wgs, int64_t nwg, const int64_t* list,
+                                 Slot* slots, const Node* nodes, const Block* blocks,
+                                 const double* d64, const double* l64, double rtol, double widen,
+                                 double* work, hipStream_t st) {
+    if (nwg <= 0) return;
+#define MR3_BST(LL, PP)                                                                        \
+    if (sh.L == LL && sh.P == PP) {                                                            \
+        hipLaunchKernelGGL((k_bisect_staged<LL, PP>), dim3((unsigned)nwg), dim3(256), 0, st,   \
+                           wgs, list, slots, nodes, blocks, d64, l64, rtol, widen, work);      \
+        return;                                                                                \
+    }
+    MR3_BST(1, 1) MR3_BST(1, 2) MR3_BST(1, 4)
+    MR3_BST(2, 1) MR3_BST(2, 2) MR3_BST(2, 4)
+    MR3_BST(4, 1) MR3_BST(4, 2) MR3_BST(4, 4)
+    MR3_BST(8, 1) MR3_BST(8, 2) MR3_BST(8, 4)
+    MR3_BST(16, 1) MR3_BST(16, 2) MR3_BST(16, 4)
+    MR3_BST(32, 1) MR3_BST(32, 2) MR3_BST(32, 4)
+    MR3_BST(64, 1) MR3_BST(64, 2) MR3_BST(64, 4)
+#undef MR3_BST
+}
+
+// nodes of at least this many rows are bisected by the LDS-staged kernel with
+// node-pure workgroups; shorter ones (which stay in cache) by the per-lane one
+constexpr int64_t STAGE_MIN_N = 2048;
+
+// slot list for a bisection launch: the slots of staged nodes first (with one
+// workgroup per G of them), then the rest
+struct BisectPlan {
+    std::vector<int64_t> list;
+    std::vector<BisWG> wgs;
+    int64_t n_staged = 0;
+    void add(int node, int64_t n, int64_t first, int64_t count, int G, std::vector<int64_t>& rest) {
+        if (n >= STAGE_MIN_N && std::getenv("MR3_NO_STAGE") == nullptr) {
+            for (int64_t o = 0; o < count; o += G)
+                wgs.push_back(BisWG{(int64_t)list.size() + o, (int)std::min<int64_t>(G, count - o), node});
+            for (int64_t i = 0; i < count; ++i) list.push_back(first + i);
+        } else {
+            for (int64_t i = 0; i < count; ++i) rest.push_back(first + i);
+        }
+    }
+    void finish(std::vector<int64_t>& rest) {
+        n_staged = (int64_t)list.size();
+        list.insert(list.end(), rest.begin(), rest.end());
+    }
+};
+
+// lanes per eigenvalue and points per lane.  Measured on the device: with
+// the rows staged through LDS the counts are issue bound, so one chain per
+// lane (P = 1) is the least work, and L doubles until ~64K lanes are busy (at
+// most 64 lanes, one wave, per eigenvalue).
 static BisectShape pick_shape(int64_t count, int user_lanes, int user_points) {
     BisectShape sh{1, 1};
     if (user_lanes > 0) {
         while (sh.L * 2 <= user_lanes && sh.L < 64) sh.L *= 2;
     } else {
-        while (sh.L < 64 && count * sh.L < 32768) sh.L *= 2;
+        while (sh.L < 64 && count * sh.L < 65536) sh.L *= 2;
     }
     if (user_points == 1 || user_points == 2 || user_points == 4) sh.P = user_points;
-    else sh.P = (count * sh.L >= 262144 || sh.L > 4) ? 1 : 2;
     return sh;
 }
 
@@ -519,18 +564,28 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     prof.end(st);
     HIPCHK(hipGetLastError());
     // ---- a3: bisection of every slot on its root ----
-    std::vector<int64_t> all_slots((size_t)K);
-    std::iota(all_slots.begin(), all_slots.end(), 0);
-    HIPCHK(upload(B[B_LIST], all_slots, st));
+    BisectShape L = pick_shape(K, prm.lanes_per_eig, prm.points_per_lane);
+    BisectPlan rplan;
+    {
+        std::vector<int64_t> rest;
+        for (int64_t b = 0; b < NB; ++b)
+            rplan.add((int)b, blocks[b].n, blocks[b].slot0, blocks[b].nslot, 256 / L.L, rest);
+        rplan.finish(rest);
+    }
+    HIPCHK(upload(B[B_LIST], rplan.list, st));
+    HIPCHK(upload(B[B_BWG], rplan.wgs, st));
     // intervals from the binary64 copy are widened by k n eps_d |lambda| before
     // classification: k = 10 on the double-double path (relative robustness
     // constant of the copy, Sec. 3.2 "Arithmetic used to approximate
     // eigenvalues"), 4 when the copy is the representation itself
     const double widen_root = (is_dd ? 10.0 : 4.0) * 1.1102230246251565e-16;  // x n_block
-    BisectShape L = pick_shape(K, prm.lanes_per_eig, prm.points_per_lane);
     prof.begin(MR3_STAGE_BISECT, st);
-    launch_bisect(L, B[B_LIST].as<int64_t>(), K, dslots, dnodes, dblocks, B[B_D64].rows<double>(),
-                  B[B_L64].rows<double>(), prm.bisect_rel, widen_root, work, st);
+    launch_bisect_staged(L, B[B_BWG].as<BisWG>(), (int64_t)rplan.wgs.size(), B[B_LIST].as<int64_t>(),
+                         dslots, dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
+                         prm.bisect_rel, widen_root, work, st);
+    launch_bisect(L, B[B_LIST].as<int64_t>() + rplan.n_staged, K - rplan.n_staged, dslots, dnodes,
+                  dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel,
+                  widen_root, work, st);
     prof.end(st);
     HIPCHK(hipGetLastError());
     // ---- output columns of split problems: order by eigenvalue ----
@@ -695,6 +750,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         std::vector<Node> pnodes;
         // parent node info (block of each cluster) from the device
         std::vector<ChildJob> jobs((size_t)C);
+        std::vector<int64_t> job_n((size_t)C);
         int64_t new_rows = 0, tmp_rows = 0;
         {
             std::vector<Node> allnodes;
@@ -712,6 +768,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                 new_rows += nb;
                 tmp_rows += nb;
                 jobs[c] = j;
+                job_n[c] = nb;
                 stats.largest_cluster = std::max<int64_t>(stats.largest_cluster, j.last - j.head + 1);
             }
         }
@@ -748,44 +805,69 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                            widen_root / prm.eps_x, prm.eps_x);
         prof.end(st);
         HIPCHK(hipGetLastError());
-        {
-            std::vector<ChildJob> done_jobs;
-            HIPCHK(download(done_jobs, B[B_JOBS].p, (size_t)C, st));
-            for (auto& j : done_jobs) {
-                if (j.best == 1) stats.n_best_candidate++;
-                if (j.best == 2) return MR3_ERR_NUMERIC;
-            }
+        std::vector<ChildJob> done_jobs;
+        HIPCHK(download(done_jobs, B[B_JOBS].p, (size_t)C, st));
+        for (auto& j : done_jobs) {
+            if (j.best == 1) stats.n_best_candidate++;
+            if (j.best == 2) return MR3_ERR_NUMERIC;
         }
         pool_rows += new_rows;
         n_nodes += C;
-        // ---- child bisection (Alg. 1 line 14) ----
-        size_t sb = 0;
-        SelectDepth seld{dslots, dnodes, depth + 1};
-        HIPCHK(hipcub::DeviceSelect::If(nullptr, sb, iter, B[B_LIST].as<int64_t>(), dcnt + 2, K, seld,
-                                        st));
-        HIPCHK(B[B_CUBTMP].ensure(sb + 256));
-        sb = B[B_CUBTMP].cap;
-        HIPCHK(hipcub::DeviceSelect::If(B[B_CUBTMP].p, sb, iter, B[B_LIST].as<int64_t>(), dcnt + 2, K,
-                                        seld, st));
-        std::vector<int64_t> c2;
-        HIPCHK(download(c2, dcnt + 2, 1, st));
-        const int64_t KC = c2[0];
+        // ---- child bisection (Alg. 1 line 14): the members of every new
+        // cluster, whose slots now belong to the child node ----
+        int64_t KC = 0;
+        for (int64_t c = 0; c < C; ++c) KC += crec[c].last - crec[c].head + 1;
         L = pick_shape(KC, prm.lanes_per_eig, prm.points_per_lane);
         if (const char* cs = std::getenv("MR3_CHILD_SHAPE")) {  // development aid: "L,P"
             int l = 0, q = 0;
             if (std::sscanf(cs, "%d,%d", &l, &q) == 2) L = pick_shape(KC, l, q);
         }
+        BisectPlan cplan;
+        {
+            std::vector<int64_t> rest;
+            for (int64_t c = 0; c < C; ++c)
+                cplan.add(jobs[c].child, job_n[c], crec[c].head, crec[c].last - crec[c].head + 1,
+                          256 / L.L, rest);
+            cplan.finish(rest);
+        }
+        HIPCHK(upload(B[B_LIST], cplan.list, st));
+        HIPCHK(upload(B[B_BWG], cplan.wgs, st));
         prof.begin(MR3_STAGE_CBISECT, st);
-        launch_bisect(L, B[B_LIST].as<int64_t>(), KC, dslots, dnodes, dblocks, B[B_D64].rows<double>(),
-                      B[B_L64].rows<double>(), prm.bisect_rel, widen_root, work, st);
+        launch_bisect_staged(L, B[B_BWG].as<BisWG>(), (int64_t)cplan.wgs.size(),
+                             B[B_LIST].as<int64_t>(), dslots, dnodes, dblocks,
+                             B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel,
+                             widen_root, work, st);
+        launch_bisect(L, B[B_LIST].as<int64_t>() + cplan.n_staged, KC - cplan.n_staged, dslots,
+                      dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
+                      prm.bisect_rel, widen_root, work, st);
         prof.end(st);
         prof.begin(MR3_STAGE_VERIFY, st);
-        if (is_dd && KC > 0) {
-            // a child may have element growth, so its binary64 copy need not
-            // be relatively robust: check every bracket with counts in y
-            hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)((KC + 31) / 32)), dim3(64), 0, st,
-                               B[B_LIST].as<int64_t>(), KC, dslots, dnodes, dblocks,
-                               B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(), prm.bisect_rel, counters + 3);
+        if (is_dd) {
+            // A child accepted within the strict growth bound k_elg * spdiam
+            // is relatively robust like the root (Sec. 2, "Requirements on
+            // the representations"), so its binary64 copy brackets its
+            // eigenvalues after the widening.  A child accepted under the
+            // relaxed bound or as least-growth candidate may not be: check
+            // its brackets with counts in y.
+            // one workgroup per 32 slots of one child node
+            std::vector<int64_t> vlist;
+            std::vector<BisWG> vwg;
+            for (int64_t c = 0; c < C; ++c) {
+                if (done_jobs[c].strict) continue;
+                const int64_t m = crec[c].last - crec[c].head + 1;
+                for (int64_t o = 0; o < m; o += 32)
+                    vwg.push_back(BisWG{(int64_t)vlist.size() + o, (int)std::min<int64_t>(32, m - o),
+                                        jobs[c].child});
+                for (int64_t sidx = crec[c].head; sidx <= crec[c].last; ++sidx) vlist.push_back(sidx);
+            }
+            if (!vwg.empty()) {
+                HIPCHK(upload(B[B_VLIST], vlist, st));
+                HIPCHK(upload(B[B_VWG], vwg, st));
+                hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)vwg.size()), dim3(64), 0, st,
+                                   B[B_VWG].as<BisWG>(), B[B_VLIST].as<int64_t>(), dslots, dnodes,
+                                   dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
+                                   prm.bisect_rel, counters + 3);
+            }
         }
         prof.end(st);
         HIPCHK(hipGetLastError());

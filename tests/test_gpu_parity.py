@@ -221,3 +221,43 @@ def test_prescribed_20000_sampled(mr3):
             zr = oracle.eigvecs(d, e, hi, lo)[:, 0]
             c = abs(float(zr @ Z[:, k]))
             assert 1 - c <= 1e-8, (rng, i, c)
+
+
+def test_fault_injection_paths(mr3):
+    """Forced least-growth shift candidates (and with them the check of child
+    brackets in y) and the forced RQI fallback (bisection in y, then one
+    step) still meet every gate."""
+    h = mr3.Handle(0)
+    d, e = W.glued_wilkinson(336)
+    h.set_params(precision=64, force_best_candidate=1)
+    run_case(mr3, d, e, handle=h)
+    assert h.stats()["n_best_candidate"] > 0
+    d, e, _ = W.prescribed_spectrum(600, 1)
+    h.set_params(precision=64, force_rqi_fallback=1)
+    run_case(mr3, d, e, handle=h)
+    assert h.stats()["n_fallbacks"] == 600
+    d, e = W.uniform(300, 3, np.float32)
+    h.set_params(precision=32, force_rqi_fallback=1)
+    run_case(mr3, d, e, handle=h)
+    assert h.stats()["n_fallbacks"] == 300
+
+
+def test_metamorphic_relations(mr3):
+    """Exact relations of the method: scaling T by a power of two scales the
+    eigenvalues exactly and leaves the vectors unchanged (the input is
+    normalised by a power of two first); flipping signs of off-diagonals
+    leaves the eigenvalues unchanged and only flips signs of vector entries
+    (the representation holds e^2, the vector products hold the signs);
+    reversing the row order gives the same spectrum to the gate."""
+    d, e = W.uniform(400, 21, np.float64)
+    W0, Z0 = mr3.solve(_dev(d), _dev(e))
+    W1, Z1 = mr3.solve(_dev(d * 2.0 ** -7), _dev(e * 2.0 ** -7))
+    assert torch.equal(W1 * 2.0 ** 7, W0) and torch.equal(Z1, Z0)
+    flips = np.where(np.random.default_rng(5).uniform(size=e.size) < 0.5, -1.0, 1.0)
+    W2, Z2 = mr3.solve(_dev(d), _dev(e * flips))
+    assert torch.equal(W2, W0) and torch.equal(Z2.abs(), Z0.abs())
+    W3, Z3 = mr3.solve(_dev(d[::-1].copy()), _dev(e[::-1].copy()))
+    n, tn = d.size, M.tnorm(d, e)
+    assert float((W3 - W0).abs().max()) <= 4 * n * 2.0 ** -53 * tn
+    R = M.residual(d[::-1].copy(), e[::-1].copy(), W3.cpu().numpy(), Z3.cpu().numpy())
+    assert R <= 10 * n * 2.0 ** -53
