@@ -982,7 +982,7 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
                 Slot* __restrict__ slots, const Node* __restrict__ nodes,
                 const Block* __restrict__ blocks, const double* __restrict__ d64,
                 const double* __restrict__ lld64, double rtol, double widen,
-                double* __restrict__ work) {
+                double* __restrict__ work, int check) {
     __shared__ double2 win[2][STAGE_ROWS];
     const BisWG w = wgs[blockIdx.x];
     const int g = threadIdx.x / L;
@@ -1003,8 +1003,9 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
     }
     const int lane = threadIdx.x & 63;
     const int gbase = lane - q;
-    // make sure the bracket holds: count(lo) <= j-1 < count(hi)
-    bool fix = active;
+    // make sure the bracket holds: count(lo) <= j-1 < count(hi) (skipped when
+    // the caller has verified every bracket with counts already)
+    bool fix = active && check;
     for (int it = 0; it < 64; ++it) {
         if (!__syncthreads_or(fix)) break;
         const double xs2[2] = {lo, hi};
@@ -1060,6 +1061,57 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
         slots[s].lo = lo - wd;
         slots[s].hi = hi + wd;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Spectrum slicing before the per-eigenvalue multisection of a large root:
+// Sturm counts at M equally spaced interior points of the root interval are
+// shared by all eigenvalues of the block, so every eigenvalue starts from one
+// slice of width (hi - lo) / (M + 1) -- log2(M + 1) bisection steps for the
+// price of M counts.  Brackets are taken only where the counts prove them.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double slice_point(double lo, double hi, int64_t m, int64_t M) {
+    return lo + (hi - lo) * ((double)(m + 1) / (double)(M + 1));
+}
+
+__global__ void __launch_bounds__(256)
+k_slice(const Block* __restrict__ blocks, int b, const Node* __restrict__ nodes,
+        const Slot* __restrict__ slots, const double* __restrict__ d64,
+        const double* __restrict__ lld64, int64_t M, int* __restrict__ cnt) {
+    __shared__ double2 win[2][STAGE_ROWS];
+    const Block blk = blocks[b];
+    const Node nd = nodes[b];
+    const double lo = slots[blk.slot0].lo, hi = slots[blk.slot0].hi;
+    const int64_t m = (int64_t)blockIdx.x * STAGE_ROWS + threadIdx.x;  // M is a multiple
+    const double xs[1] = {slice_point(lo, hi, m, M)};
+    int c[1];
+    staged_counts<1>(d64 + nd.rep, lld64 + nd.rep, blk.n, xs, c, true, win);
+    cnt[m] = c[0];
+}
+
+__global__ void __launch_bounds__(256)
+k_slice_assign(const Block* __restrict__ blocks, int b, Slot* __restrict__ slots, int64_t M,
+               const int* __restrict__ cnt, double* __restrict__ work) {
+    const Block blk = blocks[b];
+    const int64_t s = blk.slot0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= blk.slot0 + blk.nslot) return;
+    const double lo = slots[blk.slot0].lo, hi = slots[blk.slot0].hi;  // same for all slots
+    const int64_t j = slots[s].idx;
+    // first point whose count reaches j
+    int64_t a = 0, z = M;
+    while (a < z) {
+        const int64_t mid = (a + z) >> 1;
+        if (cnt[mid] >= j) z = mid;
+        else a = mid + 1;
+    }
+    const bool ok = (a == M || cnt[a] >= j) && (a == 0 || cnt[a - 1] <= j - 1);
+    if (!ok) return;  // counts not monotone here: keep the root interval
+    const double nlo = (a == 0) ? lo : slice_point(lo, hi, a - 1, M);
+    const double nhi = (a == M) ? hi : slice_point(lo, hi, a, M);
+    slots[s].lo = nlo;
+    slots[s].hi = nhi;
+    // algorithmic work: the halvings plain bisection needs for this narrowing
+    atomicAdd(&work[0], log2((hi - lo) / fmax(nhi - nlo, 1e-300)) * (double)blk.n);
 }
 
 // ---------------------------------------------------------------------------

@@ -142,7 +142,7 @@ enum BufId {
     B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BLOCKS, B_SLOTS, B_NODES, B_REPD, B_REPL, B_REPE,
     B_D64, B_L64, B_P, B_PE, B_Q, B_QE, B_LIST, B_LIST2, B_CNT, B_TILEOFF, B_TILES, B_RES,
     B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_M, B_BAD, B_COUNTERS,
-    B_BOFF, B_CREC, B_CHECK, B_BWG, B_VLIST, B_VWG, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
+    B_BOFF, B_CREC, B_CHECK, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
 };
 
 // singleton work of tree level d runs on the handle's side stream with the
@@ -322,12 +322,12 @@ static void launch_bisect(BisectShape sh, const int64_t* list, int64_t count, Sl
 static void launch_bisect_staged(BisectShape sh, const BisWG* wgs, int64_t nwg, const int64_t* list,
                                  Slot* slots, const Node* nodes, const Block* blocks,
                                  const double* d64, const double* l64, double rtol, double widen,
-                                 double* work, hipStream_t st) {
+                                 double* work, int check, hipStream_t st) {
     if (nwg <= 0) return;
 #define MR3_BST(LL, PP)                                                                        \
     if (sh.L == LL && sh.P == PP) {                                                            \
         hipLaunchKernelGGL((k_bisect_staged<LL, PP>), dim3((unsigned)nwg), dim3(256), 0, st,   \
-                           wgs, list, slots, nodes, blocks, d64, l64, rtol, widen, work);      \
+                           wgs, list, slots, nodes, blocks, d64, l64, rtol, widen, work, check); \
         return;                                                                                \
     }
     MR3_BST(1, 1) MR3_BST(1, 2) MR3_BST(1, 4)
@@ -338,6 +338,15 @@ static void launch_bisect_staged(BisectShape sh, const BisWG* wgs, int64_t nwg, 
     MR3_BST(32, 1) MR3_BST(32, 2) MR3_BST(32, 4)
     MR3_BST(64, 1) MR3_BST(64, 2) MR3_BST(64, 4)
 #undef MR3_BST
+}
+
+// slice points for a root with k wanted eigenvalues: about 3k (each point
+// costs one count, each eigenvalue gains log2(M + 1) halvings), a multiple of
+// the workgroup size, between 1024 and 65536
+static int64_t slice_points(int64_t k) {
+    int64_t M = 1024;
+    while (M < 3 * k && M < 65536) M *= 2;
+    return M;
 }
 
 // nodes of at least this many rows are bisected by the LDS-staged kernel with
@@ -580,9 +589,33 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     // eigenvalues"), 4 when the copy is the representation itself
     const double widen_root = (is_dd ? 10.0 : 4.0) * 1.1102230246251565e-16;  // x n_block
     prof.begin(MR3_STAGE_BISECT, st);
+    // staged (large) roots: spectrum slicing first; it proves every bracket,
+    // and a bracket it cannot prove keeps the root interval, which holds by
+    // construction (definite root, Gerschgorin bounds with slack)
+    {
+        std::vector<int64_t> soff;
+        int64_t tot = 0;
+        for (int64_t b = 0; b < NB; ++b) {
+            soff.push_back(tot);
+            if (blocks[b].n >= STAGE_MIN_N && blocks[b].nslot > 0) tot += slice_points(blocks[b].nslot);
+        }
+        if (tot > 0) {
+            HIPCHK(B[B_SLICE].ensure(sizeof(int) * tot));
+            for (int64_t b = 0; b < NB; ++b) {
+                if (blocks[b].n < STAGE_MIN_N || blocks[b].nslot <= 0) continue;
+                const int64_t M = slice_points(blocks[b].nslot);
+                int* cnt = B[B_SLICE].as<int>() + soff[b];
+                hipLaunchKernelGGL(k_slice, dim3((unsigned)(M / STAGE_ROWS)), dim3(STAGE_ROWS), 0, st,
+                                   dblocks, (int)b, dnodes, dslots, B[B_D64].rows<double>(),
+                                   B[B_L64].rows<double>(), M, cnt);
+                hipLaunchKernelGGL(k_slice_assign, dim3((unsigned)((blocks[b].nslot + 255) / 256)),
+                                   dim3(256), 0, st, dblocks, (int)b, dslots, M, cnt, work);
+            }
+        }
+    }
     launch_bisect_staged(L, B[B_BWG].as<BisWG>(), (int64_t)rplan.wgs.size(), B[B_LIST].as<int64_t>(),
                          dslots, dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
-                         prm.bisect_rel, widen_root, work, st);
+                         prm.bisect_rel, widen_root, work, 0, st);
     launch_bisect(L, B[B_LIST].as<int64_t>() + rplan.n_staged, K - rplan.n_staged, dslots, dnodes,
                   dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel,
                   widen_root, work, st);
@@ -836,7 +869,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         launch_bisect_staged(L, B[B_BWG].as<BisWG>(), (int64_t)cplan.wgs.size(),
                              B[B_LIST].as<int64_t>(), dslots, dnodes, dblocks,
                              B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel,
-                             widen_root, work, st);
+                             widen_root, work, 1, st);
         launch_bisect(L, B[B_LIST].as<int64_t>() + cplan.n_staged, KC - cplan.n_staged, dslots,
                       dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
                       prm.bisect_rel, widen_root, work, st);
