@@ -1524,33 +1524,211 @@ __device__ __forceinline__ dd shfl_y<dd>(dd v, int src) {
     return mk_dd(__shfl(v.hi, src, 64), __shfl(v.lo, src, 64));
 }
 
+// ---------------------------------------------------------------------------
+// LDS windows of the RQI sweeps.  All pairs of a chunk belong to one node, so
+// at step `it` every top lane reads row it and every bottom lane row n-1-it
+// (advancing over row n-2-it).  While a window of SW steps is processed, the
+// 64 threads load the next window of both streams, one step of one stream
+// each.  In the bottom stream d and lld swap roles, so both lanes run the same
+// recurrence: c = f b + a, a' = g a - tau c.
+// ---------------------------------------------------------------------------
+constexpr int SW = 32;
+
+struct ChunkInfo {
+    int64_t begin;  // first position in the singleton list
+    int count;      // pairs in the chunk (<= 32), all of one node
+    int pad;
+};
+
+template <class Y>
+struct SweepStep {
+    Y pq, f, g;
+    int pqe;
+};
+
+template <class Y>
+struct SweepWin {
+    Y pq[2][2][SW];  // [buffer][stream][step]
+    Y f[2][2][SW];
+    Y g[2][2][SW];
+    int pqe[2][2][SW];
+};
+
+template <class Y>
+__device__ __forceinline__ SweepStep<Y> load_sweep_step(int stream, int64_t it,
+                                                        const Y* __restrict__ D,
+                                                        const Y* __restrict__ LL,
+                                                        const Y* __restrict__ P,
+                                                        const int* __restrict__ Pe,
+                                                        const Y* __restrict__ Q,
+                                                        const int* __restrict__ Qe, int64_t n) {
+    SweepStep<Y> w;
+    if (it >= n) {
+        w.pq = w.f = w.g = y_from(0.0, Y());
+        w.pqe = 0;
+    } else if (stream == 0) {
+        w.pq = P[it];
+        w.pqe = Pe[it];
+        w.f = D[it];
+        w.g = LL[it];
+    } else {
+        // the advance row n-2-it is -1 only on the twist row of r = 0, whose
+        // f and g are never used; the pool keeps a guard row there
+        const int64_t kz = n - 1 - it, ka = kz - 1;
+        w.pq = Q[kz];
+        w.pqe = Qe[kz];
+        w.f = LL[ka];
+        w.g = D[ka];
+    }
+    return w;
+}
+
+template <class Y>
+__device__ __forceinline__ void put_sweep_step(SweepWin<Y>& win, int buf, int stream, int u,
+                                               const SweepStep<Y>& w) {
+    win.pq[buf][stream][u] = w.pq;
+    win.f[buf][stream][u] = w.f;
+    win.g[buf][stream][u] = w.g;
+    win.pqe[buf][stream][u] = w.pqe;
+}
+
+template <class Y>
+__device__ __forceinline__ SweepStep<Y> get_sweep_step(const SweepWin<Y>& win, int buf, int stream,
+                                                       int u) {
+    SweepStep<Y> w;
+    w.pq = win.pq[buf][stream][u];
+    w.f = win.f[buf][stream][u];
+    w.g = win.g[buf][stream][u];
+    w.pqe = win.pqe[buf][stream][u];
+    return w;
+}
+
+// One sweep of every lane of the chunk's wave (all 64 threads call it; lanes
+// with steps == 0 only help with the loads).  Same arithmetic as the
+// per-lane sweep: the top lane runs the stationary transform over rows 0..r,
+// the bottom lane the progressive one over rows n-1..r, each storing its part
+// of z in its tile column with the same storage rebasing.
+template <class Y>
+__device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __restrict__ LL,
+                                const Y* __restrict__ P, const int* __restrict__ Pe,
+                                const Y* __restrict__ Q, const int* __restrict__ Qe, int64_t n,
+                                int64_t r, Y tau, double* __restrict__ col, bool store,
+                                int64_t steps, SweepWin<Y>& win) {
+    const int t = threadIdx.x;
+    const int side = top ? 0 : 1;
+    Half<Y> h;
+    h.ss = 0.0;
+    h.zmax = 0.0;
+    h.zmaxv = 0.0;
+    h.zmaxk = -1;
+    h.zr = 0.0;
+    h.ev1 = top ? 0 : n;
+    h.ev2 = top ? 0 : n;
+    h.ev2f = 1.0;
+    Y a = neg(tau), b = y_from(1.0, Y());
+    if (!top && steps > 0) a = sub(D[n - 1], tau);
+    int eb = 0;    // binary exponent carried by b
+    int eref = 0;  // storage frame exponent
+    int64_t smax = steps;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) smax = max(smax, (int64_t)__shfl_xor(smax, off, 64));
+    put_sweep_step<Y>(win, 0, t >> 5, t & 31,
+                      load_sweep_step<Y>(t >> 5, t & 31, D, LL, P, Pe, Q, Qe, n));
+    __syncthreads();
+    auto zvalue = [&](const SweepStep<Y>& w, int64_t k, bool check) -> double {
+        const Y pb = mul(w.pq, b);
+        int ex = w.pqe + eb - eref;
+        if (check) {
+            const int ez = y_exp(pb) + ex;
+            const bool rb = ez > 300;
+            const int dlt = rb ? ez : 0;
+            eref += dlt;
+            ex -= dlt;
+            h.ss = __builtin_ldexp(h.ss, -2 * dlt);
+            h.zmax = __builtin_ldexp(h.zmax, -dlt);
+            h.zmaxv = __builtin_ldexp(h.zmaxv, -dlt);
+            h.ev1 = rb ? h.ev2 : h.ev1;
+            h.ev2 = rb ? k : h.ev2;
+            h.ev2f = rb ? __builtin_ldexp(1.0, -dlt) : h.ev2f;
+        }
+        return __builtin_ldexp(to_double(pb), ex);
+    };
+    auto body = [&](const SweepStep<Y>& w, int64_t it, int u) {
+        const int64_t k = top ? it : n - 1 - it;
+        const double zv = zvalue(w, k, (u & 1) == 1);
+        if (store) col[k * 32] = zv;
+        h.ss = __fma_rn(zv, zv, h.ss);
+        const bool bigger = fabs(zv) > h.zmax;
+        h.zmax = bigger ? fabs(zv) : h.zmax;
+        h.zmaxv = bigger ? zv : h.zmaxv;
+        h.zmaxk = bigger ? k : h.zmaxk;
+        const Y c = mul_add(w.f, b, a);
+        a = sub(mul(w.g, a), mul(tau, c));
+        b = c;
+        if ((u & 3) == 3) {
+            const int em = max(y_exp(a), y_exp(b));
+            a = y_ldexp(a, -em);
+            b = y_ldexp(b, -em);
+            eb += em;
+        }
+    };
+    for (int64_t it0 = 0; it0 < smax; it0 += SW) {
+        const int cur = (int)((it0 / SW) & 1);
+        const SweepStep<Y> nx = load_sweep_step<Y>(t >> 5, it0 + SW + (t & 31), D, LL, P, Pe, Q, Qe, n);
+        if (it0 + SW < steps) {
+            // the twist row lies beyond this window: straight-line steps
+            for (int u = 0; u < SW; u += 4) {
+                SweepStep<Y> w[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) w[v] = get_sweep_step<Y>(win, cur, side, u + v);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) body(w[v], it0 + u + v, v);
+            }
+        } else if (it0 < steps) {
+            // the window that ends with the twist row (step steps-1)
+            for (int u = 0; u < SW; ++u) {
+                const int64_t it = it0 + u;
+                if (it + 1 < steps) {
+                    body(get_sweep_step<Y>(win, cur, side, u), it, u);
+                } else if (it + 1 == steps) {
+                    h.zr = zvalue(get_sweep_step<Y>(win, cur, side, u), top ? it : n - 1 - it, true);
+                }
+            }
+        }
+        put_sweep_step<Y>(win, cur ^ 1, t >> 5, t & 31, nx);
+        __syncthreads();
+    }
+    h.sp = div(a, b);  // s_r = a_r / b_r  or  p_r = alpha_r / beta_r
+    return h;
+}
+
 template <class Y>
 __global__ void __launch_bounds__(64)
-k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict__ tile_off,
-      double* __restrict__ tiles, const Slot* __restrict__ slots, const Node* __restrict__ nodes,
+k_rqi(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
+      const int64_t* __restrict__ tile_off, double* __restrict__ tiles, const Slot* __restrict__ slots, const Node* __restrict__ nodes,
       const Block* __restrict__ blocks, const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld,
       const double* __restrict__ d64, const double* __restrict__ lld64, const Y* __restrict__ P,
       const int* __restrict__ Pe, const Y* __restrict__ Q, const int* __restrict__ Qe, Params prm,
       double eps_y, RqiResult* __restrict__ res, unsigned long long* __restrict__ counters,
       double* __restrict__ work) {
+    __shared__ SweepWin<Y> win;
     const int lane = threadIdx.x;
     const int pair = lane >> 1;
     const bool top = (lane & 1) == 0;
-    const int64_t idx = (int64_t)blockIdx.x * 32 + pair;
-    const bool active = idx < count;
+    const ChunkInfo ck = chunks[blockIdx.x];
+    const int64_t idx = ck.begin + pair;
+    const bool active = pair < ck.count;
     double* tile = tiles + tile_off[blockIdx.x] + pair;
-    int64_t n = 0, rep = 0, brow = 0;
-    double lo = 0, hi = 0, gap = 0, spd = 1;
+    // every pair of the chunk belongs to the same node
+    const Node nd = nodes[slots[list[ck.begin]].node];
+    const Block bk = blocks[nd.block];
+    const int64_t n = bk.n, rep = nd.rep, brow = bk.row0;
+    const double spd = nd.spdiam;
+    double lo = 0, hi = 0, gap = 0;
     if (active) {
         const Slot sl = slots[list[idx]];
-        const Node nd = nodes[sl.node];
-        const Block bk = blocks[nd.block];
-        n = bk.n;
-        rep = nd.rep;
-        brow = bk.row0;
         lo = sl.lo;
         hi = sl.hi;
-        spd = nd.spdiam;
         double lg = sl.lgap, rg = sl.rgap;
         if (!(lg > 0.0)) lg = (lg < 0.0) ? MR3_BIG : fmax(hi - lo, 1e-300);
         if (!(rg > 0.0)) rg = (rg < 0.0) ? MR3_BIG : fmax(hi - lo, 1e-300);
@@ -1602,15 +1780,20 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
     double zT = 1, zB = 1;
     int64_t r_out = r;     // twist of the sweep whose vector is published
     bool retried = false;  // one twist retry after leaving the interval
-    for (int it = 0; it < prm.rqi_max_iter && !fallback; ++it) {
-        if (!__any(!done)) break;
-        const int64_t steps = done ? 0 : (top ? r + 1 : n - r);
-        Half<Y> h = sweep<Y>(top, D, LL, top ? P + brow : Q + brow, top ? Pe + brow : Qe + brow,
-                             n, r, lam, tile, true, steps);
+    // every lane stays in the loop (the staged sweep needs all 64 threads);
+    // pairs that are done or falling back sweep zero steps
+    for (int it = 0; it < prm.rqi_max_iter; ++it) {
+        if (!__any(!done && !fallback)) break;
+        const int64_t steps = (done || fallback) ? 0 : (top ? r + 1 : n - r);
+        Half<Y> h = sweep_staged<Y>(top, D, LL, P + brow, Pe + brow, Q + brow, Qe + brow, n, r,
+                                    lam, tile, true, steps, win);
         const Y spo = shfl_y<Y>(h.sp, lane ^ 1);
         const double zro = __shfl_xor(h.zr, 1, 64);
         const double sso = __shfl_xor(h.ss, 1, 64);
-        if (done) continue;
+        const double rel = h.zmax / fabs(h.zr);
+        const double relo = __shfl_xor(rel, 1, 64);
+        const int64_t ko = __shfl_xor(h.zmaxk, 1, 64);
+        if (done || fallback) continue;
         ++iters;
         const Y s_r = top ? h.sp : spo;
         const Y p_r = top ? spo : h.sp;
@@ -1622,17 +1805,14 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
         const double g = to_double(gam);
         if (!(nrm2 >= 1.0) || !isfinite(nrm2) || zrT == 0.0 || zrB == 0.0) {
             fallback = true;
-            break;
+            continue;
         }
         const double resid = fabs(g) / sqrt(nrm2);
         const double corr = g / nrm2;
         const Y lnew = add(lam, y_from(corr, Y()));
-        // largest stored entry relative to the twist row, per half.  The
-        // shuffles run on both lanes of the pair (a shuffle whose source lane
-        // is inactive returns 0), then each lane selects.
-        const double rel = h.zmax / fabs(top ? zrT : zrB);
-        const double relo = __shfl_xor(rel, 1, 64);
-        const int64_t ko = __shfl_xor(h.zmaxk, 1, 64);
+        // largest stored entry relative to the twist row, per half (the
+        // shuffles above ran on both lanes of every pair, since a shuffle
+        // whose source lane is inactive returns 0)
         const double mT = top ? rel : relo;
         const double mB = top ? relo : rel;
         const int64_t kT = top ? h.zmaxk : ko;
@@ -1659,7 +1839,7 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
                 continue;
             }
             fallback = true;
-            break;
+            continue;
         }
         lam = lnew;
         // move the twist to the largest entry if the current one is poor
@@ -1722,8 +1902,8 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
         for (int rep_it = 0; rep_it < 3; ++rep_it) {
             if (!__any(again)) break;
             const int64_t steps = again ? (top ? r + 1 : n - r) : 0;
-            Half<Y> h = sweep<Y>(top, D, LL, top ? P + brow : Q + brow, top ? Pe + brow : Qe + brow,
-                                 n, r, lam, tile, true, steps);
+            Half<Y> h = sweep_staged<Y>(top, D, LL, P + brow, Pe + brow, Q + brow, Qe + brow, n, r,
+                                        lam, tile, true, steps, win);
             const Y spo = shfl_y<Y>(h.sp, lane ^ 1);
             const double zro = __shfl_xor(h.zr, 1, 64);
             const double sso = __shfl_xor(h.ss, 1, 64);
@@ -1798,8 +1978,8 @@ k_rqi(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict
 // ---------------------------------------------------------------------------
 template <class X, class Y>
 __global__ void __launch_bounds__(256)
-k_zout(const int64_t* __restrict__ list, int64_t count, const int64_t* __restrict__ tile_off,
-       const double* __restrict__ tiles, const Slot* __restrict__ slots,
+k_zout(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
+       const int64_t* __restrict__ tile_off, const double* __restrict__ tiles, const Slot* __restrict__ slots,
        const Node* __restrict__ nodes, const Block* __restrict__ blocks,
        const ProbInfo* __restrict__ pinfo, const RqiResult* __restrict__ res,
        const ProbDesc* __restrict__ probs, bool any_z) {
@@ -1809,12 +1989,12 @@ k_zout(const int64_t* __restrict__ list, int64_t count, const int64_t* __restric
     __shared__ X* s_z[32];
     __shared__ int64_t s_rows;
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * 32;
+    const ChunkInfo ck = chunks[blockIdx.x];
     const double* tile = tiles + tile_off[blockIdx.x];
     if (t < 32) {
-        const int64_t idx = base + t;
+        const int64_t idx = ck.begin + t;
         s_n[t] = 0;
-        if (idx < count) {
+        if (t < ck.count) {
             const Slot sl = slots[list[idx]];
             const Node nd = nodes[sl.node];
             const Block bk = blocks[nd.block];

@@ -47,19 +47,48 @@ struct SelectDepth {
     }
 };
 
-__global__ void k_chunk_rows(const int64_t* __restrict__ list, int64_t count,
-                             const Slot* __restrict__ slots, const Node* __restrict__ nodes,
-                             const Block* __restrict__ blocks, int64_t* __restrict__ rows,
-                             int64_t nchunk) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nchunk) return;
-    int64_t m = 0;
-    for (int q = 0; q < 32; ++q) {
-        const int64_t i = c * 32 + q;
-        if (i < count) m = max(m, blocks[nodes[slots[list[i]].node].block].n);
-    }
-    rows[c] = m * 32;
+// Node-pure chunks of at most 32 singletons.  The singleton list is ordered by
+// slot and every node owns a contiguous slot range, so each node's singletons
+// form one run of the list; chunks split the runs at every 32nd entry.
+__global__ void k_seg_marks(const int64_t* __restrict__ list, int64_t count,
+                            const Slot* __restrict__ slots, int64_t* __restrict__ seg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    seg[i] = (i == 0 || slots[list[i]].node != slots[list[i - 1]].node) ? i : 0;
 }
+
+// seg[i] = first position of i's run (after a max-scan): chunk starts
+__global__ void k_chunk_marks(const int64_t* __restrict__ seg, int64_t count,
+                              int64_t* __restrict__ mark) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    mark[i] = ((i - seg[i]) % 32 == 0) ? 1 : 0;
+}
+
+// cid[i] = chunk of position i + 1 (after an inclusive sum of the marks)
+__global__ void k_chunk_table(const int64_t* __restrict__ list, int64_t count,
+                              const Slot* __restrict__ slots, const Node* __restrict__ nodes,
+                              const Block* __restrict__ blocks, const int64_t* __restrict__ seg,
+                              const int64_t* __restrict__ cid, ChunkInfo* __restrict__ chunks,
+                              int64_t* __restrict__ rows) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count || (i - seg[i]) % 32 != 0) return;
+    int c = 1;
+    while (c < 32 && i + c < count && seg[i + c] == seg[i]) ++c;
+    const int64_t k = cid[i] - 1;
+    ChunkInfo ci;
+    ci.begin = i;
+    ci.count = c;
+    ci.pad = 0;
+    chunks[k] = ci;
+    rows[k] = blocks[nodes[slots[list[i]].node].block].n * 32;
+}
+
+struct MaxOp {
+    __host__ __device__ int64_t operator()(const int64_t& a, const int64_t& b) const {
+        return a > b ? a : b;
+    }
+};
 
 struct ClusterRec {
     int64_t head, last;
@@ -142,7 +171,7 @@ enum BufId {
     B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BLOCKS, B_SLOTS, B_NODES, B_REPD, B_REPL, B_REPE,
     B_D64, B_L64, B_P, B_PE, B_Q, B_QE, B_LIST, B_LIST2, B_CNT, B_TILEOFF, B_TILES, B_RES,
     B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_M, B_BAD, B_COUNTERS,
-    B_BOFF, B_CREC, B_CHECK, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
+    B_BOFF, B_CREC, B_CHECK, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
 };
 
 // singleton work of tree level d runs on the handle's side stream with the
@@ -152,6 +181,7 @@ constexpr int B_SIDE_LIST[2] = {B_SLIST0, B_SLIST1};
 constexpr int B_SIDE_TOFF[2] = {B_TILEOFF, B_TILEOFF1};
 constexpr int B_SIDE_TILES[2] = {B_TILES, B_TILES1};
 constexpr int B_SIDE_RES[2] = {B_RES, B_RES1};
+constexpr int B_SIDE_CHUNK[2] = {B_CHUNK0, B_CHUNK1};
 
 }  // namespace mr3
 
@@ -676,6 +706,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         Buf& STO = B[B_SIDE_TOFF[par]];
         Buf& STI = B[B_SIDE_TILES[par]];
         Buf& SRE = B[B_SIDE_RES[par]];
+        Buf& SCK = B[B_SIDE_CHUNK[par]];
         HIPCHK(SL.ensure(sizeof(int64_t) * K));
         size_t tmp_bytes = 0, tb2 = 0;
         SelectKind sel_s{dslots, dnodes, KIND_SINGLETON, depth};
@@ -700,12 +731,36 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                          depth, level_nodes.size(), (long long)S, (long long)C, now_ms() - t_start);
         // ---- a6 + a7: singletons, on the side stream ----
         if (S > 0) {
-            const int64_t nchunk = (S + 31) / 32;
+            // node-pure chunks (at most S of them)
+            HIPCHK(B[B_SEG].ensure(sizeof(int64_t) * S));
+            HIPCHK(B[B_CMARK].ensure(sizeof(int64_t) * S));
+            HIPCHK(B[B_CID].ensure(sizeof(int64_t) * S));
+            int64_t* seg = B[B_SEG].as<int64_t>();
+            int64_t* cmark = B[B_CMARK].as<int64_t>();
+            int64_t* cid = B[B_CID].as<int64_t>();
+            const unsigned gS = (unsigned)((S + 255) / 256);
+            hipLaunchKernelGGL(k_seg_marks, dim3(gS), dim3(256), 0, st, SL.as<int64_t>(), S, dslots, seg);
+            {
+                size_t tb = 0;
+                HIPCHK(hipcub::DeviceScan::InclusiveScan(nullptr, tb, seg, seg, MaxOp(), S, st));
+                size_t tb2 = 0;
+                HIPCHK(hipcub::DeviceScan::InclusiveSum(nullptr, tb2, cmark, cid, S, st));
+                HIPCHK(B[B_CUBTMP].ensure(std::max(tb, tb2) + 256));
+                tb = B[B_CUBTMP].cap;
+                HIPCHK(hipcub::DeviceScan::InclusiveScan(B[B_CUBTMP].p, tb, seg, seg, MaxOp(), S, st));
+                hipLaunchKernelGGL(k_chunk_marks, dim3(gS), dim3(256), 0, st, seg, S, cmark);
+                tb2 = B[B_CUBTMP].cap;
+                HIPCHK(hipcub::DeviceScan::InclusiveSum(B[B_CUBTMP].p, tb2, cmark, cid, S, st));
+            }
+            std::vector<int64_t> nck;
+            HIPCHK(download(nck, cid + S - 1, 1, st));
+            const int64_t nchunk = nck[0];
+            HIPCHK(SCK.ensure(sizeof(ChunkInfo) * nchunk));
             HIPCHK(STO.ensure(sizeof(int64_t) * (nchunk + 1)));
             HIPCHK(B[B_FLAGS].ensure(sizeof(int64_t) * (nchunk + 1)));
             int64_t* rows = reinterpret_cast<int64_t*>(B[B_FLAGS].p);
-            hipLaunchKernelGGL(k_chunk_rows, dim3((unsigned)((nchunk + 255) / 256)), dim3(256), 0, st,
-                               SL.as<int64_t>(), S, dslots, dnodes, dblocks, rows, nchunk);
+            hipLaunchKernelGGL(k_chunk_table, dim3(gS), dim3(256), 0, st, SL.as<int64_t>(), S, dslots,
+                               dnodes, dblocks, seg, cid, SCK.as<ChunkInfo>(), rows);
             size_t sb = 0;
             HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, sb, rows, STO.as<int64_t>(), nchunk + 1,
                                                     st));
@@ -722,7 +777,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             HIPCHK(hipStreamWaitEvent(side, h->ev_fork, 0));
             prof.begin(MR3_STAGE_RQI, side);
             hipLaunchKernelGGL(k_rqi<Y>, dim3((unsigned)nchunk), dim3(64), 0, side,
-                               SL.as<int64_t>(), S, STO.as<int64_t>(), STI.rows<double>(32), dslots,
+                               SCK.as<ChunkInfo>(), SL.as<int64_t>(), STO.as<int64_t>(),
+                               STI.rows<double>(32), dslots,
                                dnodes, dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
                                B[B_D64].rows<double>(), B[B_L64].rows<double>(), B[B_P].rows<Y>(),
                                B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>(), prm,
@@ -730,7 +786,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             prof.end(side);
             prof.begin(MR3_STAGE_ZOUT, side);
             hipLaunchKernelGGL((k_zout<X, Y>), dim3((unsigned)nchunk), dim3(256), 0, side,
-                               SL.as<int64_t>(), S, STO.as<int64_t>(), STI.rows<double>(32), dslots,
+                               SCK.as<ChunkInfo>(), SL.as<int64_t>(), STO.as<int64_t>(),
+                               STI.rows<double>(32), dslots,
                                dnodes, dblocks, B[B_PINFO].as<ProbInfo>(), SRE.as<RqiResult>(),
                                B[B_PROBS].as<ProbDesc>(), any_z);
             prof.end(side);
