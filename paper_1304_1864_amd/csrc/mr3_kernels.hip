@@ -794,12 +794,12 @@ __global__ void __launch_bounds__(256)
 k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slots,
          const Node* __restrict__ nodes, const Block* __restrict__ blocks,
          const double* __restrict__ d64, const double* __restrict__ lld64, double rtol,
-         double widen, double* __restrict__ work) {
+         double widen, double* __restrict__ work, int64_t skip_n) {
     constexpr int G = 256 / L;
     const int g = threadIdx.x / L;
     const int q = threadIdx.x % L;
     const int64_t idx = (int64_t)blockIdx.x * G + g;
-    const bool active = idx < count;
+    bool active = idx < count;
     int64_t s = 0, n = 0, j = 0;
     double lo = 0.0, hi = 0.0;
     const double* D = d64;
@@ -814,6 +814,11 @@ k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slo
         j = sl.idx;
         lo = sl.lo;
         hi = sl.hi;
+        // slots of nodes this long are served by the staged kernel
+        if (n >= skip_n) {
+            active = false;
+            n = 0;
+        }
     }
     const int lane = threadIdx.x & 63;
     const int gbase = lane - q;  // first lane of this group within the wave
@@ -1603,6 +1608,106 @@ __device__ __forceinline__ SweepStep<Y> get_sweep_step(const SweepWin<Y>& win, i
     return w;
 }
 
+// LDS window of the binary64 twist search: the copy's rows of both streams,
+// roles swapped in the bottom stream as in the sweeps.
+struct TwistWin {
+    double f[2][2][SW];  // [buffer][stream][step]
+    double g[2][2][SW];
+};
+
+// One phase of the binary64 twist search for every lane of the chunk's wave
+// (all 64 threads call it).  In this phase stream 0 (top lanes) starts at
+// step s0t and stream 1 (bottom lanes) at step s0b; this lane runs cnt steps.
+// Step s handles row k = s (top, stationary transform) or k = n-1-s (bottom,
+// progressive transform).  Without `combine` the quotient s_k = a/b (resp.
+// p_k) is stored in the lane's tile column; with it, the value the other lane
+// stored for row k is combined into |gamma_k| = |s_k + p_k + tau| and the
+// minimum is tracked.  The tile values are read one block of 8 steps ahead.
+__device__ void prepass_staged(bool top, const double* __restrict__ D,
+                               const double* __restrict__ LL, int64_t n, double tau, int64_t s0t,
+                               int64_t s0b, int64_t cnt, double& a, double& b, bool combine,
+                               double* __restrict__ col, double& gmin, int64_t& rmin,
+                               TwistWin& win) {
+    const int t = threadIdx.x;
+    const int side = top ? 0 : 1;
+    const int64_t s0 = top ? s0t : s0b;
+    int64_t cmax = cnt;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) cmax = max(cmax, (int64_t)__shfl_xor(cmax, off, 64));
+    auto load = [&](int stream, int64_t o) -> double2 {
+        const int64_t sidx = (stream == 0 ? s0t : s0b) + o;
+        if (sidx >= n) return make_double2(0.0, 0.0);
+        if (stream == 0) return make_double2(D[sidx], LL[sidx]);
+        const int64_t ka = n - 2 - sidx;  // advance row of k = n-1-s (guard row at -1)
+        return make_double2(LL[ka], D[ka]);
+    };
+    auto rowk = [&](int64_t o) -> int64_t { return top ? s0 + o : n - 1 - (s0 + o); };
+    {
+        const double2 w = load(t >> 5, t & 31);
+        win.f[0][t >> 5][t & 31] = w.x;
+        win.g[0][t >> 5][t & 31] = w.y;
+    }
+    __syncthreads();
+    // tile values of the next block of 8 steps
+    double ctn[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) ctn[v] = (combine && v < cnt) ? col[rowk(v) * 32] : 0.0;
+    auto step = [&](double f, double g, double ct, int64_t o) {
+        const int64_t k = rowk(o);
+        const double q = a / b;
+        if (combine) {
+            const double gv = fabs(q + ct + tau);
+            const bool take = gv < gmin || (gv == gmin && k < rmin);
+            gmin = take ? gv : gmin;
+            rmin = take ? k : rmin;
+        } else {
+            col[k * 32] = q;
+        }
+        const double c = __fma_rn(f, b, a);
+        a = __fma_rn(-tau, c, g * a);
+        b = c;
+        if ((o & 3) == 3) {
+            const int em = max(dexp(a), dexp(b));
+            a = __builtin_ldexp(a, -em);
+            b = __builtin_ldexp(b, -em);
+        }
+    };
+    for (int64_t o0 = 0; o0 < cmax; o0 += SW) {
+        const int cur = (int)((o0 / SW) & 1);
+        const double2 nx = load(t >> 5, o0 + SW + (t & 31));
+        if (o0 < cnt) {
+            const int m = (int)min<int64_t>(SW, cnt - o0);
+            int u = 0;
+            for (; u + 8 <= m; u += 8) {
+                double ctc[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) ctc[v] = ctn[v];
+                if (combine) {
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) {
+                        const int64_t o = o0 + u + 8 + v;
+                        ctn[v] = (o < cnt) ? col[rowk(o) * 32] : 0.0;
+                    }
+                }
+                double f[8], g[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    f[v] = win.f[cur][side][u + v];
+                    g[v] = win.g[cur][side][u + v];
+                }
+#pragma unroll
+                for (int v = 0; v < 8; ++v) step(f[v], g[v], ctc[v], o0 + u + v);
+            }
+            // tail of the phase (fewer than 8 steps): its tile values are in ctn
+            for (int v = 0; u < m; ++u, ++v)
+                step(win.f[cur][side][u], win.g[cur][side][u], ctn[v & 7], o0 + u);
+        }
+        win.f[cur ^ 1][t >> 5][t & 31] = nx.x;
+        win.g[cur ^ 1][t >> 5][t & 31] = nx.y;
+        __syncthreads();
+    }
+}
+
 // One sweep of every lane of the chunk's wave (all 64 threads call it; lanes
 // with steps == 0 only help with the loads).  Same arithmetic as the
 // per-lane sweep: the top lane runs the stationary transform over rows 0..r,
@@ -1712,6 +1817,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
       double eps_y, RqiResult* __restrict__ res, unsigned long long* __restrict__ counters,
       double* __restrict__ work) {
     __shared__ SweepWin<Y> win;
+    __shared__ TwistWin twin;
     const int lane = threadIdx.x;
     const int pair = lane >> 1;
     const bool top = (lane & 1) == 0;
@@ -1747,9 +1853,9 @@ k_rqi(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
     const int64_t len2 = active ? (top ? n - hh : hh) : 0;
     double gmin = INFINITY;
     int64_t rmin = n / 2;
-    prepass_phase(top, D64, LL64, n, tau0, 0, len1, a, b, false, tile, gmin, rmin);
+    prepass_staged(top, D64, LL64, n, tau0, 0, 0, len1, a, b, false, tile, gmin, rmin, twin);
     __syncthreads();
-    prepass_phase(top, D64, LL64, n, tau0, len1, len2, a, b, true, tile, gmin, rmin);
+    prepass_staged(top, D64, LL64, n, tau0, hh, n - hh, len2, a, b, true, tile, gmin, rmin, twin);
     {
         const double go = __shfl_xor(gmin, 1, 64);
         const int64_t ro = __shfl_xor(rmin, 1, 64);

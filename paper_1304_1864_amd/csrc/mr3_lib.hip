@@ -47,6 +47,70 @@ struct SelectDepth {
     }
 };
 
+// Block records of every problem from the preprocessing output (one thread
+// per problem; boff[p] = first block index of problem p), with the number of
+// slots each block needs: the requested indices plus one helper on each side
+// that has a neighbour (the helpers carry the gaps to eigenvalues outside the
+// range).
+__global__ void k_blocks(const ProbDesc* __restrict__ probs, const ProbInfo* __restrict__ pinfo,
+                         const BlockInfo* __restrict__ binfo, const int64_t* __restrict__ boff,
+                         int64_t count, Block* __restrict__ blocks, int64_t* __restrict__ nslot) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    const ProbDesc pd = probs[p];
+    const int nb = pinfo[p].nblocks;
+    for (int b = 0; b < nb; ++b) {
+        const BlockInfo x = binfo[pd.row0 + b];
+        Block bk{};
+        bk.prob = (int)p;
+        bk.row0 = pd.row0 + x.start;
+        bk.start = x.start;
+        bk.n = x.n;
+        bk.il = max((int64_t)1, x.il);
+        bk.iu = min(x.n, x.iu);
+        bk.gl = x.gl;
+        bk.gu = x.gu;
+        const int64_t ns = (bk.il <= bk.iu) ? (bk.iu - bk.il + 1) + (bk.il > 1) + (bk.iu < bk.n) : 0;
+        blocks[boff[p] + b] = bk;
+        nslot[boff[p] + b] = ns;
+    }
+}
+
+// slot ranges of the blocks (exclusive sum of nslot in slot0)
+__global__ void k_blocks_slots(Block* __restrict__ blocks, const int64_t* __restrict__ nslot,
+                               const int64_t* __restrict__ slot0, int64_t nb) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    blocks[b].slot0 = slot0[b];
+    blocks[b].nslot = nslot[b];
+}
+
+// the slots of block blockIdx.x: local index, output column (-1 helper, -2
+// decided later for split problems), gap markers
+__global__ void k_slots(const Block* __restrict__ blocks, const ProbInfo* __restrict__ pinfo,
+                        Slot* __restrict__ slots) {
+    const Block bk = blocks[blockIdx.x];
+    if (bk.nslot == 0) return;
+    const bool multi = pinfo[bk.prob].nblocks > 1;
+    const int64_t lo_i = bk.il > 1 ? bk.il - 1 : bk.il;
+    const int64_t hi_i = bk.iu < bk.n ? bk.iu + 1 : bk.iu;
+    for (int64_t i = lo_i + threadIdx.x; i <= hi_i; i += blockDim.x) {
+        Slot sl{};
+        sl.idx = i;
+        const bool req = (i >= bk.il && i <= bk.iu);
+        sl.out = req ? (multi ? -2 : i - bk.il) : -1;
+        sl.lgap = (i == lo_i) ? (i == 1 ? MR3_BIG : -1.0) : 0.0;
+        sl.rgap = (i == hi_i) ? (i == bk.n ? MR3_BIG : -1.0) : 0.0;
+        sl.kind = KIND_NONE;
+        slots[bk.slot0 + (i - lo_i)] = sl;
+    }
+}
+
+__global__ void k_iota(int64_t* __restrict__ v, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) v[i] = i;
+}
+
 // Node-pure chunks of at most 32 singletons.  The singleton list is ordered by
 // slot and every node owns a contiguous slot range, so each node's singletons
 // form one run of the list; chunks split the runs at every 32nd entry.
@@ -167,11 +231,45 @@ struct Buf {
     }
 };
 
+// Pinned host staging for the driver's small transfers: copies from pinned
+// memory are asynchronous (a pageable copy would wait for the stream), and the
+// space handed out during a solve is not reused before the next solve, which
+// starts only after the previous one has synchronised.
+struct Staging {
+    struct Chunk {
+        void* p;
+        size_t cap, used;
+    };
+    std::vector<Chunk> chunks;
+    void* get(size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        for (auto& c : chunks)
+            if (c.cap - c.used >= bytes) {
+                void* r = static_cast<char*>(c.p) + c.used;
+                c.used += bytes;
+                return r;
+            }
+        size_t cap = std::max<size_t>(bytes, (size_t)4 << 20);
+        if (!chunks.empty()) cap = std::max(cap, 2 * chunks.back().cap);
+        void* p = nullptr;
+        if (hipHostMalloc(&p, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+        chunks.push_back(Chunk{p, cap, bytes});
+        return p;
+    }
+    void reset() {
+        for (auto& c : chunks) c.used = 0;
+    }
+    void release() {
+        for (auto& c : chunks) (void)hipHostFree(c.p);
+        chunks.clear();
+    }
+};
+
 enum BufId {
     B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BLOCKS, B_SLOTS, B_NODES, B_REPD, B_REPL, B_REPE,
     B_D64, B_L64, B_P, B_PE, B_Q, B_QE, B_LIST, B_LIST2, B_CNT, B_TILEOFF, B_TILES, B_RES,
     B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_M, B_BAD, B_COUNTERS,
-    B_BOFF, B_CREC, B_CHECK, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
+    B_BOFF, B_CREC, B_CHECK, B_NSLOT, B_SLOT0, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
 };
 
 // singleton work of tree level d runs on the handle's side stream with the
@@ -196,6 +294,8 @@ struct mr3_handle_s {
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_side[2] = {nullptr, nullptr};
     bool side_pending[2] = {false, false};
+    mr3::Staging stage;      // pinned host staging
+    bool clean_exit = true;  // the last solve synchronised its stream
 };
 
 namespace mr3 {
@@ -303,20 +403,31 @@ static Params effective(const mr3_handle_s* h, int precision) {
     return p;
 }
 
+// staging arena of the solve running on this thread (set by solve_impl)
+static thread_local Staging* g_stage = nullptr;
+
 template <class T>
 static hipError_t upload(Buf& b, const std::vector<T>& v, hipStream_t st) {
     hipError_t e = b.ensure(std::max<size_t>(1, v.size()) * sizeof(T));
     if (e != hipSuccess || v.empty()) return e;
-    return hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+    const size_t bytes = v.size() * sizeof(T);
+    void* pin = g_stage ? g_stage->get(bytes) : nullptr;
+    if (!pin) return hipMemcpyAsync(b.p, v.data(), bytes, hipMemcpyHostToDevice, st);
+    std::memcpy(pin, v.data(), bytes);
+    return hipMemcpyAsync(b.p, pin, bytes, hipMemcpyHostToDevice, st);
 }
 
 template <class T>
 static hipError_t download(std::vector<T>& v, const void* src, size_t count, hipStream_t st) {
     v.resize(count);
     if (count == 0) return hipSuccess;
-    hipError_t e = hipMemcpyAsync(v.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, st);
+    const size_t bytes = count * sizeof(T);
+    void* pin = g_stage ? g_stage->get(bytes) : nullptr;
+    hipError_t e = hipMemcpyAsync(pin ? pin : v.data(), src, bytes, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
-    return hipStreamSynchronize(st);
+    e = hipStreamSynchronize(st);
+    if (e == hipSuccess && pin) std::memcpy(v.data(), pin, bytes);
+    return e;
 }
 
 // multisection shape: L lanes per eigenvalue, P points per lane and pass
@@ -327,14 +438,14 @@ struct BisectShape {
 static void launch_bisect(BisectShape sh, const int64_t* list, int64_t count, Slot* slots,
                           const Node* nodes, const Block* blocks, const double* d64,
                           const double* l64, double rtol, double widen, double* work,
-                          hipStream_t st) {
+                          int64_t skip_n, hipStream_t st) {
     if (count <= 0) return;
     const int G = 256 / sh.L;
     const dim3 grid((unsigned)((count + G - 1) / G));
 #define MR3_BIS(LL, PP)                                                                        \
     if (sh.L == LL && sh.P == PP) {                                                            \
         hipLaunchKernelGGL((k_bisect<LL, PP>), grid, dim3(256), 0, st, list, count, slots,     \
-                           nodes, blocks, d64, l64, rtol, widen, work);                        \
+                           nodes, blocks, d64, l64, rtol, widen, work, skip_n);                \
         return;                                                                                \
     }
     MR3_BIS(1, 1) MR3_BIS(1, 2) MR3_BIS(1, 4)
@@ -346,7 +457,7 @@ static void launch_bisect(BisectShape sh, const int64_t* list, int64_t count, Sl
     MR3_BIS(64, 1) MR3_BIS(64, 2) MR3_BIS(64, 4)
 #undef MR3_BIS
     hipLaunchKernelGGL((k_bisect<1, 4>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
-                       list, count, slots, nodes, blocks, d64, l64, rtol, widen, work);
+                       list, count, slots, nodes, blocks, d64, l64, rtol, widen, work, skip_n);
 }
 
 static void launch_bisect_staged(BisectShape sh, const BisWG* wgs, int64_t nwg, const int64_t* list,
@@ -379,6 +490,12 @@ static int64_t slice_points(int64_t k) {
     return M;
 }
 
+// development aid: MR3_NO_STAGE=1 sends every node to the per-lane kernel
+static bool no_stage() {
+    static const bool v = std::getenv("MR3_NO_STAGE") != nullptr;
+    return v;
+}
+
 // nodes of at least this many rows are bisected by the LDS-staged kernel with
 // node-pure workgroups; shorter ones (which stay in cache) by the per-lane one
 constexpr int64_t STAGE_MIN_N = 2048;
@@ -390,7 +507,7 @@ struct BisectPlan {
     std::vector<BisWG> wgs;
     int64_t n_staged = 0;
     void add(int node, int64_t n, int64_t first, int64_t count, int G, std::vector<int64_t>& rest) {
-        if (n >= STAGE_MIN_N && std::getenv("MR3_NO_STAGE") == nullptr) {
+        if (n >= STAGE_MIN_N && !no_stage()) {
             for (int64_t o = 0; o < count; o += G)
                 wgs.push_back(BisWG{(int64_t)list.size() + o, (int)std::min<int64_t>(G, count - o), node});
             for (int64_t i = 0; i < count; ++i) list.push_back(first + i);
@@ -443,6 +560,15 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         h->side_pending[0] = h->side_pending[1] = false;
     }
     hipStream_t side = h->side;
+    // pinned staging space is reused from the last solve, which has finished
+    // unless it left with an error
+    if (!h->clean_exit) HIPCHK(hipDeviceSynchronize());
+    h->clean_exit = false;
+    h->stage.reset();
+    struct StageScope {
+        StageScope(Staging* s) { g_stage = s; }
+        ~StageScope() { g_stage = nullptr; }
+    } stage_scope(&h->stage);
     // every exit makes `st` wait for the side stream, so that synchronizing
     // the caller's stream covers all of this call's work
     struct SideJoin {
@@ -481,7 +607,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         R += pd.n;
         m_out[p] = 0;
     }
-    if (R == 0) { h->stats = stats; return MR3_OK; }
+    if (R == 0) { h->stats = stats; h->clean_exit = true; return MR3_OK; }
     HIPCHK(upload(B[B_PROBS], probs, st));
     HIPCHK(B[B_PINFO].ensure(sizeof(ProbInfo) * count));
     HIPCHK(B[B_TD].ensure(sizeof(double) * (R + 2 * GUARD)));
@@ -495,66 +621,50 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(download(pinfo, B[B_PINFO].p, (size_t)count, st));
     for (int64_t p = 0; p < count; ++p)
         if (pinfo[p].err) return -6;  // non-finite entry in d or e
-    // ---- blocks (gather the per-problem block records) ----
-    std::vector<Block> blocks;
-    std::vector<BlockInfo> bi;
-    {
-        // block records live at binfo[row0 + b]; fetch each problem's slice
-        std::vector<BlockInfo> all;
-        // one contiguous copy when the blocks are dense enough, else per problem
-        HIPCHK(download(all, B[B_BINFO].p, (size_t)R, st));
-        for (int64_t p = 0; p < count; ++p)
-            for (int b = 0; b < pinfo[p].nblocks; ++b) bi.push_back(all[probs[p].row0 + b]);
-    }
+    // ---- blocks and slots, assembled on the device ----
     std::vector<int> multi(count, 0);
-    std::vector<Slot> slots;
     std::vector<int64_t> m_p(count, 0);
-    {
-        size_t k = 0;
-        for (int64_t p = 0; p < count; ++p) {
-            multi[p] = pinfo[p].nblocks > 1;
-            for (int b = 0; b < pinfo[p].nblocks; ++b, ++k) {
-                const BlockInfo& x = bi[k];
-                Block bk{};
-                bk.prob = (int)p;
-                bk.row0 = probs[p].row0 + x.start;
-                bk.start = x.start;
-                bk.n = x.n;
-                bk.il = std::max<int64_t>(1, x.il);
-                bk.iu = std::min<int64_t>(x.n, x.iu);
-                bk.gl = x.gl;
-                bk.gu = x.gu;
-                bk.slot0 = (int64_t)slots.size();
-                if (bk.il <= bk.iu) {
-                    const int64_t lo_i = bk.il > 1 ? bk.il - 1 : bk.il;
-                    const int64_t hi_i = bk.iu < bk.n ? bk.iu + 1 : bk.iu;
-                    for (int64_t i = lo_i; i <= hi_i; ++i) {
-                        Slot s{};
-                        s.idx = i;
-                        const bool req = (i >= bk.il && i <= bk.iu);
-                        s.out = req ? (multi[p] ? -2 : (i - bk.il) + (probs[p].range == RANGE_INDEX && !multi[p] ? 0 : 0)) : -1;
-                        if (req && !multi[p]) s.out = i - bk.il;
-                        s.lgap = (i == lo_i) ? (i == 1 ? MR3_BIG : -1.0) : 0.0;
-                        s.rgap = (i == hi_i) ? (i == bk.n ? MR3_BIG : -1.0) : 0.0;
-                        s.kind = KIND_NONE;
-                        slots.push_back(s);
-                    }
-                    m_p[p] += bk.iu - bk.il + 1;
-                }
-                bk.nslot = (int64_t)slots.size() - bk.slot0;
-                blocks.push_back(bk);
-            }
-        }
+    std::vector<int64_t> boff((size_t)count + 1, 0);
+    for (int64_t p = 0; p < count; ++p) {
+        multi[p] = pinfo[p].nblocks > 1;
+        boff[p + 1] = boff[p] + pinfo[p].nblocks;
     }
-    const int64_t NB = (int64_t)blocks.size();
-    const int64_t K = (int64_t)slots.size();
+    const int64_t NB = boff[count];
+    HIPCHK(upload(B[B_BOFF], boff, st));
+    HIPCHK(B[B_BLOCKS].ensure(sizeof(Block) * (size_t)std::max<int64_t>(NB, 1)));
+    HIPCHK(B[B_NSLOT].ensure(sizeof(int64_t) * (size_t)(NB + 1)));
+    HIPCHK(B[B_SLOT0].ensure(sizeof(int64_t) * (size_t)(NB + 1)));
+    int64_t* nslot_d = B[B_NSLOT].as<int64_t>();
+    int64_t* slot0_d = B[B_SLOT0].as<int64_t>();
+    std::vector<Block> blocks;
+    if (NB > 0) {
+        HIPCHK(hipMemsetAsync(nslot_d + NB, 0, sizeof(int64_t), st));
+        hipLaunchKernelGGL(k_blocks, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                           B[B_PROBS].as<ProbDesc>(), B[B_PINFO].as<ProbInfo>(),
+                           B[B_BINFO].as<BlockInfo>(), B[B_BOFF].as<int64_t>(), count,
+                           B[B_BLOCKS].as<Block>(), nslot_d);
+        size_t tb = 0;
+        HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, nslot_d, slot0_d, NB + 1, st));
+        HIPCHK(B[B_CUBTMP].ensure(tb + 256));
+        tb = B[B_CUBTMP].cap;
+        HIPCHK(hipcub::DeviceScan::ExclusiveSum(B[B_CUBTMP].p, tb, nslot_d, slot0_d, NB + 1, st));
+        hipLaunchKernelGGL(k_blocks_slots, dim3((unsigned)((NB + 255) / 256)), dim3(256), 0, st,
+                           B[B_BLOCKS].as<Block>(), nslot_d, slot0_d, NB);
+        HIPCHK(download(blocks, B[B_BLOCKS].p, (size_t)NB, st));
+    }
+    int64_t K = 0;
+    for (const Block& bk : blocks) {
+        K += bk.nslot;
+        if (bk.il <= bk.iu) m_p[bk.prob] += bk.iu - bk.il + 1;
+    }
     stats.n_blocks = NB;
     for (int64_t p = 0; p < count; ++p) { m_out[p] = m_p[p]; stats.n_eigenpairs += m_p[p]; }
-    if (K == 0) { h->stats = stats; return MR3_OK; }
+    if (K == 0) { h->stats = stats; h->clean_exit = true; return MR3_OK; }
+    HIPCHK(B[B_SLOTS].ensure(sizeof(Slot) * (size_t)K));
+    hipLaunchKernelGGL(k_slots, dim3((unsigned)NB), dim3(256), 0, st, B[B_BLOCKS].as<Block>(),
+                       B[B_PINFO].as<ProbInfo>(), B[B_SLOTS].as<Slot>());
     // nodes: roots first (node index == block index), children appended
     int64_t node_cap = NB + K;  // each cluster head creates at most one node per level
-    HIPCHK(upload(B[B_BLOCKS], blocks, st));
-    HIPCHK(upload(B[B_SLOTS], slots, st));
     HIPCHK(B[B_NODES].ensure(sizeof(Node) * (size_t)std::max<int64_t>(node_cap, 1)));
     // representation pool: root rows first
     int64_t pool_rows = R;
@@ -603,16 +713,25 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     prof.end(st);
     HIPCHK(hipGetLastError());
     // ---- a3: bisection of every slot on its root ----
+    // the slot list is the identity; staged workgroups of a large block
+    // serve its slot range directly, and the per-lane kernel skips those slots
     BisectShape L = pick_shape(K, prm.lanes_per_eig, prm.points_per_lane);
-    BisectPlan rplan;
-    {
-        std::vector<int64_t> rest;
-        for (int64_t b = 0; b < NB; ++b)
-            rplan.add((int)b, blocks[b].n, blocks[b].slot0, blocks[b].nslot, 256 / L.L, rest);
-        rplan.finish(rest);
+    std::vector<BisWG> rwgs;
+    int64_t k_small = 0;
+    for (int64_t b = 0; b < NB; ++b) {
+        if (blocks[b].n >= STAGE_MIN_N && !no_stage()) {
+            const int G = 256 / L.L;
+            for (int64_t o = 0; o < blocks[b].nslot; o += G)
+                rwgs.push_back(BisWG{blocks[b].slot0 + o,
+                                     (int)std::min<int64_t>(G, blocks[b].nslot - o), (int)b});
+        } else {
+            k_small += blocks[b].nslot;
+        }
     }
-    HIPCHK(upload(B[B_LIST], rplan.list, st));
-    HIPCHK(upload(B[B_BWG], rplan.wgs, st));
+    HIPCHK(B[B_LIST].ensure(sizeof(int64_t) * (size_t)K));
+    hipLaunchKernelGGL(k_iota, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st,
+                       B[B_LIST].as<int64_t>(), K);
+    HIPCHK(upload(B[B_BWG], rwgs, st));
     // intervals from the binary64 copy are widened by k n eps_d |lambda| before
     // classification: k = 10 on the double-double path (relative robustness
     // constant of the copy, Sec. 3.2 "Arithmetic used to approximate
@@ -643,12 +762,13 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             }
         }
     }
-    launch_bisect_staged(L, B[B_BWG].as<BisWG>(), (int64_t)rplan.wgs.size(), B[B_LIST].as<int64_t>(),
+    launch_bisect_staged(L, B[B_BWG].as<BisWG>(), (int64_t)rwgs.size(), B[B_LIST].as<int64_t>(),
                          dslots, dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
                          prm.bisect_rel, widen_root, work, 0, st);
-    launch_bisect(L, B[B_LIST].as<int64_t>() + rplan.n_staged, K - rplan.n_staged, dslots, dnodes,
-                  dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel,
-                  widen_root, work, st);
+    if (k_small > 0)
+        launch_bisect(L, B[B_LIST].as<int64_t>(), K, dslots, dnodes, dblocks,
+                      B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel, widen_root,
+                      work, no_stage() ? INT64_MAX : STAGE_MIN_N, st);
     prof.end(st);
     HIPCHK(hipGetLastError());
     // ---- output columns of split problems: order by eigenvalue ----
@@ -808,6 +928,30 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                     std::fprintf(stderr, "[mr3]   iteration histogram:");
                     for (int k = 0; k < 12; ++k) std::fprintf(stderr, " %d:%lld", k, (long long)hist[k]);
                     std::fprintf(stderr, "\n");
+                    // sweep lengths: per pair max(r+1, n-r), per chunk the max over its pairs
+                    std::vector<ChunkInfo> cks;
+                    HIPCHK(download(cks, SCK.p, (size_t)nchunk, st));
+                    std::vector<Slot> sl;
+                    std::vector<int64_t> ls;
+                    std::vector<Node> nds;
+                    HIPCHK(download(sl, dslots, (size_t)K, st));
+                    HIPCHK(download(ls, SL.p, (size_t)S, st));
+                    HIPCHK(download(nds, dnodes, (size_t)n_nodes, st));
+                    double sp = 0, sc = 0, sn = 0;
+                    for (const ChunkInfo& c : cks) {
+                        const int64_t nn = blocks[nds[sl[ls[c.begin]].node].block].n;
+                        int64_t mx = 0;
+                        for (int q = 0; q < c.count; ++q) {
+                            const int64_t r = rr[c.begin + q].r;
+                            const int64_t len = std::max(r + 1, nn - r);
+                            sp += (double)len;
+                            mx = std::max(mx, len);
+                        }
+                        sc += (double)mx * c.count;
+                        sn += (double)nn * c.count;
+                    }
+                    std::fprintf(stderr, "[mr3]   sweep length / n: pair mean %.3f, chunk max (pair-weighted) %.3f, chunks %lld\n",
+                                 sp / sn, sc / sn, (long long)nchunk);
                 }
                 if (std::getenv("MR3_DEBUG")[0] == '2') {
                     std::vector<RqiResult> rr;
@@ -929,7 +1073,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                              widen_root, work, 1, st);
         launch_bisect(L, B[B_LIST].as<int64_t>() + cplan.n_staged, KC - cplan.n_staged, dslots,
                       dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
-                      prm.bisect_rel, widen_root, work, st);
+                      prm.bisect_rel, widen_root, work, INT64_MAX, st);
         prof.end(st);
         prof.begin(MR3_STAGE_VERIFY, st);
         if (is_dd) {
@@ -1038,6 +1182,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             HIPCHK(hipStreamSynchronize(st));
         }
     }
+    h->clean_exit = true;
     return MR3_OK;
 }
 
@@ -1154,6 +1299,7 @@ int mr3_destroy(mr3_handle h) {
     for (auto& ev : h->ev_side)
         if (ev) (void)hipEventDestroy(ev);
     if (h->side) (void)hipStreamDestroy(h->side);
+    h->stage.release();
     delete h;
     return MR3_OK;
 }
