@@ -117,9 +117,43 @@ __device__ __forceinline__ double mul(double a, double b) { return a * b; }
 __device__ __forceinline__ double div(double a, double b) { return a / b; }
 __device__ __forceinline__ double add_acc(double a, double b) { return a + b; }
 
-// a * b + c with one rounding in double; in dd a product then a sum
+// a * b + c with one rounding in double.  In dd the product's error term is
+// carried unnormalised into a sloppy sum: the result is the exact sum of
+// (a b)(1 + d1) and c(1 + d2) with |d1|, |d2| a few u^2 -- the same
+// componentwise backward error as a product followed by add().
 __device__ __forceinline__ double mul_add(double a, double b, double c) { return __fma_rn(a, b, c); }
-__device__ __forceinline__ dd mul_add(dd a, dd b, dd c) { return add(mul(a, b), c); }
+__device__ __forceinline__ dd mul_add(dd a, dd b, dd c) {
+    const double p = a.hi * b.hi;
+    double e = __fma_rn(a.hi, b.hi, -p);
+    e = __fma_rn(a.hi, b.lo, e);
+    e = __fma_rn(a.lo, b.hi, e);
+    const dd s = two_sum(p, c.hi);
+    return fast_two_sum(s.hi, s.lo + (e + c.lo));
+}
+
+// g * a - t * c: in double two roundings; in dd both products' error terms are
+// carried unnormalised into one sloppy sum (componentwise backward error a few
+// u^2 on each product, as for sub(mul(g, a), mul(t, c)))
+__device__ __forceinline__ double mul_sub(double g, double a, double t, double c) {
+    return __fma_rn(-t, c, g * a);
+}
+__device__ __forceinline__ dd mul_sub(dd g, dd a, dd t, dd c) {
+    const double p = g.hi * a.hi;
+    double e = __fma_rn(g.hi, a.hi, -p);
+    e = __fma_rn(g.hi, a.lo, e);
+    e = __fma_rn(g.lo, a.hi, e);
+    const double q = t.hi * c.hi;
+    double f = __fma_rn(t.hi, c.hi, -q);
+    f = __fma_rn(t.hi, c.lo, f);
+    f = __fma_rn(t.lo, c.hi, f);
+    const dd s = two_sum(p, -q);
+    return fast_two_sum(s.hi, s.lo + (e - f));
+}
+
+// product of the leading parts, for values needed to binary64 accuracy only
+// (relative error below 3 * 2^-53 in dd)
+__device__ __forceinline__ double prod_hi(double a, double b) { return a * b; }
+__device__ __forceinline__ double prod_hi(dd a, dd b) { return a.hi * b.hi; }
 
 // x * 2^k (exact unless it under/overflows)
 __device__ __forceinline__ double y_ldexp(double a, int k) { return __builtin_ldexp(a, k); }

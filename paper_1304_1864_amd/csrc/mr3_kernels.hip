@@ -232,7 +232,7 @@ __device__ int negcount_y(const Y* __restrict__ D, const Y* __restrict__ LL, int
     for (int64_t i = 0; i < n; ++i) {
         Y c = mul_add(D[i], b, a);
         neg_ += sign_differs(hi_of(c), hi_of(b));
-        a = sub(mul(LL[i], a), mul(x, c));
+        a = mul_sub(LL[i], a, x, c);
         b = c;
         if ((i & 3) == 3) {
             const int em = max(y_exp(a), y_exp(b));
@@ -845,6 +845,7 @@ k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slo
     // multisection until the relative width reaches rtol
     const double lo0 = lo, hi0 = hi;
     bool busy = active;
+    int passes = 0;
     for (int it = 0; it < 400; ++it) {
         if (busy) {
             const double w = hi - lo;
@@ -852,6 +853,7 @@ k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slo
             if (w <= rtol * scale || w <= 1e-300 || !(w > 0.0)) busy = false;
         }
         if (!__any(busy)) break;
+        passes += busy ? 1 : 0;
         // L lanes x PTS points: point t = q*PTS + p sits at lo + (t+1) h
         constexpr int NP = L * PTS;
         const double h = (hi - lo) / (double)(NP + 1);
@@ -886,6 +888,10 @@ k_bisect(const int64_t* __restrict__ list, int64_t count, Slot* __restrict__ slo
         // algorithmic work: halvings plain bisection needs for this bracket
         const double bits = log2(fmax((lo0 - hi0 == 0.0) ? 1.0 : (hi0 - lo0) / fmax(hi - lo, 1e-300), 1.0));
         atomicAdd(&work[0], bits * (double)n);
+        // diagnostics: largest and total number of multisection passes
+        atomicMax(reinterpret_cast<unsigned long long*>(&work[6]),
+                  (unsigned long long)__double_as_longlong((double)passes));
+        atomicAdd(&work[7], (double)passes);
         const double w = widen * (double)n * fmax(fabs(lo), fabs(hi));
         slots[s].lo = lo - w;
         slots[s].hi = hi + w;
@@ -1028,6 +1034,7 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
     }
     const double lo0 = lo, hi0 = hi;
     bool busy = active;
+    int passes = 0;
     for (int it = 0; it < 400; ++it) {
         if (busy) {
             const double wd = hi - lo;
@@ -1035,6 +1042,7 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
             if (wd <= rtol * scale || wd <= 1e-300 || !(wd > 0.0)) busy = false;
         }
         if (!__syncthreads_or(busy)) break;
+        passes += busy ? 1 : 0;
         constexpr int NP = L * PTS;
         const double h = (hi - lo) / (double)(NP + 1);
         double xs[PTS];
@@ -1062,6 +1070,10 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
     if (active && q == 0) {
         const double bits = log2(fmax((lo0 - hi0 == 0.0) ? 1.0 : (hi0 - lo0) / fmax(hi - lo, 1e-300), 1.0));
         atomicAdd(&work[0], bits * (double)n);
+        // diagnostics: largest and total number of multisection passes
+        atomicMax(reinterpret_cast<unsigned long long*>(&work[6]),
+                  (unsigned long long)__double_as_longlong((double)passes));
+        atomicAdd(&work[7], (double)passes);
         const double wd = widen * (double)n * fmax(fabs(lo), fabs(hi));
         slots[s].lo = lo - wd;
         slots[s].hi = hi + wd;
@@ -1158,7 +1170,7 @@ __device__ int staged_count_y(const Y* __restrict__ D, const Y* __restrict__ LL,
             auto row = [&](const Y& dv, const Y& lv, int i) {
                 const Y c = mul_add(dv, b, a);
                 negc += sign_differs(hi_of(c), hi_of(b));
-                a = sub(mul(lv, a), mul(x, c));
+                a = mul_sub(lv, a, x, c);
                 b = c;
                 if ((i & 3) == 3) {
                     const int em = max(y_exp(a), y_exp(b));
@@ -1309,217 +1321,24 @@ k_classify(const int64_t* __restrict__ node_list, int64_t count, const Node* __r
 // a6: Rayleigh quotient iteration with twisted factorizations
 // one wave per 32 singletons; lane 2q sweeps top-down, lane 2q+1 bottom-up
 // ---------------------------------------------------------------------------
+// Per-lane sweep output.  z is stored in a scaled frame: when a stored value
+// would pass about 2^300 the frame is rebased (an "event" at that row).  The
+// output kernel multiplies values stored before the last event by ev2f and
+// zeroes those stored before the one-but-last, which lie below 2^-250 of the
+// final maximum.  z values are products of the leading parts (binary64
+// accuracy, all the output needs).
 template <class Y>
-struct Half {  // per-lane sweep output
+struct Half {
     Y sp;        // s_r (top lane) or p_r (bottom lane)
     double zr;   // z at the twist row, in the lane's storage frame
     double ss;   // sum of squares of stored z, storage frame
-    double zmax; // largest |stored z| and its signed value / row
-    double zmaxv;
+    double zmax; // largest |stored z| and its row
     int64_t zmaxk;
-    int64_t ev1, ev2;  // rebasing events (see below)
+    int64_t ev1, ev2;  // rebasing events
     double ev2f;
 };
 
-// One sweep of one lane at shift tau with twist index r.  The top lane
-// (top == true) runs the stationary transform over rows 0..r, the bottom lane
-// the progressive one over rows n-1..r, and each stores its part of z
-// (rows < r resp. > r) into its tile column.  Stored values are kept below
-// about 2^300 by rebasing the storage exponent; the output kernel multiplies
-// values stored before the last rebase by ev2f and zeroes those stored before
-// the one-but-last (they are below 2^-250 of the final maximum).
-// One phase of the binary64 twist search.  Step s handles row k = s (top
-// lane, stationary transform) or k = n-1-s (bottom lane, progressive
-// transform).  Without `combine` the quotient s_k = a/b (resp. p_k) is stored
-// in the tile column; with it, the value the other lane stored for row k is
-// combined into |gamma_k| = |s_k + p_k + tau| and the minimum is tracked.
-// Row data are double buffered like in negcount64.
-__device__ __forceinline__ void prepass_phase(bool top, const double* __restrict__ D,
-                                              const double* __restrict__ LL, int64_t n, double tau,
-                                              int64_t s0, int64_t cnt, double& a, double& b,
-                                              bool combine, double* __restrict__ col, double& gmin,
-                                              int64_t& rmin) {
-    constexpr int U = 8;
-    if (cnt <= 0) return;
-    double nd[U], nl[U], nt[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t sidx = s0 + u;
-        const int64_t k = top ? sidx : n - 1 - sidx;
-        const int64_t ka = top ? k : k - 1;
-        nd[u] = D[ka];
-        nl[u] = LL[ka];
-        nt[u] = combine ? col[k * 32] : 0.0;
-    }
-    auto body = [&](double dd, double ll, double tt, int64_t sidx, int u) {
-        const int64_t k = top ? sidx : n - 1 - sidx;
-        const double q = a / b;
-        if (combine) {
-            const double g = fabs(q + tt + tau);
-            const bool take = g < gmin || (g == gmin && k < rmin);
-            gmin = take ? g : gmin;
-            rmin = take ? k : rmin;
-        } else {
-            col[k * 32] = q;
-        }
-        const double c = __fma_rn(top ? dd : ll, b, a);
-        a = __fma_rn(-tau, c, (top ? ll : dd) * a);
-        b = c;
-        if ((u & 3) == 3) {
-            const int em = max(dexp(a), dexp(b));
-            a = __builtin_ldexp(a, -em);
-            b = __builtin_ldexp(b, -em);
-        }
-    };
-    int64_t i = 0;
-    for (; i + U <= cnt; i += U) {
-        double cd[U], cl[U], ct[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            cd[u] = nd[u];
-            cl[u] = nl[u];
-            ct[u] = nt[u];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t sidx = s0 + i + U + u;
-            const int64_t k = top ? sidx : n - 1 - sidx;
-            const int64_t ka = top ? k : k - 1;
-            nd[u] = D[ka];
-            nl[u] = LL[ka];
-            nt[u] = combine ? col[k * 32] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) body(cd[u], cl[u], ct[u], s0 + i + u, u);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-        if (i + u < cnt) body(nd[u], nl[u], nt[u], s0 + i + u, u);
-}
-
-template <class Y>
-struct Row {
-    Y pq;   // P_k or Q_k mantissa
-    Y d;    // d of the row the recurrence advances over
-    Y ll;   // lld of that row
-    int pqe;
-};
-
-// data of sweep step `it`: the z row k and the row the recurrence advances
-// over (k for the top lane, k-1 for the bottom lane); prefetches past either
-// end of the representation read the arrays' guard rows
-template <class Y>
-__device__ __forceinline__ Row<Y> load_row(bool top, const Y* __restrict__ D,
-                                           const Y* __restrict__ LL, const Y* __restrict__ PQ,
-                                           const int* __restrict__ PQe, int64_t n, int64_t it) {
-    Row<Y> w;
-    const int64_t kz = top ? it : n - 1 - it;
-    const int64_t ka = top ? it : n - 2 - it;
-    w.pq = PQ[kz];
-    w.pqe = PQe[kz];
-    w.d = D[ka];
-    w.ll = LL[ka];
-    return w;
-}
-
-template <class Y>
-__device__ Half<Y> sweep(bool top, const Y* __restrict__ D, const Y* __restrict__ LL,
-                         const Y* __restrict__ PQ, const int* __restrict__ PQe, int64_t n,
-                         int64_t r, Y tau, double* __restrict__ col, bool store, int64_t steps) {
-    constexpr int U = 4;
-    Half<Y> h;
-    h.ss = 0.0;
-    h.zmax = 0.0;
-    h.zmaxv = 0.0;
-    h.zmaxk = -1;
-    h.zr = 0.0;
-    h.ev1 = top ? 0 : n;
-    h.ev2 = top ? 0 : n;
-    h.ev2f = 1.0;
-    Y a, b;
-    if (top) {
-        a = neg(tau);
-        b = y_from(1.0, Y());
-    } else {
-        a = (steps > 0) ? sub(D[n - 1], tau) : neg(tau);
-        b = y_from(1.0, Y());
-    }
-    int eb = 0;    // binary exponent carried by b
-    int eref = 0;  // storage frame exponent
-    Row<Y> nx[U];
-    if (steps > 0) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) nx[u] = load_row<Y>(top, D, LL, PQ, PQe, n, u);
-    }
-    // z value of row k in the storage frame.  The frame is rebased when the
-    // stored exponent would pass 300 (checked every second row, branch free;
-    // |z| grows by |d+_k / e_k| per row, so values and their squares stay in
-    // range between checks).
-    auto zvalue = [&](const Row<Y>& w, int64_t k, bool check) -> double {
-        const Y pb = mul(w.pq, b);
-        int ex = w.pqe + eb - eref;
-        if (check) {
-            const int ez = y_exp(pb) + ex;
-            const bool rb = ez > 300;
-            const int dlt = rb ? ez : 0;
-            eref += dlt;
-            ex -= dlt;
-            h.ss = __builtin_ldexp(h.ss, -2 * dlt);
-            h.zmax = __builtin_ldexp(h.zmax, -dlt);
-            h.zmaxv = __builtin_ldexp(h.zmaxv, -dlt);
-            h.ev1 = rb ? h.ev2 : h.ev1;
-            h.ev2 = rb ? k : h.ev2;
-            h.ev2f = rb ? __builtin_ldexp(1.0, -dlt) : h.ev2f;
-        }
-        return __builtin_ldexp(to_double(pb), ex);
-    };
-    // one step before the twist row: store z_k, then advance past row k
-    auto body = [&](const Row<Y>& w, int64_t it, int u) {
-        const int64_t k = top ? it : n - 1 - it;
-        const double zv = zvalue(w, k, (u & 1) == 1);
-        if (store) col[k * 32] = zv;
-        h.ss = __fma_rn(zv, zv, h.ss);
-        const bool bigger = fabs(zv) > h.zmax;
-        h.zmax = bigger ? fabs(zv) : h.zmax;
-        h.zmaxv = bigger ? zv : h.zmaxv;
-        h.zmaxk = bigger ? k : h.zmaxk;
-        const Y c = mul_add(top ? w.d : w.ll, b, a);
-        a = sub(mul(top ? w.ll : w.d, a), mul(tau, c));
-        b = c;
-        if ((u & 3) == 3) {
-            const int em = max(y_exp(a), y_exp(b));
-            a = y_ldexp(a, -em);
-            b = y_ldexp(b, -em);
-            eb += em;
-        }
-    };
-    int64_t it0 = 0;
-    // full blocks (the twist row, step steps-1, lies beyond them)
-    for (; it0 + U < steps; it0 += U) {
-        Row<Y> cu[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) cu[u] = nx[u];
-#pragma unroll
-        for (int u = 0; u < U; ++u) nx[u] = load_row<Y>(top, D, LL, PQ, PQe, n, it0 + U + u);
-#pragma unroll
-        for (int u = 0; u < U; ++u) body(cu[u], it0 + u, u);
-    }
-    // last block: up to U - 1 more steps, then the twist row
-    if (steps > 0) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t it = it0 + u;
-            if (it + 1 < steps) {
-                body(nx[u], it, u);
-            } else if (it + 1 == steps) {
-                h.zr = zvalue(nx[u], top ? it : n - 1 - it, true);
-            }
-        }
-    }
-    h.sp = div(a, b);  // s_r = a_r / b_r  or  p_r = alpha_r / beta_r
-    return h;
-}
-
+// shuffle of a working-precision value between the lanes of a pair
 template <class Y>
 __device__ __forceinline__ Y shfl_y(Y v, int src);
 template <>
@@ -1724,7 +1543,6 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
     Half<Y> h;
     h.ss = 0.0;
     h.zmax = 0.0;
-    h.zmaxv = 0.0;
     h.zmaxk = -1;
     h.zr = 0.0;
     h.ev1 = top ? 0 : n;
@@ -1741,22 +1559,21 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
                       load_sweep_step<Y>(t >> 5, t & 31, D, LL, P, Pe, Q, Qe, n));
     __syncthreads();
     auto zvalue = [&](const SweepStep<Y>& w, int64_t k, bool check) -> double {
-        const Y pb = mul(w.pq, b);
+        const double pb = prod_hi(w.pq, b);
         int ex = w.pqe + eb - eref;
         if (check) {
-            const int ez = y_exp(pb) + ex;
+            const int ez = dexp(pb) + ex;
             const bool rb = ez > 300;
             const int dlt = rb ? ez : 0;
             eref += dlt;
             ex -= dlt;
             h.ss = __builtin_ldexp(h.ss, -2 * dlt);
             h.zmax = __builtin_ldexp(h.zmax, -dlt);
-            h.zmaxv = __builtin_ldexp(h.zmaxv, -dlt);
             h.ev1 = rb ? h.ev2 : h.ev1;
             h.ev2 = rb ? k : h.ev2;
             h.ev2f = rb ? __builtin_ldexp(1.0, -dlt) : h.ev2f;
         }
-        return __builtin_ldexp(to_double(pb), ex);
+        return __builtin_ldexp(pb, ex);
     };
     auto body = [&](const SweepStep<Y>& w, int64_t it, int u) {
         const int64_t k = top ? it : n - 1 - it;
@@ -1765,10 +1582,9 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
         h.ss = __fma_rn(zv, zv, h.ss);
         const bool bigger = fabs(zv) > h.zmax;
         h.zmax = bigger ? fabs(zv) : h.zmax;
-        h.zmaxv = bigger ? zv : h.zmaxv;
         h.zmaxk = bigger ? k : h.zmaxk;
         const Y c = mul_add(w.f, b, a);
-        a = sub(mul(w.g, a), mul(tau, c));
+        a = mul_sub(w.g, a, tau, c);
         b = c;
         if ((u & 3) == 3) {
             const int em = max(y_exp(a), y_exp(b));
@@ -1876,7 +1692,6 @@ k_rqi(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
     mine.zr = 1.0;
     mine.ss = 0.0;
     mine.zmax = 0.0;
-    mine.zmaxv = 0.0;
     mine.zmaxk = -1;
     mine.ev1 = top ? 0 : n;
     mine.ev2 = top ? 0 : n;
@@ -2040,7 +1855,8 @@ k_rqi(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
     }
     // exchange the per-lane storage bookkeeping and publish the result
     const double zmaxo = __shfl_xor(mine.zmax, 1, 64);
-    const double zmaxvo = __shfl_xor(mine.zmaxv, 1, 64);
+    const int64_t zmaxko = __shfl_xor(mine.zmaxk, 1, 64);
+    __syncthreads();  // both halves' final stores are visible in the tile
     const int64_t ev1o = __shfl_xor(mine.ev1, 1, 64);
     const int64_t ev2o = __shfl_xor(mine.ev2, 1, 64);
     const double ev2fo = __shfl_xor(mine.ev2f, 1, 64);
@@ -2050,8 +1866,9 @@ k_rqi(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
         const double cT = (r_out > 0) ? mine.zmax / fabs(zT) : 0.0;
         const double cB = (r_out < n - 1) ? zmaxo / fabs(zB) : 0.0;
         double sgn = 1.0;
-        if (cT > 1.0 && cT >= cB) sgn = ((mine.zmaxv < 0) != (zT < 0)) ? -1.0 : 1.0;
-        else if (cB > 1.0) sgn = ((zmaxvo < 0) != (zB < 0)) ? -1.0 : 1.0;
+        // (the signed largest entry is read back from the tile column)
+        if (cT > 1.0 && cT >= cB) sgn = ((tile[mine.zmaxk * 32] < 0) != (zT < 0)) ? -1.0 : 1.0;
+        else if (cB > 1.0) sgn = ((tile[zmaxko * 32] < 0) != (zB < 0)) ? -1.0 : 1.0;
         RqiResult o;
         const Y lam_T = add(lam_out, y_from(0.0, Y()));
         o.lam_hi = hi_of(lam_T);
@@ -2338,7 +2155,7 @@ k_child_rep(const ChildJob* __restrict__ jobs, int64_t njobs, Slot* __restrict__
                     const Y c = mul_add(dv, b, a);
                     C[c0 + i] = c;
                     CE[c0 + i] = eb;
-                    a = sub(mul(lv, a), mul(tau, c));
+                    a = mul_sub(lv, a, tau, c);
                     b = c;
                     if ((i & 3) == 3) {
                         const int em = max(y_exp(a), y_exp(b));

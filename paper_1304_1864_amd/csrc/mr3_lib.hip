@@ -106,6 +106,23 @@ __global__ void k_slots(const Block* __restrict__ blocks, const ProbInfo* __rest
     }
 }
 
+// sort key of a singleton: its node, then its relative gap in steps of 2^-3
+// (smaller gaps need more RQI iterations; a wave runs until its slowest pair
+// is done, so pairs of similar gaps share chunks)
+__global__ void k_gap_keys(const int64_t* __restrict__ list, int64_t count,
+                           const Slot* __restrict__ slots, unsigned long long* __restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const Slot sl = slots[list[i]];
+    double lg = sl.lgap, rg = sl.rgap;
+    if (!(lg > 0.0)) lg = MR3_BIG;
+    if (!(rg > 0.0)) rg = MR3_BIG;
+    const double scale = fmax(fmax(fabs(sl.lo), fabs(sl.hi)), 1e-300);
+    const double rel = fmin(fmin(lg, rg) / scale, 1.0);
+    const int bucket = min(255, max(0, (int)(-log2(rel) / 3.0)));
+    keys[i] = ((unsigned long long)(unsigned)sl.node << 8) | (unsigned long long)bucket;
+}
+
 __global__ void k_iota(int64_t* __restrict__ v, int64_t count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) v[i] = i;
@@ -269,7 +286,7 @@ enum BufId {
     B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BLOCKS, B_SLOTS, B_NODES, B_REPD, B_REPL, B_REPE,
     B_D64, B_L64, B_P, B_PE, B_Q, B_QE, B_LIST, B_LIST2, B_CNT, B_TILEOFF, B_TILES, B_RES,
     B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_M, B_BAD, B_COUNTERS,
-    B_BOFF, B_CREC, B_CHECK, B_NSLOT, B_SLOT0, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
+    B_BOFF, B_CREC, B_CHECK, B_NSLOT, B_SLOT0, B_GKEY, B_GVAL, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
 };
 
 // singleton work of tree level d runs on the handle's side stream with the
@@ -850,6 +867,26 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             std::fprintf(stderr, "[mr3] depth %d: nodes %zu singletons %lld clusters %lld  t=%.2f ms\n",
                          depth, level_nodes.size(), (long long)S, (long long)C, now_ms() - t_start);
         // ---- a6 + a7: singletons, on the side stream ----
+        if (S > 1) {
+            // node-major order, gap bucket within a node
+            HIPCHK(B[B_GKEY].ensure(sizeof(unsigned long long) * 2 * S));
+            HIPCHK(B[B_GVAL].ensure(sizeof(int64_t) * S));
+            unsigned long long* k0 = B[B_GKEY].as<unsigned long long>();
+            unsigned long long* k1 = k0 + S;
+            int64_t* v1 = B[B_GVAL].as<int64_t>();
+            hipLaunchKernelGGL(k_gap_keys, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, st,
+                               SL.as<int64_t>(), S, dslots, k0);
+            int end_bit = 9;
+            while (end_bit < 64 && ((int64_t)1 << (end_bit - 8)) <= n_nodes) ++end_bit;
+            size_t tb = 0;
+            HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k0, k1, SL.as<int64_t>(), v1, (int)S,
+                                                      0, end_bit, st));
+            HIPCHK(B[B_CUBTMP].ensure(tb + 256));
+            tb = B[B_CUBTMP].cap;
+            HIPCHK(hipcub::DeviceRadixSort::SortPairs(B[B_CUBTMP].p, tb, k0, k1, SL.as<int64_t>(), v1,
+                                                      (int)S, 0, end_bit, st));
+            HIPCHK(hipMemcpyAsync(SL.p, v1, sizeof(int64_t) * S, hipMemcpyDeviceToDevice, st));
+        }
         if (S > 0) {
             // node-pure chunks (at most S of them)
             HIPCHK(B[B_SEG].ensure(sizeof(int64_t) * S));
@@ -937,21 +974,25 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                     HIPCHK(download(sl, dslots, (size_t)K, st));
                     HIPCHK(download(ls, SL.p, (size_t)S, st));
                     HIPCHK(download(nds, dnodes, (size_t)n_nodes, st));
-                    double sp = 0, sc = 0, sn = 0;
+                    double sp = 0, sc = 0, sn = 0, it_mean = 0, it_cmax = 0;
                     for (const ChunkInfo& c : cks) {
                         const int64_t nn = blocks[nds[sl[ls[c.begin]].node].block].n;
                         int64_t mx = 0;
+                        int imx = 0;
                         for (int q = 0; q < c.count; ++q) {
                             const int64_t r = rr[c.begin + q].r;
                             const int64_t len = std::max(r + 1, nn - r);
                             sp += (double)len;
                             mx = std::max(mx, len);
+                            imx = std::max(imx, rr[c.begin + q].iters);
+                            it_mean += rr[c.begin + q].iters;
                         }
                         sc += (double)mx * c.count;
                         sn += (double)nn * c.count;
+                        it_cmax += (double)imx * c.count;
                     }
-                    std::fprintf(stderr, "[mr3]   sweep length / n: pair mean %.3f, chunk max (pair-weighted) %.3f, chunks %lld\n",
-                                 sp / sn, sc / sn, (long long)nchunk);
+                    std::fprintf(stderr, "[mr3]   sweep length / n: pair mean %.3f, chunk max (pair-weighted) %.3f, chunks %lld; iterations: mean %.2f, chunk max %.2f\n",
+                                 sp / sn, sc / sn, (long long)nchunk, it_mean / S, it_cmax / S);
                 }
                 if (std::getenv("MR3_DEBUG")[0] == '2') {
                     std::vector<RqiResult> rr;
@@ -1066,6 +1107,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         }
         HIPCHK(upload(B[B_LIST], cplan.list, st));
         HIPCHK(upload(B[B_BWG], cplan.wgs, st));
+        if (debug_on()) HIPCHK(hipMemsetAsync(work + 6, 0, 2 * sizeof(double), st));
         prof.begin(MR3_STAGE_CBISECT, st);
         launch_bisect_staged(L, B[B_BWG].as<BisWG>(), (int64_t)cplan.wgs.size(),
                              B[B_LIST].as<int64_t>(), dslots, dnodes, dblocks,
@@ -1075,6 +1117,12 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                       dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
                       prm.bisect_rel, widen_root, work, INT64_MAX, st);
         prof.end(st);
+        if (debug_on()) {
+            std::vector<double> wk;
+            HIPCHK(download(wk, work, 8, st));
+            std::fprintf(stderr, "[mr3]   child bisection: %lld intervals, shape %dx%d, passes max %.0f total %.0f\n",
+                         (long long)KC, L.L, L.P, wk[6], wk[7]);
+        }
         prof.begin(MR3_STAGE_VERIFY, st);
         if (is_dd) {
             // A child accepted within the strict growth bound k_elg * spdiam
