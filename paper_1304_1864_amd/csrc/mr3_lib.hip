@@ -306,8 +306,9 @@ struct mr3_handle_s {
     bool have_user = false;
     mr3::Buf buf[mr3::B_NBUF];
     mr3_stats stats{};
-    // side stream (default priority) for singleton work, and its events
-    hipStream_t side = nullptr;
+    // side streams (default priority) for singleton work, one per level
+    // parity, and their events
+    hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_side[2] = {nullptr, nullptr};
     bool side_pending[2] = {false, false};
@@ -564,8 +565,9 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     Buf* B = h->buf;
     mr3_stats stats{};
     HIPCHK(hipSetDevice(h->device));
-    if (!h->side) {
-        HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    if (!h->side[0]) {
+        HIPCHK(hipStreamCreateWithFlags(&h->side[0], hipStreamNonBlocking));
+        HIPCHK(hipStreamCreateWithFlags(&h->side[1], hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_side[0], hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&h->ev_side[1], hipEventDisableTiming));
@@ -573,10 +575,10 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     // work a failed earlier call left on the side stream must end before
     // buffers are reused
     if (h->side_pending[0] || h->side_pending[1]) {
-        HIPCHK(hipStreamSynchronize(h->side));
+        HIPCHK(hipStreamSynchronize(h->side[0]));
+        HIPCHK(hipStreamSynchronize(h->side[1]));
         h->side_pending[0] = h->side_pending[1] = false;
     }
-    hipStream_t side = h->side;
     // pinned staging space is reused from the last solve, which has finished
     // unless it left with an error
     if (!h->clean_exit) HIPCHK(hipDeviceSynchronize());
@@ -599,7 +601,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     // synchronizes the side stream before a buffer it may read is reallocated
     auto quiesce = [&]() -> hipError_t {
         if (!h->side_pending[0] && !h->side_pending[1]) return hipSuccess;
-        hipError_t e = hipStreamSynchronize(side);
+        hipError_t e = hipStreamSynchronize(h->side[0]);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->side[1]);
         h->side_pending[0] = h->side_pending[1] = false;
         return e;
     };
@@ -887,6 +890,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                                                       (int)S, 0, end_bit, st));
             HIPCHK(hipMemcpyAsync(SL.p, v1, sizeof(int64_t) * S, hipMemcpyDeviceToDevice, st));
         }
+        int64_t nchunk = 0;
         if (S > 0) {
             // node-pure chunks (at most S of them)
             HIPCHK(B[B_SEG].ensure(sizeof(int64_t) * S));
@@ -911,7 +915,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             }
             std::vector<int64_t> nck;
             HIPCHK(download(nck, cid + S - 1, 1, st));
-            const int64_t nchunk = nck[0];
+            nchunk = nck[0];
             HIPCHK(SCK.ensure(sizeof(ChunkInfo) * nchunk));
             HIPCHK(STO.ensure(sizeof(int64_t) * (nchunk + 1)));
             HIPCHK(B[B_FLAGS].ensure(sizeof(int64_t) * (nchunk + 1)));
@@ -930,6 +934,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             HIPCHK(download(tot, STO.as<int64_t>() + nchunk, 1, st));
             HIPCHK(STI.ensure(sizeof(double) * (std::max<int64_t>(tot[0], 1) + 2 * 32 * GUARD)));
             HIPCHK(SRE.ensure(sizeof(RqiResult) * S));
+        }
+        // RQI and output of this level's singletons go to the side stream of
+        // the level's parity once the level's cluster work has been issued:
+        // the cluster work is the longer chain, so it gets the device first,
+        // and the singleton work then overlaps the next level.
+        auto fork_singletons = [&]() -> int {
+            if (S == 0) return MR3_OK;
+            hipStream_t side = h->side[par];
             HIPCHK(hipEventRecord(h->ev_fork, st));
             HIPCHK(hipStreamWaitEvent(side, h->ev_fork, 0));
             prof.begin(MR3_STAGE_RQI, side);
@@ -1013,9 +1025,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                                          (long long)rr[i].evB2);
                 }
             }
-        }
+            return MR3_OK;
+        };
         level_nodes.clear();
-        if (C == 0) break;
+        if (C == 0) {
+            const int rc = fork_singletons();
+            if (rc) return rc;
+            break;
+        }
         // ---- a5: clusters -> child representations ----
         HIPCHK(B[B_CREC].ensure(sizeof(ClusterRec) * C));
         hipLaunchKernelGGL(k_cluster_recs, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, st,
@@ -1153,6 +1170,10 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         }
         prof.end(st);
         HIPCHK(hipGetLastError());
+        {
+            const int rc = fork_singletons();
+            if (rc) return rc;
+        }
         for (int64_t c = 0; c < C; ++c) level_nodes.push_back(jobs[c].child);
     }
     // ---- join the side stream; diagnostics and the ascending-order check ----
@@ -1341,12 +1362,14 @@ int mr3_create(mr3_handle* h, int device) {
 int mr3_destroy(mr3_handle h) {
     if (!h) return -1;
     (void)hipSetDevice(h->device);
-    if (h->side) (void)hipStreamSynchronize(h->side);
+    for (auto& sd : h->side)
+        if (sd) (void)hipStreamSynchronize(sd);
     for (auto& b : h->buf) b.release();
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     for (auto& ev : h->ev_side)
         if (ev) (void)hipEventDestroy(ev);
-    if (h->side) (void)hipStreamDestroy(h->side);
+    for (auto& sd : h->side)
+        if (sd) (void)hipStreamDestroy(sd);
     h->stage.release();
     delete h;
     return MR3_OK;
