@@ -233,6 +233,65 @@ def served_c5(mr3, n_req=2000, seed=0, window=64, calib=600):
     return out
 
 
+def gaptol_study(mr3):
+    """Clustering rho (largest cluster / n), tree depth and solve time against
+    gaptol, with and without splitting by absolute gaps (gaptol_abs = gaptol),
+    on the synthetic stand-ins of the paper's matrix types."""
+    import torch
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    cases = [
+        ("uniform n=512 fp32", *W.uniform(512, 0, np.float32)),
+        ("1-2-1 n=512 fp32", *W.toeplitz_121(512, np.float32)),
+        ("N(0,1) n=1024 fp32", *W.normal(1024, 1, np.float32)),
+        ("1-2-1 + noise n=8192 fp32", *W.toeplitz_121_noisy(8192, 0, 1e-6, np.float32)),
+        ("1-2-1 + noise n=8192 fp64", *W.toeplitz_121_noisy(8192, 0, 1e-6, np.float64)),
+        ("glued Wilkinson n=4096 fp64", *W.glued_wilkinson(4096)),
+        ("prescribed n=20000 fp64", *W.prescribed_spectrum(20000, 0)[:2]),
+    ]
+    rows = []
+    for name, d, e in cases:
+        n = d.size
+        prec = 32 if d.dtype == np.float32 else 64
+        tols = (1e-3, 1e-4, 1e-5, 1e-6) if prec == 32 else (1e-3, 1e-5, 1e-8, 1e-10, 1e-12)
+        dg, eg = torch.from_numpy(d).to(dev), torch.from_numpy(e).to(dev)
+        for g in tols:
+            for ab in (0.0, g):
+                h = mr3.Handle(0)
+                h.set_params(precision=prec, gaptol=g, gaptol_abs=ab)
+                try:
+                    mr3.solve(dg, eg, handle=h)
+                except mr3.MR3Error as err:
+                    if err.code != mr3.MR3_ERR_GAPTOL:
+                        raise
+                    row = {"matrix": name, "gaptol": g, "abs_split": ab > 0,
+                           "rejected": "gaptol below the binary64 eigenvalue accuracy 20 n eps"}
+                    rows.append(row)
+                    print(json.dumps(row), flush=True)
+                    h.close()
+                    continue
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    Wg, Zg = mr3.solve(dg, eg, handle=h)
+                    torch.cuda.synchronize()
+                    ts.append((time.perf_counter() - t0) * 1e3)
+                st = h.stats()
+                row = {"matrix": name, "gaptol": g, "abs_split": ab > 0,
+                       "rho": max(st["largest_cluster"], 1) / n, "d_max": st["d_max"],
+                       "clusters": st["n_clusters"], "ms": round(float(np.median(ts)), 3)}
+                if prec == 64:
+                    (off, diag), res = mr3.check(dg, eg, Wg, Zg, handle=h)
+                    row["orth"] = max(off, diag)
+                    row["resid"] = res
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+                h.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,7 +306,14 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (calibrates "
                          "hardware byte counters against a known traffic) and exit")
+    ap.add_argument("--gaptol-study", action="store_true",
+                    help="only run the clustering study against gaptol and exit")
     args = ap.parse_args()
+    if args.gaptol_study:
+        import paper_1304_1864_amd as mr3
+
+        gaptol_study(mr3)
+        return
     if args.copy_probe:
         import torch
 

@@ -65,6 +65,11 @@ extern "C" {
 #define MR3_ERR_NUMERIC 1
 #define MR3_ERR_HIP 2
 #define MR3_ERR_NO_DEVICE 3
+/* FP64 path: gaptol below the accuracy of eigenvalues approximated on the
+ * binary64 copy of a representation, (k_rr + k_bi) n eps_x with
+ * k_rr = k_bi = 10 (Sec. 3.2, "Arithmetic used to approximate eigenvalues")
+ * for the longest block of the call */
+#define MR3_ERR_GAPTOL 4
 
 typedef enum { MR3_RANGE_ALL = 0, MR3_RANGE_VALUE = 1, MR3_RANGE_INDEX = 2 } mr3_range;
 
@@ -94,6 +99,10 @@ typedef struct {
     int profile;
     int points_per_lane;   /* bisection points per lane and pass: 1, 2 or 4;
                               0 = chosen with lanes_per_eig from the size */
+    double gaptol_abs;     /* splitting by absolute gaps (Sec. 2, "Classification
+                              of the eigenvalues"): neighbours whose gap is at
+                              least gaptol_abs * spdiam are separated whatever
+                              their relative gap; 0 = off [0] */
 } mr3_params;
 
 /* Diagnostics of the last solve on a handle (Section 4.2 reports d_max and

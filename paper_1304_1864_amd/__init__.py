@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libmr3.so")
 
 RANGE_ALL, RANGE_VALUE, RANGE_INDEX = 0, 1, 2
 STAGES = ["prep", "bisect", "classify", "rqi", "zout", "child", "cbisect", "verify"]
-MR3_OK, MR3_ERR_NUMERIC, MR3_ERR_HIP, MR3_ERR_NO_DEVICE = 0, 1, 2, 3
+MR3_OK, MR3_ERR_NUMERIC, MR3_ERR_HIP, MR3_ERR_NO_DEVICE, MR3_ERR_GAPTOL = 0, 1, 2, 3, 4
 
 
 class MR3Error(RuntimeError):
@@ -51,6 +51,7 @@ class mr3_params(ctypes.Structure):
         ("force_best_candidate", ctypes.c_int),
         ("profile", ctypes.c_int),
         ("points_per_lane", ctypes.c_int),
+        ("gaptol_abs", ctypes.c_double),
     ]
 
 

@@ -996,9 +996,14 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
                 double* __restrict__ work, int check) {
     __shared__ double2 win[2][STAGE_ROWS];
     const BisWG w = wgs[blockIdx.x];
-    const int g = threadIdx.x / L;
-    const int q = threadIdx.x % L;
-    const bool active = g < w.count;
+    // groups of L lanes never straddle a wave: 64 / L groups per wave (the
+    // last 64 mod L lanes of a wave only help with the loads)
+    constexpr int GW = 64 / L;
+    const int lane = threadIdx.x & 63;
+    const int lg = lane / L;
+    const int q = lane % L;
+    const int g = (threadIdx.x >> 6) * GW + lg;
+    const bool active = lg < GW && g < w.count;
     const Node nd = nodes[w.node];
     const int64_t n = blocks[nd.block].n;
     const double* D = d64 + nd.rep;
@@ -1012,8 +1017,7 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
         lo = sl.lo;
         hi = sl.hi;
     }
-    const int lane = threadIdx.x & 63;
-    const int gbase = lane - q;
+    const int gbase = (lg < GW ? lg : 0) * L;  // first lane of this group
     // make sure the bracket holds: count(lo) <= j-1 < count(hi) (skipped when
     // the caller has verified every bracket with counts already)
     bool fix = active && check;
@@ -1283,13 +1287,18 @@ __device__ __forceinline__ double reldist(const Slot& a, const Slot& b) {
 
 __global__ void __launch_bounds__(256)
 k_classify(const int64_t* __restrict__ node_list, int64_t count, const Node* __restrict__ nodes,
-           Slot* __restrict__ slots, int* __restrict__ start_flag, double gaptol, int force_single) {
+           Slot* __restrict__ slots, int* __restrict__ start_flag, double gaptol, double gaptol_abs,
+           int force_single) {
     const int64_t ni = node_list[blockIdx.x];
     const Node nd = nodes[ni];
     const int t = threadIdx.x;
     for (int64_t s = nd.first + t; s <= nd.last; s += blockDim.x) {
         int f = 1;
-        if (s > nd.first && !force_single) f = reldist(slots[s - 1], slots[s]) >= gaptol;
+        if (s > nd.first && !force_single) {
+            // relative separation, amended by the absolute one when enabled
+            const Slot a = slots[s - 1], b = slots[s];
+            f = reldist(a, b) >= gaptol || (gaptol_abs > 0.0 && b.lo - a.hi >= gaptol_abs * nd.spdiam);
+        }
         start_flag[s] = f;
     }
     __syncthreads();

@@ -404,6 +404,7 @@ static Params effective(const mr3_handle_s* h, int precision) {
     const mr3_params& u = h->user;
     Params p;
     p.gaptol = (h->have_user && u.gaptol > 0) ? u.gaptol : d.gaptol;
+    p.gaptol_abs = (h->have_user && u.gaptol_abs > 0) ? u.gaptol_abs : 0.0;
     p.bisect_rel = (h->have_user && u.bisect_rel > 0) ? u.bisect_rel : 1e-2 * p.gaptol;
     p.xi = (h->have_user && u.xi > 0) ? u.xi : d.xi;
     p.k_elg = (h->have_user && u.k_elg > 0) ? u.k_elg : d.k_elg;
@@ -491,6 +492,7 @@ static void launch_bisect_staged(BisectShape sh, const BisWG* wgs, int64_t nwg, 
     }
     MR3_BST(1, 1) MR3_BST(1, 2) MR3_BST(1, 4)
     MR3_BST(2, 1) MR3_BST(2, 2) MR3_BST(2, 4)
+    MR3_BST(3, 1) MR3_BST(6, 1) MR3_BST(12, 1) MR3_BST(24, 1)
     MR3_BST(4, 1) MR3_BST(4, 2) MR3_BST(4, 4)
     MR3_BST(8, 1) MR3_BST(8, 2) MR3_BST(8, 4)
     MR3_BST(16, 1) MR3_BST(16, 2) MR3_BST(16, 4)
@@ -551,6 +553,27 @@ static BisectShape pick_shape(int64_t count, int user_lanes, int user_points) {
         while (sh.L < 64 && count * sh.L < 65536) sh.L *= 2;
     }
     if (user_points == 1 || user_points == 2 || user_points == 4) sh.P = user_points;
+    return sh;
+}
+
+// shape of the LDS-staged kernel, whose lane groups need not divide the wave:
+// the smallest L (one chain per lane) that fills about one wave per SIMD
+// (1024 SIMDs), which spreads the waves evenly and keeps the redundant
+// multisection work low
+static BisectShape pick_shape_staged(int64_t count, int user_lanes) {
+    static const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64};
+    BisectShape sh{64, 1};
+    for (int L : cand) {
+        if (user_lanes > 0) {
+            if (L <= user_lanes) sh.L = L;
+            continue;
+        }
+        const int64_t gw = 64 / L;
+        if ((count + gw - 1) / gw >= 900) {
+            sh.L = L;
+            break;
+        }
+    }
     return sh;
 }
 
@@ -680,6 +703,17 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     stats.n_blocks = NB;
     for (int64_t p = 0; p < count; ++p) { m_out[p] = m_p[p]; stats.n_eigenpairs += m_p[p]; }
     if (K == 0) { h->stats = stats; h->clean_exit = true; return MR3_OK; }
+    if (is_dd) {
+        // eigenvalues are approximated on binary64 copies: their accuracy
+        // (k_rr + k_bi) n eps_x must stay below gaptol
+        int64_t nmax = 0;
+        for (const Block& bk : blocks)
+            if (bk.nslot > 0) nmax = std::max(nmax, bk.n);
+        if (prm.gaptol < 20.0 * (double)nmax * 1.1102230246251565e-16) {
+            h->clean_exit = true;
+            return MR3_ERR_GAPTOL;
+        }
+    }
     HIPCHK(B[B_SLOTS].ensure(sizeof(Slot) * (size_t)K));
     hipLaunchKernelGGL(k_slots, dim3((unsigned)NB), dim3(256), 0, st, B[B_BLOCKS].as<Block>(),
                        B[B_PINFO].as<ProbInfo>(), B[B_SLOTS].as<Slot>());
@@ -735,12 +769,16 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     // ---- a3: bisection of every slot on its root ----
     // the slot list is the identity; staged workgroups of a large block
     // serve its slot range directly, and the per-lane kernel skips those slots
-    BisectShape L = pick_shape(K, prm.lanes_per_eig, prm.points_per_lane);
+    int64_t k_staged = 0;
+    for (int64_t b = 0; b < NB; ++b)
+        if (blocks[b].n >= STAGE_MIN_N && !no_stage()) k_staged += blocks[b].nslot;
+    BisectShape L = pick_shape(K - k_staged, prm.lanes_per_eig, prm.points_per_lane);
+    const BisectShape Ls = pick_shape_staged(k_staged, prm.lanes_per_eig);
     std::vector<BisWG> rwgs;
     int64_t k_small = 0;
     for (int64_t b = 0; b < NB; ++b) {
         if (blocks[b].n >= STAGE_MIN_N && !no_stage()) {
-            const int G = 256 / L.L;
+            const int G = 4 * (64 / Ls.L);
             for (int64_t o = 0; o < blocks[b].nslot; o += G)
                 rwgs.push_back(BisWG{blocks[b].slot0 + o,
                                      (int)std::min<int64_t>(G, blocks[b].nslot - o), (int)b});
@@ -782,7 +820,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             }
         }
     }
-    launch_bisect_staged(L, B[B_BWG].as<BisWG>(), (int64_t)rwgs.size(), B[B_LIST].as<int64_t>(),
+    launch_bisect_staged(Ls, B[B_BWG].as<BisWG>(), (int64_t)rwgs.size(), B[B_LIST].as<int64_t>(),
                          dslots, dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
                          prm.bisect_rel, widen_root, work, 0, st);
     if (k_small > 0)
@@ -833,7 +871,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         prof.begin(MR3_STAGE_CLASSIFY, st);
         hipLaunchKernelGGL(k_classify, dim3((unsigned)level_nodes.size()), dim3(256), 0, st,
                            B[B_LIST].as<int64_t>(), (int64_t)level_nodes.size(), dnodes, dslots,
-                           B[B_FLAGS].as<int>(), prm.gaptol, force_single);
+                           B[B_FLAGS].as<int>(), prm.gaptol, prm.gaptol_abs, force_single);
         HIPCHK(hipGetLastError());
         // compact the singletons (into the side list of this level's parity)
         // and the cluster heads of this level
@@ -1107,26 +1145,30 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         n_nodes += C;
         // ---- child bisection (Alg. 1 line 14): the members of every new
         // cluster, whose slots now belong to the child node ----
-        int64_t KC = 0;
-        for (int64_t c = 0; c < C; ++c) KC += crec[c].last - crec[c].head + 1;
-        L = pick_shape(KC, prm.lanes_per_eig, prm.points_per_lane);
-        if (const char* cs = std::getenv("MR3_CHILD_SHAPE")) {  // development aid: "L,P"
-            int l = 0, q = 0;
-            if (std::sscanf(cs, "%d,%d", &l, &q) == 2) L = pick_shape(KC, l, q);
+        int64_t KC = 0, KCs = 0;
+        for (int64_t c = 0; c < C; ++c) {
+            KC += crec[c].last - crec[c].head + 1;
+            if (job_n[c] >= STAGE_MIN_N && !no_stage()) KCs += crec[c].last - crec[c].head + 1;
+        }
+        L = pick_shape(KC - KCs, prm.lanes_per_eig, prm.points_per_lane);
+        BisectShape Lcs = pick_shape_staged(KCs, prm.lanes_per_eig);
+        if (const char* cs = std::getenv("MR3_CHILD_SHAPE")) {  // development aid: lanes
+            int l = 0;
+            if (std::sscanf(cs, "%d", &l) == 1) Lcs = pick_shape_staged(KCs, l);
         }
         BisectPlan cplan;
         {
             std::vector<int64_t> rest;
             for (int64_t c = 0; c < C; ++c)
                 cplan.add(jobs[c].child, job_n[c], crec[c].head, crec[c].last - crec[c].head + 1,
-                          256 / L.L, rest);
+                          4 * (64 / Lcs.L), rest);
             cplan.finish(rest);
         }
         HIPCHK(upload(B[B_LIST], cplan.list, st));
         HIPCHK(upload(B[B_BWG], cplan.wgs, st));
         if (debug_on()) HIPCHK(hipMemsetAsync(work + 6, 0, 2 * sizeof(double), st));
         prof.begin(MR3_STAGE_CBISECT, st);
-        launch_bisect_staged(L, B[B_BWG].as<BisWG>(), (int64_t)cplan.wgs.size(),
+        launch_bisect_staged(Lcs, B[B_BWG].as<BisWG>(), (int64_t)cplan.wgs.size(),
                              B[B_LIST].as<int64_t>(), dslots, dnodes, dblocks,
                              B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel,
                              widen_root, work, 1, st);
@@ -1137,8 +1179,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         if (debug_on()) {
             std::vector<double> wk;
             HIPCHK(download(wk, work, 8, st));
-            std::fprintf(stderr, "[mr3]   child bisection: %lld intervals, shape %dx%d, passes max %.0f total %.0f\n",
-                         (long long)KC, L.L, L.P, wk[6], wk[7]);
+            std::fprintf(stderr, "[mr3]   child bisection: %lld intervals, staged lanes %d, passes max %.0f total %.0f\n",
+                         (long long)KC, Lcs.L, wk[6], wk[7]);
         }
         prof.begin(MR3_STAGE_VERIFY, st);
         if (is_dd) {

@@ -106,6 +106,7 @@ struct RqiResult {    // per singleton, consumed by the output kernel
 
 struct Params {
     double gaptol;
+    double gaptol_abs;
     double bisect_rel;
     double xi;
     double k_elg;

@@ -264,3 +264,21 @@ def test_metamorphic_relations(mr3):
     assert float((W3 - W0).abs().max()) <= 4 * n * 2.0 ** -53 * tn
     R = M.residual(d[::-1].copy(), e[::-1].copy(), W3.cpu().numpy(), Z3.cpu().numpy())
     assert R <= 10 * n * 2.0 ** -53
+
+
+def test_gaptol_settings(mr3):
+    """Non-default gaptol: a smaller value (more parallelism) still meets the
+    gates; a value below what binary64 eigenvalue approximation resolves at
+    this size, 20 n eps (Sec. 3.2), is rejected; absolute-gap splitting is
+    accepted and keeps the gates."""
+    d, e, _ = W.prescribed_spectrum(2000, 2)
+    h = mr3.Handle(0)
+    h.set_params(precision=64, gaptol=1e-11, gaptol_abs=1e-11)
+    run_case(mr3, d, e, handle=h, check_angles=False)
+    h.set_params(precision=64, gaptol=1e-13)
+    with pytest.raises(mr3.MR3Error) as ei:
+        mr3.solve(_dev(d), _dev(e), handle=h)
+    assert ei.value.code == mr3.MR3_ERR_GAPTOL
+    h.set_params(precision=32, gaptol=1e-6)
+    d32, e32 = W.uniform(700, 8, np.float32)
+    run_case(mr3, d32, e32, handle=h)
