@@ -385,7 +385,7 @@ def main():
         "peak": FP64_VECTOR_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 4),
-        "traffic": profiled_traffic("k_rqi<dd>" if dom == "rqi" else "k_bisect<2,2>"),
+        "traffic": profiled_traffic("k_rqi<dd>" if dom == "rqi" else "k_bisect_staged"),
         "launches": int(stage_launch[idx[dom]]),
         "avg_launch_ms": round(dom_ms / max(stage_launch[idx[dom]], 1), 3),
     }
