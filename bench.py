@@ -292,6 +292,57 @@ def gaptol_study(mr3):
     return rows
 
 
+def dqds_study(mr3, steps=3):
+    """Initial eigenvalues by dqds (one lane per root) against bisection, by
+    eigenpairs/s: the 4096-problem batch (n log-uniform in [32, 1024], FP32
+    I/O) and single prescribed-spectrum problems (FP64 I/O).  initial_ms is
+    the device time of the initial eigenvalues (dqds or slicing, then the
+    bracket check and multisection)."""
+    import torch
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    rows = []
+
+    def timed(run, h, eigenpairs, reps):
+        run()
+        torch.cuda.synchronize()
+        ts, bis = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+            bis.append(h.stats()["stage_ms"][1])
+        ms = float(np.median(ts))
+        return {"ms": round(ms, 3), "initial_ms": round(float(np.median(bis)), 3),
+                "eigenpairs_per_s": round(eigenpairs / (ms / 1e3), 1),
+                "dqds_roots": h.stats()["n_dqds_roots"],
+                "dqds_transforms": h.stats()["dqds_transforms"]}
+
+    probs = W.batch_normal(4096, 32, 1024, seed=0, dtype=np.float32)
+    ds = [torch.from_numpy(p[0]).to(dev) for p in probs]
+    es = [torch.from_numpy(p[1]).to(dev) for p in probs]
+    total = sum(p[0].size for p in probs)
+    cases = [("batch 4096 x n in [32, 1024] fp32", 32, lambda h: mr3.solve_batched(ds, es, handle=h), total)]
+    for n in (256, 512, 1024):
+        d, e, _ = W.prescribed_spectrum(n, 0)
+        dg, eg = torch.from_numpy(d).to(dev), torch.from_numpy(e).to(dev)
+        cases.append((f"prescribed n={n} fp64", 64,
+                      (lambda dg, eg: (lambda h: mr3.solve(dg, eg, handle=h)))(dg, eg), n))
+    for name, prec, fn, pairs in cases:
+        for init in (mr3.MR3_INITIAL_BISECTION, mr3.MR3_INITIAL_DQDS):
+            h = mr3.Handle(0)
+            h.set_params(precision=prec, initial=init, profile=1)
+            row = {"problem": name, "initial": "dqds" if init else "bisection"}
+            # dqds runs one lane per root for seconds: one timed repetition
+            row.update(timed(lambda: fn(h), h, pairs, steps if init == mr3.MR3_INITIAL_BISECTION else 1))
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+            h.close()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,7 +359,15 @@ def main():
                          "hardware byte counters against a known traffic) and exit")
     ap.add_argument("--gaptol-study", action="store_true",
                     help="only run the clustering study against gaptol and exit")
+    ap.add_argument("--dqds-study", action="store_true",
+                    help="only run the dqds against bisection comparison of initial eigenvalues "
+                         "and exit")
     args = ap.parse_args()
+    if args.dqds_study:
+        import paper_1304_1864_amd as mr3
+
+        dqds_study(mr3)
+        return
     if args.gaptol_study:
         import paper_1304_1864_amd as mr3
 

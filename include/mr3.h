@@ -103,7 +103,19 @@ typedef struct {
                               of the eigenvalues"): neighbours whose gap is at
                               least gaptol_abs * spdiam are separated whatever
                               their relative gap; 0 = off [0] */
+    int initial;           /* initial eigenvalue approximations of a root whose
+                              whole spectrum is wanted (Sec. 4.1):
+                              MR3_INITIAL_BISECTION, or MR3_INITIAL_DQDS for the
+                              sequential dqds algorithm, one lane per root of at
+                              most MR3_DQDS_MAX_N rows (larger roots and subsets
+                              use bisection).  The dqds values are checked with
+                              Sturm counts and refined by bisection like any
+                              other bracket [MR3_INITIAL_BISECTION] */
 } mr3_params;
+
+#define MR3_INITIAL_BISECTION 0
+#define MR3_INITIAL_DQDS 1
+#define MR3_DQDS_MAX_N 4096
 
 /* Diagnostics of the last solve on a handle (Section 4.2 reports d_max and
  * the clustering rho = largest cluster / n). */
@@ -126,6 +138,8 @@ typedef struct {
     double bisect_row_steps;
     double rqi_row_steps;
     double twist_row_steps;
+    int64_t n_dqds_roots;     /* roots whose initial eigenvalues came from dqds */
+    int64_t dqds_transforms;  /* shifted qd transforms summed over those roots */
 } mr3_stats;
 
 /* stage indices of mr3_stats.stage_ms */

@@ -28,6 +28,8 @@ LIB_PATH = os.path.join(_HERE, "libmr3.so")
 RANGE_ALL, RANGE_VALUE, RANGE_INDEX = 0, 1, 2
 STAGES = ["prep", "bisect", "classify", "rqi", "zout", "child", "cbisect", "verify"]
 MR3_OK, MR3_ERR_NUMERIC, MR3_ERR_HIP, MR3_ERR_NO_DEVICE, MR3_ERR_GAPTOL = 0, 1, 2, 3, 4
+MR3_INITIAL_BISECTION, MR3_INITIAL_DQDS = 0, 1
+MR3_DQDS_MAX_N = 4096
 
 
 class MR3Error(RuntimeError):
@@ -52,6 +54,7 @@ class mr3_params(ctypes.Structure):
         ("profile", ctypes.c_int),
         ("points_per_lane", ctypes.c_int),
         ("gaptol_abs", ctypes.c_double),
+        ("initial", ctypes.c_int),
     ]
 
 
@@ -70,6 +73,8 @@ class mr3_stats(ctypes.Structure):
         ("bisect_row_steps", ctypes.c_double),
         ("rqi_row_steps", ctypes.c_double),
         ("twist_row_steps", ctypes.c_double),
+        ("n_dqds_roots", ctypes.c_int64),
+        ("dqds_transforms", ctypes.c_int64),
     ]
 
 

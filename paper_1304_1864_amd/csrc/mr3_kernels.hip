@@ -11,7 +11,12 @@
 //               recurrences (shared by every node of a tree)
 //   k_bisect    multisection on Sturm counts of a binary64 copy of a
 //               representation (Alg. 1 lines 3 and 14; Sec. 3.2 "Arithmetic
-//               used to approximate eigenvalues")
+//               used to approximate eigenvalues"); k_bisect_staged streams
+//               the rows of large nodes through LDS, k_slice shares counts
+//               among all eigenvalues of a large root
+//   k_dqds      optional initial eigenvalues of whole spectra by the dqds
+//               algorithm, one lane per root (Sec. 4.1), checked and refined
+//               by the multisection afterwards
 //   k_classify  singleton / cluster partition by reldist >= gaptol (Alg. 1
 //               line 7; Sec. 2 "Classification of the eigenvalues")
 //   k_rqi       Rayleigh quotient iteration with twisted factorizations
@@ -552,27 +557,36 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
         }
         return neg;
     };
-    // which end: all eigenvalues -> the more populated end; a subset -> the
-    // end nearer to the requested indices
+    // round 0: 254 points over the whole interval bracket both extreme
+    // eigenvalues, and two threads count at the quarter points, which choose
+    // the end: all eigenvalues -> the more populated end; a subset -> the end
+    // nearer to the requested indices
     {
-        const bool all = blk.il == 1 && blk.iu == n;
-        const int c = tcount(t == 0 ? gl + 0.25 * spd : gu - 0.25 * spd, all && t < 2);
-        if (t < 2) sc[t] = c;
+        const double lo = gl - 1e-3 * spd, hi = gu + 1e-3 * spd;
+        double x;
+        if (t < 254) x = lo + (hi - lo) * ((double)(t + 1) / 255.0);
+        else x = (t == 254) ? gl + 0.25 * spd : gu - 0.25 * spd;
+        sx[t] = x;
+        sc[t] = tcount(x, true);
+        __syncthreads();
+        if (t == 0) {
+            int right;
+            if (blk.il == 1 && blk.iu == n) right = ((int64_t)n - sc[255] > sc[254]) ? 1 : 0;
+            else right = (blk.il + blk.iu > n + 1) ? 1 : 0;
+            s_right = right;
+            const int64_t target = right ? n - 1 : 0;
+            int f = 254;
+            for (int q = 0; q < 254; ++q)
+                if (sc[q] > target) { f = q; break; }
+            s_lo = (f > 0) ? sx[f - 1] : lo;
+            s_hi = (f < 254) ? sx[f] : hi;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (t == 0) {
-        int right;
-        if (blk.il == 1 && blk.iu == n) right = ((int64_t)n - sc[1] > sc[0]) ? 1 : 0;
-        else right = (blk.il + blk.iu > n + 1) ? 1 : 0;
-        s_right = right;
-        s_lo = gl - 1e-3 * spd;
-        s_hi = gu + 1e-3 * spd;
-    }
-    __syncthreads();
     const int right = s_right;
-    // bracket the extreme eigenvalue by multisection (4 rounds x 255 points)
+    // three more rounds of 255-point multisection on the chosen end
     const int64_t target = right ? n - 1 : 0;  // count threshold
-    for (int round = 0; round < 4; ++round) {
+    for (int round = 0; round < 3; ++round) {
         const double lo = s_lo, hi = s_hi;
         const double x = lo + (hi - lo) * ((double)(t + 1) / 256.0);
         sx[t] = x;
@@ -1082,6 +1096,202 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
         slots[s].lo = lo - wd;
         slots[s].hi = hi + wd;
     }
+}
+
+// ---------------------------------------------------------------------------
+// a3 alternative for whole spectra: the dqds algorithm, the sequential choice
+// when every eigenpair of a matrix is wanted (Sec. 4.1), one lane per root.
+// The definite root M = L D L^T has the qd array q_k = d_k, e_k = lld_k,
+// negated for a negative definite root so that every entry is positive.  The
+// differential qd transform with shift s,
+//     d = q_0 - s;   qh_k = d + e_k,  t = q_{k+1} / qh_k,  eh_k = e_k t,
+//                    d = d t - s;     qh_{m-1} = d,
+// gives the qd array of the same matrix shifted by s (factors in the other
+// order); all its entries stay positive exactly when s is below the smallest
+// eigenvalue.  The shift is Laguerre's step from below for the characteristic
+// polynomial of the m x m array,
+//     s = m / (S1 + sqrt((m - 1)(m S2 - S1^2))),  S1 = tr A^{-1},  S2 = tr A^{-2},
+// which never passes the smallest eigenvalue and converges cubically.  The
+// diagonal of A^{-1} is 1/g_k, g_k the twist elements at zero shift, and S2 is
+// the derivative of S1 with respect to the shift: with the top-down values
+// u_0 = -1, u_{k+1} = (e_k / q_k) u_k - 1 (derivatives of the stationary
+// transform) and the bottom-up p_{m-1} = q_{m-1}, p_k = p_{k+1} q_k / r_k,
+// r_k = e_k + p_{k+1}, with derivatives v_{m-1} = -1,
+// v_k = q_k e_k v_{k+1} / r_k^2 - 1, one has g_k = p_k and
+// g_k' = u_k + v_k + 1, so S1 = sum 1/g_k and S2 = -sum g_k' / g_k^2.  The
+// u_k of the next array are formed inside the transform.  A transform that
+// fails anyway (rounding) is retried with smaller shifts, down to zero, which
+// cannot fail.  The bottom entry deflates when e_{m-2} is small enough that
+// dropping it moves the eigenvalue by at most about a unit roundoff (the
+// singular values of the bidiagonal factor move by at most sqrt(e_{m-2}));
+// the bottom 2 x 2 block deflates likewise on e_{m-3}, which settles close
+// pairs without resolving them by shifts.  The values come out nearly
+// ascending and an insertion sort orders them.  They are estimates only: the
+// multisection that follows checks every bracket with Sturm counts, repairs
+// it where needed and refines it.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool dqds_deflates(double lam, double sh, double el) {
+    const double tol = 1.1102230246251565e-16 * (sh + lam);
+    return el <= tol && 4.0 * lam * el <= tol * tol;
+}
+
+__global__ void __launch_bounds__(64)
+k_dqds(const int* __restrict__ blist, int count, const Block* __restrict__ blocks,
+       const Node* __restrict__ nodes, const double* __restrict__ d64,
+       const double* __restrict__ lld64, double* __restrict__ scratch, Slot* __restrict__ slots,
+       unsigned long long* __restrict__ transforms) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= count) return;
+    const int b = blist[i];
+    const Block bk = blocks[b];
+    const int64_t n = bk.n;
+    const Node nd = nodes[b];  // root node of block b
+    const double* D = d64 + nd.rep;
+    const double* LL = lld64 + nd.rep;
+    // six arrays of n per root: the qd array and its transform, u, the values
+    double* q = scratch + 6 * bk.row0;
+    double* e = q + n;
+    double* q2 = e + n;
+    double* e2 = q2 + n;
+    double* u = e2 + n;
+    double* ev = u + n;
+    const double sg = (n > 0 && D[0] < 0.0) ? -1.0 : 1.0;  // a definite root: one sign
+    double uk = -1.0;
+    for (int64_t k = 0; k < n; ++k) {
+        q[k] = sg * D[k];
+        e[k] = (k + 1 < n) ? sg * LL[k] : 0.0;
+        u[k] = uk;
+        uk = (e[k] / q[k]) * uk - 1.0;
+    }
+    constexpr double EPS = 1.1102230246251565e-16;
+    double sh = 0.0, sl = 0.0;  // accumulated shift (compensated sum)
+    int64_t m = n, found = 0;
+    unsigned long long steps = 0;
+    int64_t budget = 12 * n + 40;  // transforms before giving up on the rest
+    while (m > 0) {
+        if (m == 1) {
+            ev[found++] = sh + (sl + q[0]);
+            m = 0;
+            break;
+        }
+        if (dqds_deflates(q[m - 1], sh, e[m - 2])) {
+            ev[found++] = sh + (sl + q[m - 1]);
+            --m;
+            continue;
+        }
+        {
+            // bottom 2 x 2 block: [[a, sqrt(a b)], [sqrt(a b), b + c]]
+            const double a = q[m - 2], bb = e[m - 2], c = q[m - 1];
+            const double tr2 = a + bb + c;
+            const double big = 0.5 * (tr2 + sqrt(fmax(tr2 * tr2 - 4.0 * a * c, 0.0)));
+            const double small = a * c / big;
+            if (m == 2 || dqds_deflates(small, sh, e[m - 3])) {
+                ev[found++] = sh + (sl + small);
+                ev[found++] = sh + (sl + big);
+                m -= 2;
+                continue;
+            }
+        }
+        if (budget-- <= 0) break;
+        // Laguerre shift from S1 = tr A^{-1}, S2 = tr A^{-2}
+        double p = q[m - 1], v = -1.0;
+        double S1, S2;
+        {
+            const double ip = 1.0 / p;
+            S1 = ip;
+            S2 = -(u[m - 1] + v + 1.0) * ip * ip;
+        }
+        auto up = [&](double qk, double ek, double uk) {
+            const double rr = 1.0 / (ek + p);
+            v = __fma_rn(qk * ek * v, rr * rr, -1.0);
+            p = p * qk * rr;
+            const double ip = 1.0 / p;
+            S1 += ip;
+            S2 -= (uk + v + 1.0) * ip * ip;
+        };
+        int64_t k = m - 2;
+        for (; k >= 7; k -= 8) {  // loads of a block of rows first
+            double qk[8], ek[8], uk[8];
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+                qk[w] = q[k - w];
+                ek[w] = e[k - w];
+                uk[w] = u[k - w];
+            }
+#pragma unroll
+            for (int w = 0; w < 8; ++w) up(qk[w], ek[w], uk[w]);
+        }
+        for (; k >= 0; --k) up(q[k], e[k], u[k]);
+        const double fm = (double)m;
+        double s = fm / (S1 + sqrt(fmax((fm - 1.0) * (fm * S2 - S1 * S1), 0.0)));
+        s *= 1.0 - 8.0 * fm * EPS;
+        if (!(s > 0.0) || !isfinite(s)) s = 0.0;
+        bool ok = false;
+        for (int attempt = 0; attempt < 4 && !ok; ++attempt) {
+            if (attempt == 3) s = 0.0;
+            else if (attempt > 0) s *= 0.25;
+            double d = q[0] - s;
+            double un = -1.0;
+            ok = d > 0.0;
+            auto row = [&](int64_t j, double qn, double ej) {
+                const double rq = 1.0 / (d + ej);
+                const double t = qn * rq;
+                const double eh = ej * t;
+                q2[j] = d + ej;
+                e2[j] = eh;
+                u[j] = un;
+                un = __fma_rn(eh * rq, un, -1.0);
+                d = __fma_rn(d, t, -s);
+                ok = ok && d > 0.0;
+            };
+            int64_t j = 0;
+            for (; j + 8 < m && ok; j += 8) {  // a failed block is discarded with the rest
+                double qn[8], ej[8];
+#pragma unroll
+                for (int w = 0; w < 8; ++w) {
+                    qn[w] = q[j + 1 + w];
+                    ej[w] = e[j + w];
+                }
+#pragma unroll
+                for (int w = 0; w < 8; ++w) row(j + w, qn[w], ej[w]);
+            }
+            for (; j + 1 < m && ok; ++j) row(j, q[j + 1], e[j]);
+            q2[m - 1] = d;
+            u[m - 1] = un;
+            ++steps;
+        }
+        if (!ok) break;
+        double* tq = q;
+        q = q2;
+        q2 = tq;
+        double* te = e;
+        e = e2;
+        e2 = te;
+        const double x = sh + s, bv = x - sh;
+        sl += (sh - (x - bv)) + (s - bv);
+        sh = x;
+    }
+    // an unfinished array leaves rough estimates; the bracket check repairs them
+    for (int64_t k = 0; k < m; ++k) ev[found++] = sh + (sl + q[k]);
+    for (int64_t k = 1; k < n; ++k) {
+        const double val = ev[k];
+        int64_t j = k - 1;
+        while (j >= 0 && ev[j] > val) {
+            ev[j + 1] = ev[j];
+            --j;
+        }
+        ev[j + 1] = val;
+    }
+    const double w0 = 4.0 * (double)n * EPS;
+    for (int64_t k = 0; k < bk.nslot; ++k) {
+        const int64_t sidx = bk.slot0 + k;
+        const int64_t j = slots[sidx].idx;  // 1-based index among the eigenvalues of M
+        const double lam = (sg > 0.0) ? ev[j - 1] : -ev[n - j];
+        const double w = w0 * fabs(lam) + 1e-300;
+        slots[sidx].lo = lam - w;
+        slots[sidx].hi = lam + w;
+    }
+    atomicAdd(transforms, steps);
 }
 
 // ---------------------------------------------------------------------------

@@ -286,7 +286,7 @@ enum BufId {
     B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BLOCKS, B_SLOTS, B_NODES, B_REPD, B_REPL, B_REPE,
     B_D64, B_L64, B_P, B_PE, B_Q, B_QE, B_LIST, B_LIST2, B_CNT, B_TILEOFF, B_TILES, B_RES,
     B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_M, B_BAD, B_COUNTERS,
-    B_BOFF, B_CREC, B_CHECK, B_NSLOT, B_SLOT0, B_GKEY, B_GVAL, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_NBUF
+    B_BOFF, B_CREC, B_CHECK, B_NSLOT, B_SLOT0, B_GKEY, B_GVAL, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_DQDS, B_DQB, B_NBUF
 };
 
 // singleton work of tree level d runs on the handle's side stream with the
@@ -414,6 +414,7 @@ static Params effective(const mr3_handle_s* h, int precision) {
     p.rqi_max_iter = (h->have_user && u.rqi_max_iter > 0) ? u.rqi_max_iter : d.rqi_max_iter;
     p.lanes_per_eig = h->have_user ? u.lanes_per_eig : 0;
     p.points_per_lane = h->have_user ? u.points_per_lane : 0;
+    p.initial = h->have_user ? u.initial : MR3_INITIAL_BISECTION;
     p.force_rqi_fallback = h->have_user ? u.force_rqi_fallback : 0;
     p.force_best_candidate = h->have_user ? u.force_best_candidate : 0;
     p.seed = (h->have_user && u.seed) ? u.seed : d.seed;
@@ -772,6 +773,19 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     int64_t k_staged = 0;
     for (int64_t b = 0; b < NB; ++b)
         if (blocks[b].n >= STAGE_MIN_N && !no_stage()) k_staged += blocks[b].nslot;
+    // roots whose whole spectrum is wanted may start from dqds values instead
+    // (one lane per root); their brackets are then checked by Sturm counts
+    std::vector<int> dq_blocks;
+    std::vector<char> is_dq((size_t)NB, 0);
+    bool dq_staged = false;
+    if (prm.initial == MR3_INITIAL_DQDS)
+        for (int64_t b = 0; b < NB; ++b)
+            if (blocks[b].nslot > 0 && blocks[b].nslot == blocks[b].n && blocks[b].n <= MR3_DQDS_MAX_N) {
+                dq_blocks.push_back((int)b);
+                is_dq[b] = 1;
+                dq_staged |= blocks[b].n >= STAGE_MIN_N && !no_stage();
+            }
+    stats.n_dqds_roots = (int64_t)dq_blocks.size();
     BisectShape L = pick_shape(K - k_staged, prm.lanes_per_eig, prm.points_per_lane);
     const BisectShape Ls = pick_shape_staged(k_staged, prm.lanes_per_eig);
     std::vector<BisWG> rwgs;
@@ -796,6 +810,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     // eigenvalues"), 4 when the copy is the representation itself
     const double widen_root = (is_dd ? 10.0 : 4.0) * 1.1102230246251565e-16;  // x n_block
     prof.begin(MR3_STAGE_BISECT, st);
+    if (!dq_blocks.empty()) {
+        HIPCHK(B[B_DQDS].ensure(sizeof(double) * 6 * (size_t)R));
+        HIPCHK(upload(B[B_DQB], dq_blocks, st));
+        const int nq = (int)dq_blocks.size();
+        hipLaunchKernelGGL(k_dqds, dim3((unsigned)((nq + 63) / 64)), dim3(64), 0, st,
+                           B[B_DQB].as<int>(), nq, dblocks, dnodes, B[B_D64].rows<double>(),
+                           B[B_L64].rows<double>(), B[B_DQDS].as<double>(), dslots, counters + 4);
+    }
     // staged (large) roots: spectrum slicing first; it proves every bracket,
     // and a bracket it cannot prove keeps the root interval, which holds by
     // construction (definite root, Gerschgorin bounds with slack)
@@ -804,12 +826,13 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         int64_t tot = 0;
         for (int64_t b = 0; b < NB; ++b) {
             soff.push_back(tot);
-            if (blocks[b].n >= STAGE_MIN_N && blocks[b].nslot > 0) tot += slice_points(blocks[b].nslot);
+            if (blocks[b].n >= STAGE_MIN_N && blocks[b].nslot > 0 && !is_dq[b])
+                tot += slice_points(blocks[b].nslot);
         }
         if (tot > 0) {
             HIPCHK(B[B_SLICE].ensure(sizeof(int) * tot));
             for (int64_t b = 0; b < NB; ++b) {
-                if (blocks[b].n < STAGE_MIN_N || blocks[b].nslot <= 0) continue;
+                if (blocks[b].n < STAGE_MIN_N || blocks[b].nslot <= 0 || is_dq[b]) continue;
                 const int64_t M = slice_points(blocks[b].nslot);
                 int* cnt = B[B_SLICE].as<int>() + soff[b];
                 hipLaunchKernelGGL(k_slice, dim3((unsigned)(M / STAGE_ROWS)), dim3(STAGE_ROWS), 0, st,
@@ -822,7 +845,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     }
     launch_bisect_staged(Ls, B[B_BWG].as<BisWG>(), (int64_t)rwgs.size(), B[B_LIST].as<int64_t>(),
                          dslots, dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
-                         prm.bisect_rel, widen_root, work, 0, st);
+                         prm.bisect_rel, widen_root, work, dq_staged ? 1 : 0, st);
     if (k_small > 0)
         launch_bisect(L, B[B_LIST].as<int64_t>(), K, dslots, dnodes, dblocks,
                       B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel, widen_root,
@@ -1230,6 +1253,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(download(sts, status, 1, st));
     stats.n_rqi_iters = (int64_t)ctr[0];
     stats.n_fallbacks = (int64_t)ctr[1];
+    stats.dqds_transforms = (int64_t)ctr[4];
     std::vector<double> wk;
     HIPCHK(download(wk, work, 4, st));
     stats.bisect_row_steps = wk[0];
@@ -1427,6 +1451,7 @@ int mr3_default_params(mr3_params* p, int precision) {
 int mr3_set_params(mr3_handle h, const mr3_params* p) {
     if (!h) return -1;
     if (p) {
+        if (p->initial != MR3_INITIAL_BISECTION && p->initial != MR3_INITIAL_DQDS) return -2;
         h->user = *p;
         h->have_user = true;
     } else {

@@ -63,7 +63,6 @@ struct BlockInfo {    // written by the preprocessing kernel, one per block
 
 struct Block {        // assembled by the host
     int prob;
-    int end_right;    // root shift at the right end of the spectrum
     int64_t row0;     // internal row of the first row
     int64_t start;    // first row within the problem
     int64_t n;
@@ -116,6 +115,7 @@ struct Params {
     int rqi_max_iter;
     int lanes_per_eig;
     int points_per_lane;
+    int initial;          // MR3_INITIAL_*
     int force_rqi_fallback;
     int force_best_candidate;
     int profile;

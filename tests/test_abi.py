@@ -50,8 +50,8 @@ int main(void) {
     printf("mr3_params %zu\nmr3_stats %zu\nmr3_range_desc %zu\nmr3_request %zu\nmr3_result %zu\n",
            sizeof(mr3_params), sizeof(mr3_stats), sizeof(mr3_range_desc), sizeof(mr3_request),
            sizeof(mr3_result));
-    F(mr3_params, seed) F(mr3_params, profile) F(mr3_params, points_per_lane) F(mr3_params, gaptol_abs)
-    F(mr3_stats, stage_ms) F(mr3_stats, twist_row_steps)
+    F(mr3_params, seed) F(mr3_params, profile) F(mr3_params, points_per_lane) F(mr3_params, gaptol_abs) F(mr3_params, initial)
+    F(mr3_stats, stage_ms) F(mr3_stats, twist_row_steps) F(mr3_stats, dqds_transforms)
     F(mr3_request, range) F(mr3_request, ldz) F(mr3_result, batch_size)
     return 0;
 }

@@ -128,3 +128,25 @@ def test_batched_c3_shape_sampled(mr3):
         p = probs[i]
         _check_problem(p[0], p[1], ("all", 0.0, 0.0, 1, p[0].size), Wb[i].double().cpu().numpy(),
                        Zb[i].double().cpu().numpy(), f"C3 problem {i}")
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_batched_dqds_initial_values(mr3, dtype):
+    """dqds initial values in a batch: every problem whose whole spectrum is
+    wanted starts from dqds (one lane per root), the others from bisection;
+    all meet the gates."""
+    probs = W.batch_normal(48, 32, 700, seed=13, dtype=dtype)
+    ranges = _ranges_for([p[0].size for p in probs], 17)
+    kinds = {"all": 0, "value": 1, "index": 2}
+    desc = [(kinds[r[0]], r[1], r[2], r[3], r[4]) for r in ranges]
+    h = mr3.Handle(0)
+    h.set_params(precision=32 if dtype == np.float32 else 64, initial=mr3.MR3_INITIAL_DQDS)
+    print(f"batched dqds {len(probs)} problems dtype={np.dtype(dtype).name}", flush=True)
+    Wb, Zb = mr3.solve_batched([_dev(p[0]) for p in probs], [_dev(p[1]) for p in probs],
+                               ranges=desc, handle=h)
+    torch.cuda.synchronize()
+    whole = sum(1 for r in ranges if r[0] == "all")
+    assert h.stats()["n_dqds_roots"] >= whole
+    for i, (p, r) in enumerate(zip(probs, ranges)):
+        _check_problem(p[0], p[1], r, Wb[i].double().cpu().numpy(), Zb[i].double().cpu().numpy(),
+                       f"dqds problem {i} n={p[0].size} range={r}")

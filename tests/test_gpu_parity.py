@@ -282,3 +282,51 @@ def test_gaptol_settings(mr3):
     h.set_params(precision=32, gaptol=1e-6)
     d32, e32 = W.uniform(700, 8, np.float32)
     run_case(mr3, d32, e32, handle=h)
+
+
+def test_dqds_initial_values(mr3):
+    """Initial eigenvalues from dqds (one lane per root whose whole spectrum is
+    wanted, Sec. 4.1) instead of bisection: the same gates against the oracle,
+    the same eigenvalues as the bisection path to the gate, and the stats show
+    which roots took dqds.  Subsets and roots above the size limit keep
+    bisection."""
+    h = mr3.Handle(0)
+    ref = mr3.Handle(0)
+    d_split, e_split = W.uniform(90, 4, np.float64)
+    e_split[29] = 0.0
+    e_split[59] = 1e-300
+    cases = [
+        ("uniform n=200 fp64", W.uniform(200, 3, np.float64), 1),
+        ("1-2-1 n=300 fp64", W.toeplitz_121(300, np.float64), 1),
+        ("glued Wilkinson n=336", W.glued_wilkinson(336), 1),
+        ("uniform n=512 fp32", W.uniform(512, 0, np.float32), 1),
+        ("prescribed n=600", W.prescribed_spectrum(600, 1)[:2], 1),
+        ("Clement n=101 fp32", W.clement(101, np.float32), 1),
+        ("split into three", (d_split, e_split), 3),
+        ("n=2 fp64", W.uniform(2, 5, np.float64), 1),
+    ]
+    for name, (d, e), roots in cases:
+        prec = 32 if d.dtype == np.float32 else 64
+        h.set_params(precision=prec, initial=mr3.MR3_INITIAL_DQDS)
+        print("dqds case", name, flush=True)
+        run_case(mr3, d, e, handle=h)
+        st = h.stats()
+        assert st["n_dqds_roots"] == roots, (name, st["n_dqds_roots"])
+        assert d.size < 3 or st["dqds_transforms"] > 0, name
+        ref.set_params(precision=prec)
+        wb, _ = mr3.solve(_dev(d), _dev(e), vectors=False, handle=ref)
+        wd, _ = mr3.solve(_dev(d), _dev(e), vectors=False, handle=h)
+        n = d.size
+        tn = M.tnorm(d.astype(np.float64), e.astype(np.float64))
+        diff = float((wb.double() - wd.double()).abs().max())
+        assert diff <= 4 * n * M.eps_of(d.dtype) * tn, (name, diff)
+    # a subset, and a root above the size limit, keep bisection
+    d, e, _ = W.prescribed_spectrum(600, 1)
+    h.set_params(precision=64, initial=mr3.MR3_INITIAL_DQDS)
+    run_case(mr3, d, e, rng="index", il=20, iu=80, handle=h)
+    assert h.stats()["n_dqds_roots"] == 0
+    d, e = W.uniform(mr3.MR3_DQDS_MAX_N + 1, 6, np.float32)
+    mr3.solve(_dev(d), _dev(e), vectors=False, handle=h)
+    assert h.stats()["n_dqds_roots"] == 0
+    with pytest.raises(mr3.MR3Error):
+        h.set_params(precision=64, initial=7)
