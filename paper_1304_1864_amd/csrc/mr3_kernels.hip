@@ -1646,6 +1646,18 @@ __device__ __forceinline__ SweepStep<Y> get_sweep_step(const SweepWin<Y>& win, i
     return w;
 }
 
+// k_rqi runs up to RQI_WAVES independent waves per workgroup, one chunk each
+// (blockDim.x / 64 of them); the waves of a workgroup share the CU's L1, which
+// pays when their chunks sweep the same representation.  A wave synchronises
+// only with itself: its lanes exchange data through its own LDS windows and
+// its tile.
+constexpr int RQI_WAVES = 4;
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // LDS window of the binary64 twist search: the copy's rows of both streams,
 // roles swapped in the bottom stream as in the sweeps.
 struct TwistWin {
@@ -1666,7 +1678,7 @@ __device__ void prepass_staged(bool top, const double* __restrict__ D,
                                int64_t s0b, int64_t cnt, double& a, double& b, bool combine,
                                double* __restrict__ col, double& gmin, int64_t& rmin,
                                TwistWin& win) {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x & 63;
     const int side = top ? 0 : 1;
     const int64_t s0 = top ? s0t : s0b;
     int64_t cmax = cnt;
@@ -1685,7 +1697,7 @@ __device__ void prepass_staged(bool top, const double* __restrict__ D,
         win.f[0][t >> 5][t & 31] = w.x;
         win.g[0][t >> 5][t & 31] = w.y;
     }
-    __syncthreads();
+    wave_sync();
     // tile values of the next block of 8 steps
     double ctn[8];
 #pragma unroll
@@ -1742,7 +1754,7 @@ __device__ void prepass_staged(bool top, const double* __restrict__ D,
         }
         win.f[cur ^ 1][t >> 5][t & 31] = nx.x;
         win.g[cur ^ 1][t >> 5][t & 31] = nx.y;
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -1757,7 +1769,7 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
                                 const Y* __restrict__ Q, const int* __restrict__ Qe, int64_t n,
                                 int64_t r, Y tau, double* __restrict__ col, bool store,
                                 int64_t steps, SweepWin<Y>& win) {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x & 63;
     const int side = top ? 0 : 1;
     Half<Y> h;
     h.ss = 0.0;
@@ -1776,7 +1788,7 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
     for (int off = 32; off > 0; off >>= 1) smax = max(smax, (int64_t)__shfl_xor(smax, off, 64));
     put_sweep_step<Y>(win, 0, t >> 5, t & 31,
                       load_sweep_step<Y>(t >> 5, t & 31, D, LL, P, Pe, Q, Qe, n));
-    __syncthreads();
+    wave_sync();
     auto zvalue = [&](const SweepStep<Y>& w, int64_t k, bool check) -> double {
         const double pb = prod_hi(w.pq, b);
         int ex = w.pqe + eb - eref;
@@ -1836,30 +1848,35 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
             }
         }
         put_sweep_step<Y>(win, cur ^ 1, t >> 5, t & 31, nx);
-        __syncthreads();
+        wave_sync();
     }
     h.sp = div(a, b);  // s_r = a_r / b_r  or  p_r = alpha_r / beta_r
     return h;
 }
 
 template <class Y>
-__global__ void __launch_bounds__(64)
-k_rqi(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
+__global__ void __launch_bounds__(64 * RQI_WAVES)
+k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __restrict__ list,
       const int64_t* __restrict__ tile_off, double* __restrict__ tiles, const Slot* __restrict__ slots, const Node* __restrict__ nodes,
       const Block* __restrict__ blocks, const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld,
       const double* __restrict__ d64, const double* __restrict__ lld64, const Y* __restrict__ P,
       const int* __restrict__ Pe, const Y* __restrict__ Q, const int* __restrict__ Qe, Params prm,
       double eps_y, RqiResult* __restrict__ res, unsigned long long* __restrict__ counters,
       double* __restrict__ work) {
-    __shared__ SweepWin<Y> win;
-    __shared__ TwistWin twin;
-    const int lane = threadIdx.x;
+    __shared__ SweepWin<Y> wins[RQI_WAVES];
+    __shared__ TwistWin twins[RQI_WAVES];
+    const int wv = threadIdx.x >> 6;
+    const int64_t cidx = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+    if (cidx >= nchunks) return;  // the whole wave: no workgroup barrier follows
+    SweepWin<Y>& win = wins[wv];
+    TwistWin& twin = twins[wv];
+    const int lane = threadIdx.x & 63;
     const int pair = lane >> 1;
     const bool top = (lane & 1) == 0;
-    const ChunkInfo ck = chunks[blockIdx.x];
+    const ChunkInfo ck = chunks[cidx];
     const int64_t idx = ck.begin + pair;
     const bool active = pair < ck.count;
-    double* tile = tiles + tile_off[blockIdx.x] + pair;
+    double* tile = tiles + tile_off[cidx] + pair;
     // every pair of the chunk belongs to the same node
     const Node nd = nodes[slots[list[ck.begin]].node];
     const Block bk = blocks[nd.block];
@@ -1889,7 +1906,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
     double gmin = INFINITY;
     int64_t rmin = n / 2;
     prepass_staged(top, D64, LL64, n, tau0, 0, 0, len1, a, b, false, tile, gmin, rmin, twin);
-    __syncthreads();
+    wave_sync();
     prepass_staged(top, D64, LL64, n, tau0, hh, n - hh, len2, a, b, true, tile, gmin, rmin, twin);
     {
         const double go = __shfl_xor(gmin, 1, 64);
@@ -1898,7 +1915,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
     }
     int64_t r = rmin;
     if (r < 0 || r >= n) r = n / 2;
-    __syncthreads();
+    wave_sync();
     // ---- RQI in y at a fixed twist ----
     const double sqn = sqrt((double)(n > 0 ? n : 1));
     const double tol = prm.k_rs * gap * prm.eps_x * sqn;
@@ -2075,7 +2092,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
     // exchange the per-lane storage bookkeeping and publish the result
     const double zmaxo = __shfl_xor(mine.zmax, 1, 64);
     const int64_t zmaxko = __shfl_xor(mine.zmaxk, 1, 64);
-    __syncthreads();  // both halves' final stores are visible in the tile
+    wave_sync();  // both halves' final stores are visible in the tile
     const int64_t ev1o = __shfl_xor(mine.ev1, 1, 64);
     const int64_t ev2o = __shfl_xor(mine.ev2, 1, 64);
     const double ev2fo = __shfl_xor(mine.ev2f, 1, 64);

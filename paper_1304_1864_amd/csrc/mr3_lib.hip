@@ -856,27 +856,38 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     bool any_multi = false;
     for (int64_t p = 0; p < count; ++p) any_multi |= (multi[p] && m_p[p] > 0);
     if (any_multi) {
-        std::vector<Slot> cur;
-        HIPCHK(download(cur, dslots, (size_t)K, st));
+        // only the slots of split problems move: each problem's blocks hold a
+        // contiguous slot range, which is read, ordered and written back
+        std::vector<std::vector<int64_t>> pblocks((size_t)count);
+        for (int64_t b = 0; b < NB; ++b)
+            if (multi[blocks[b].prob]) pblocks[blocks[b].prob].push_back(b);
         std::vector<Node> roots;
         HIPCHK(download(roots, dnodes, (size_t)NB, st));
         for (int64_t p = 0; p < count; ++p) {
-            if (!multi[p]) continue;
-            std::vector<std::pair<double, int64_t>> v;
-            for (int64_t b = 0; b < NB; ++b) {
-                if (blocks[b].prob != p) continue;
-                for (int64_t s = blocks[b].slot0; s < blocks[b].slot0 + blocks[b].nslot; ++s)
-                    if (cur[s].out == -2)
-                        v.push_back({roots[b].sigma_hi + 0.5 * (cur[s].lo + cur[s].hi), s});
+            if (!multi[p] || m_p[p] <= 0 || pblocks[p].empty()) continue;
+            int64_t s0 = INT64_MAX, s1 = 0;
+            for (int64_t b : pblocks[p]) {
+                if (blocks[b].nslot <= 0) continue;
+                s0 = std::min(s0, blocks[b].slot0);
+                s1 = std::max(s1, blocks[b].slot0 + blocks[b].nslot);
             }
+            if (s1 <= s0) continue;
+            std::vector<Slot> cur;
+            HIPCHK(download(cur, dslots + s0, (size_t)(s1 - s0), st));
+            std::vector<std::pair<double, int64_t>> v;
+            for (int64_t b : pblocks[p])
+                for (int64_t s = blocks[b].slot0; s < blocks[b].slot0 + blocks[b].nslot; ++s)
+                    if (cur[s - s0].out == -2)
+                        v.push_back({roots[b].sigma_hi + 0.5 * (cur[s - s0].lo + cur[s - s0].hi), s});
             std::stable_sort(v.begin(), v.end(),
                              [](const std::pair<double, int64_t>& a, const std::pair<double, int64_t>& b) {
                                  return a.first < b.first;
                              });
-            for (size_t i = 0; i < v.size(); ++i) cur[v[i].second].out = (int64_t)i;
+            for (size_t i = 0; i < v.size(); ++i) cur[v[i].second - s0].out = (int64_t)i;
+            HIPCHK(hipMemcpyAsync(dslots + s0, cur.data(), sizeof(Slot) * cur.size(),
+                                  hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
         }
-        HIPCHK(upload(B[B_SLOTS], cur, st));
-        dslots = B[B_SLOTS].as<Slot>();
     }
     // ---- levels of the representation trees ----
     std::vector<int64_t> level_nodes((size_t)NB);
@@ -1006,8 +1017,13 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             HIPCHK(hipEventRecord(h->ev_fork, st));
             HIPCHK(hipStreamWaitEvent(side, h->ev_fork, 0));
             prof.begin(MR3_STAGE_RQI, side);
-            hipLaunchKernelGGL(k_rqi<Y>, dim3((unsigned)nchunk), dim3(64), 0, side,
-                               SCK.as<ChunkInfo>(), SL.as<int64_t>(), STO.as<int64_t>(),
+            // several waves per workgroup when few chunks sweep large nodes
+            // (they share rows through L1); one when many small problems'
+            // chunks of unequal lengths would hold each other's CU slots
+            const int wpg = nchunk <= 2048 ? RQI_WAVES : 1;
+            hipLaunchKernelGGL(k_rqi<Y>, dim3((unsigned)((nchunk + wpg - 1) / wpg)), dim3(64 * wpg),
+                               0, side, SCK.as<ChunkInfo>(), (int64_t)nchunk,
+                               SL.as<int64_t>(), STO.as<int64_t>(),
                                STI.rows<double>(32), dslots,
                                dnodes, dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
                                B[B_D64].rows<double>(), B[B_L64].rows<double>(), B[B_P].rows<Y>(),
