@@ -1543,8 +1543,8 @@ k_classify(const int64_t* __restrict__ node_list, int64_t count, const Node* __r
 // Per-lane sweep output.  z is stored in a scaled frame: when a stored value
 // would pass about 2^300 the frame is rebased (an "event" at that row).  The
 // output kernel multiplies values stored before the last event by ev2f and
-// zeroes those stored before the one-but-last, which lie below 2^-250 of the
-// final maximum.  z values are products of the leading parts (binary64
+// zeroes those stored before the one-but-last, which lie below 2^-300 times
+// the growth of z over four rows, relative to the final maximum.  z values are products of the leading parts (binary64
 // accuracy, all the output needs).
 template <class Y>
 struct Half {
@@ -1759,10 +1759,15 @@ __device__ void prepass_staged(bool top, const double* __restrict__ D,
 }
 
 // One sweep of every lane of the chunk's wave (all 64 threads call it; lanes
-// with steps == 0 only help with the loads).  Same arithmetic as the
-// per-lane sweep: the top lane runs the stationary transform over rows 0..r,
-// the bottom lane the progressive one over rows n-1..r, each storing its part
-// of z in its tile column with the same storage rebasing.
+// with steps == 0 only help with the loads).  The top lane runs the
+// stationary transform over rows 0..r, the bottom lane the progressive one
+// over rows n-1..r, each storing its part of z in its tile column.  Steps go
+// in groups of four: the pair (a, b) is rescaled after each group, and the
+// storage frame is checked on the group's last value (and on the twist row).
+// Between checks a stored value grows by at most four rows' growth of z, so
+// values stay far below overflow (and their squares in ss) for per-row growth
+// up to 2^50.  Book-keeping is by step index (32-bit), turned into rows at
+// the end.
 template <class Y>
 __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __restrict__ LL,
                                 const Y* __restrict__ P, const int* __restrict__ Pe,
@@ -1772,24 +1777,25 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
     const int t = threadIdx.x & 63;
     const int side = top ? 0 : 1;
     Half<Y> h;
-    h.ss = 0.0;
-    h.zmax = 0.0;
-    h.zmaxk = -1;
     h.zr = 0.0;
-    h.ev1 = top ? 0 : n;
-    h.ev2 = top ? 0 : n;
-    h.ev2f = 1.0;
+    double ss = 0.0, zmax = 0.0;
+    int zmi = -1;                        // step of the largest stored |z|
+    int ev1 = 0, ev2 = 0, ev2e = 0;      // steps of the last two rebasings, last shift
     Y a = neg(tau), b = y_from(1.0, Y());
     if (!top && steps > 0) a = sub(D[n - 1], tau);
     int eb = 0;    // binary exponent carried by b
     int eref = 0;  // storage frame exponent
-    int64_t smax = steps;
+    const int nsteps = (int)steps;
+    int smax = nsteps;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) smax = max(smax, (int64_t)__shfl_xor(smax, off, 64));
+    for (int off = 32; off > 0; off >>= 1) smax = max(smax, __shfl_xor(smax, off, 64));
+    double* zp = col + (top ? (int64_t)0 : (n - 1) * 32);  // tile row of the current step
+    const int64_t zstep = top ? 32 : -32;
     put_sweep_step<Y>(win, 0, t >> 5, t & 31,
                       load_sweep_step<Y>(t >> 5, t & 31, D, LL, P, Pe, Q, Qe, n));
     wave_sync();
-    auto zvalue = [&](const SweepStep<Y>& w, int64_t k, bool check) -> double {
+    // the value of z at a step, after the storage check when `check`
+    auto zvalue = [&](const SweepStep<Y>& w, int it, bool check) -> double {
         const double pb = prod_hi(w.pq, b);
         int ex = w.pqe + eb - eref;
         if (check) {
@@ -1798,52 +1804,52 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
             const int dlt = rb ? ez : 0;
             eref += dlt;
             ex -= dlt;
-            h.ss = __builtin_ldexp(h.ss, -2 * dlt);
-            h.zmax = __builtin_ldexp(h.zmax, -dlt);
-            h.ev1 = rb ? h.ev2 : h.ev1;
-            h.ev2 = rb ? k : h.ev2;
-            h.ev2f = rb ? __builtin_ldexp(1.0, -dlt) : h.ev2f;
+            ss = __builtin_ldexp(ss, -2 * dlt);
+            zmax = __builtin_ldexp(zmax, -dlt);
+            ev1 = rb ? ev2 : ev1;
+            ev2 = rb ? it : ev2;
+            ev2e = rb ? dlt : ev2e;
         }
         return __builtin_ldexp(pb, ex);
     };
-    auto body = [&](const SweepStep<Y>& w, int64_t it, int u) {
-        const int64_t k = top ? it : n - 1 - it;
-        const double zv = zvalue(w, k, (u & 1) == 1);
-        if (store) col[k * 32] = zv;
-        h.ss = __fma_rn(zv, zv, h.ss);
-        const bool bigger = fabs(zv) > h.zmax;
-        h.zmax = bigger ? fabs(zv) : h.zmax;
-        h.zmaxk = bigger ? k : h.zmaxk;
+    auto body = [&](const SweepStep<Y>& w, int it, bool last_of_group) {
+        const double zv = zvalue(w, it, last_of_group);
+        if (store) *zp = zv;
+        zp += zstep;
+        ss = __fma_rn(zv, zv, ss);
+        const bool bigger = fabs(zv) > zmax;
+        zmax = fmax(zmax, fabs(zv));
+        zmi = bigger ? it : zmi;
         const Y c = mul_add(w.f, b, a);
         a = mul_sub(w.g, a, tau, c);
         b = c;
-        if ((u & 3) == 3) {
+        if (last_of_group) {
             const int em = max(y_exp(a), y_exp(b));
             a = y_ldexp(a, -em);
             b = y_ldexp(b, -em);
             eb += em;
         }
     };
-    for (int64_t it0 = 0; it0 < smax; it0 += SW) {
-        const int cur = (int)((it0 / SW) & 1);
+    for (int it0 = 0; it0 < smax; it0 += SW) {
+        const int cur = (it0 / SW) & 1;
         const SweepStep<Y> nx = load_sweep_step<Y>(t >> 5, it0 + SW + (t & 31), D, LL, P, Pe, Q, Qe, n);
-        if (it0 + SW < steps) {
+        if (it0 + SW < nsteps) {
             // the twist row lies beyond this window: straight-line steps
             for (int u = 0; u < SW; u += 4) {
                 SweepStep<Y> w[4];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) w[v] = get_sweep_step<Y>(win, cur, side, u + v);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) body(w[v], it0 + u + v, v);
+                for (int v = 0; v < 4; ++v) body(w[v], it0 + u + v, v == 3);
             }
-        } else if (it0 < steps) {
-            // the window that ends with the twist row (step steps-1)
+        } else if (it0 < nsteps) {
+            // the window that ends with the twist row (step nsteps - 1)
             for (int u = 0; u < SW; ++u) {
-                const int64_t it = it0 + u;
-                if (it + 1 < steps) {
-                    body(get_sweep_step<Y>(win, cur, side, u), it, u);
-                } else if (it + 1 == steps) {
-                    h.zr = zvalue(get_sweep_step<Y>(win, cur, side, u), top ? it : n - 1 - it, true);
+                const int it = it0 + u;
+                if (it + 1 < nsteps) {
+                    body(get_sweep_step<Y>(win, cur, side, u), it, (u & 3) == 3);
+                } else if (it + 1 == nsteps) {
+                    h.zr = zvalue(get_sweep_step<Y>(win, cur, side, u), it, true);
                 }
             }
         }
@@ -1851,6 +1857,14 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
         wave_sync();
     }
     h.sp = div(a, b);  // s_r = a_r / b_r  or  p_r = alpha_r / beta_r
+    // steps to rows: step s is row s (top) or n-1-s (bottom)
+    auto row = [&](int s) -> int64_t { return top ? (int64_t)s : n - 1 - (int64_t)s; };
+    h.ss = ss;
+    h.zmax = zmax;
+    h.zmaxk = zmi < 0 ? -1 : row(zmi);
+    h.ev1 = row(ev1);
+    h.ev2 = row(ev2);
+    h.ev2f = __builtin_ldexp(1.0, -ev2e);
     return h;
 }
 
