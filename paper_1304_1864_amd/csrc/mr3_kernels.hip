@@ -1702,16 +1702,23 @@ __device__ void prepass_staged(bool top, const double* __restrict__ D,
     double ctn[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) ctn[v] = (combine && v < cnt) ? col[rowk(v) * 32] : 0.0;
-    auto step = [&](double f, double g, double ct, int64_t o) {
-        const int64_t k = rowk(o);
-        const double q = a / b;
+    // the quotient needs no correct rounding (it only ranks rows): the
+    // hardware reciprocal refined by one Newton step is within a few ulps.
+    // Ties go to the smallest row: the top lane visits rows upwards and keeps
+    // the first minimum, the bottom lane visits them downwards and keeps the
+    // last.
+    int omin = -1;
+    auto step = [&](double f, double g, double ct, int o) {
+        double rb = __builtin_amdgcn_rcp(b);
+        rb = __fma_rn(__fma_rn(-b, rb, 1.0), rb, rb);
+        const double q = a * rb;
         if (combine) {
             const double gv = fabs(q + ct + tau);
-            const bool take = gv < gmin || (gv == gmin && k < rmin);
+            const bool take = top ? (gv < gmin) : (gv <= gmin);
             gmin = take ? gv : gmin;
-            rmin = take ? k : rmin;
+            omin = take ? o : omin;
         } else {
-            col[k * 32] = q;
+            col[rowk(o) * 32] = q;
         }
         const double c = __fma_rn(f, b, a);
         a = __fma_rn(-tau, c, g * a);
@@ -1722,11 +1729,12 @@ __device__ void prepass_staged(bool top, const double* __restrict__ D,
             b = __builtin_ldexp(b, -em);
         }
     };
-    for (int64_t o0 = 0; o0 < cmax; o0 += SW) {
-        const int cur = (int)((o0 / SW) & 1);
+    const int icnt = (int)cnt, icmax = (int)cmax;
+    for (int o0 = 0; o0 < icmax; o0 += SW) {
+        const int cur = (o0 / SW) & 1;
         const double2 nx = load(t >> 5, o0 + SW + (t & 31));
-        if (o0 < cnt) {
-            const int m = (int)min<int64_t>(SW, cnt - o0);
+        if (o0 < icnt) {
+            const int m = min(SW, icnt - o0);
             int u = 0;
             for (; u + 8 <= m; u += 8) {
                 double ctc[8];
@@ -1735,8 +1743,8 @@ __device__ void prepass_staged(bool top, const double* __restrict__ D,
                 if (combine) {
 #pragma unroll
                     for (int v = 0; v < 8; ++v) {
-                        const int64_t o = o0 + u + 8 + v;
-                        ctn[v] = (o < cnt) ? col[rowk(o) * 32] : 0.0;
+                        const int o = o0 + u + 8 + v;
+                        ctn[v] = (o < icnt) ? col[rowk(o) * 32] : 0.0;
                     }
                 }
                 double f[8], g[8];
@@ -1756,6 +1764,7 @@ __device__ void prepass_staged(bool top, const double* __restrict__ D,
         win.g[cur ^ 1][t >> 5][t & 31] = nx.y;
         wave_sync();
     }
+    if (combine && omin >= 0) rmin = rowk(omin);
 }
 
 // One sweep of every lane of the chunk's wave (all 64 threads call it; lanes
