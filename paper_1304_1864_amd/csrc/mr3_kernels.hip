@@ -584,9 +584,11 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
         __syncthreads();
     }
     const int right = s_right;
-    // three more rounds of 255-point multisection on the chosen end
+    // one more round of 255-point multisection on the chosen end brackets the
+    // extreme eigenvalue to spdiam / 2^16, well inside the distance that mu
+    // keeps from it (below)
     const int64_t target = right ? n - 1 : 0;  // count threshold
-    for (int round = 0; round < 3; ++round) {
+    for (int round = 0; round < 1; ++round) {
         const double lo = s_lo, hi = s_hi;
         const double x = lo + (hi - lo) * ((double)(t + 1) / 256.0);
         sx[t] = x;
@@ -605,7 +607,13 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
     // shift and factor T - mu I = L D L^T in binary64 (continuant form:
     // q_i = (a_i - mu) q_{i-1} - e_{i-1}^2 q_{i-2},  d_i = q_i / q_{i-1}) by
     // thread 0, rows from the LDS window
-    double delta = fmax(2.0 * (s_hi - s_lo), 8.0 * (double)n * 1.1102230246251565e-16);
+    // mu stays at least 10^-3 spdiam outside the spectrum: the eigenvalues of
+    // M then all have |lambda| >= 10^-3 spdiam, so bisection to a relative
+    // width costs about as many passes at that end as anywhere else, and the
+    // relative gaps there only lose what a 10^-3 spdiam move of the origin
+    // takes
+    double delta = fmax(fmax(2.0 * (s_hi - s_lo), 8.0 * (double)n * 1.1102230246251565e-16),
+                        1e-3 * spd);
     for (int attempt = 0; attempt < 40; ++attempt) {
         const double mu = right ? s_hi + delta : s_lo - delta;
         int ok = 1;

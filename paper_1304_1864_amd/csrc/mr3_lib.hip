@@ -852,6 +852,13 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                       work, no_stage() ? INT64_MAX : STAGE_MIN_N, st);
     prof.end(st);
     HIPCHK(hipGetLastError());
+    if (debug_on()) {
+        std::vector<double> wk;
+        HIPCHK(download(wk, work, 8, st));
+        std::fprintf(stderr, "[mr3] root bisection: %lld intervals (%lld staged, lanes %d), passes max %.0f total %.0f\n",
+                     (long long)K, (long long)k_staged, Ls.L, wk[6], wk[7]);
+        HIPCHK(hipMemsetAsync(work + 6, 0, 2 * sizeof(double), st));
+    }
     // ---- output columns of split problems: order by eigenvalue ----
     bool any_multi = false;
     for (int64_t p = 0; p < count; ++p) any_multi |= (multi[p] && m_p[p] > 0);
