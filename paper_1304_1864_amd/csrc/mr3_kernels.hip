@@ -949,14 +949,24 @@ __device__ __forceinline__ void staged_counts(const double* __restrict__ D,
         b[p] = 1.0;
         neg[p] = 0;
     }
-    if (t < n) win[0][t] = make_double2(D[t], LL[t]);
+    // a workgroup of W threads loads STAGE_ROWS / W rows per thread
+    constexpr int RPT = STAGE_ROWS / 64;  // rows per thread, at most (W = 64)
+    const int W = blockDim.x;
+    for (int j = 0; j < RPT; ++j) {
+        const int rr = t + j * W;
+        if (rr < STAGE_ROWS && rr < n) win[0][rr] = make_double2(D[rr], LL[rr]);
+    }
     __syncthreads();
     for (int64_t c0 = 0; c0 < n; c0 += STAGE_ROWS) {
         const int cur = (int)((c0 / STAGE_ROWS) & 1);
         // next window: loaded now, stored after this window is processed
-        const int64_t nr = c0 + STAGE_ROWS + t;
-        double2 nx = make_double2(0.0, 0.0);
-        if (nr < n) nx = make_double2(D[nr], LL[nr]);
+        double2 nx[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int64_t nr = c0 + STAGE_ROWS + t + j * W;
+            nx[j] = make_double2(0.0, 0.0);
+            if (t + j * W < STAGE_ROWS && nr < n) nx[j] = make_double2(D[nr], LL[nr]);
+        }
         const int64_t left = n - c0;
         if (on) {
             if (left >= STAGE_ROWS) {
@@ -1004,7 +1014,9 @@ __device__ __forceinline__ void staged_counts(const double* __restrict__ D,
                 }
             }
         }
-        win[cur ^ 1][t] = nx;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+            if (t + j * W < STAGE_ROWS) win[cur ^ 1][t + j * W] = nx[j];
         __syncthreads();
     }
 }

@@ -483,11 +483,11 @@ static void launch_bisect(BisectShape sh, const int64_t* list, int64_t count, Sl
 static void launch_bisect_staged(BisectShape sh, const BisWG* wgs, int64_t nwg, const int64_t* list,
                                  Slot* slots, const Node* nodes, const Block* blocks,
                                  const double* d64, const double* l64, double rtol, double widen,
-                                 double* work, int check, hipStream_t st) {
+                                 double* work, int check, hipStream_t st, int waves = 4) {
     if (nwg <= 0) return;
 #define MR3_BST(LL, PP)                                                                        \
     if (sh.L == LL && sh.P == PP) {                                                            \
-        hipLaunchKernelGGL((k_bisect_staged<LL, PP>), dim3((unsigned)nwg), dim3(256), 0, st,   \
+        hipLaunchKernelGGL((k_bisect_staged<LL, PP>), dim3((unsigned)nwg), dim3(64 * waves), 0, st, \
                            wgs, list, slots, nodes, blocks, d64, l64, rtol, widen, work, check); \
         return;                                                                                \
     }
@@ -555,6 +555,29 @@ static BisectShape pick_shape(int64_t count, int user_lanes, int user_points) {
     }
     if (user_points == 1 || user_points == 2 || user_points == 4) sh.P = user_points;
     return sh;
+}
+
+// shape of the LDS-staged kernel for many small node-pure groups (the
+// members of the clusters of a level): a pass costs about the same while the
+// waves fit one per SIMD (1024) and proportionally more beyond, and gains
+// log2(L + 1) bits, so L minimises max(1, waves(L) / 1024) / log2(L + 1), with
+// waves(L) = sum over groups of ceil(size / (64 / L)) for one-wave workgroups
+static BisectShape pick_shape_groups(const std::vector<int64_t>& sizes, int user_lanes) {
+    static const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64};
+    BisectShape best{64, 1};
+    double best_cost = 1e300;
+    for (int L : cand) {
+        if (user_lanes > 0 && L > user_lanes) break;
+        const int64_t gw = 64 / L;
+        double waves = 0.0;
+        for (int64_t m : sizes) waves += (double)((m + gw - 1) / gw);
+        const double cost = std::max(1.0, waves / 1024.0) / std::log2((double)L + 1.0);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best.L = L;
+        }
+    }
+    return best;
 }
 
 // shape of the LDS-staged kernel, whose lane groups need not divide the wave:
@@ -1197,17 +1220,21 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             if (job_n[c] >= STAGE_MIN_N && !no_stage()) KCs += crec[c].last - crec[c].head + 1;
         }
         L = pick_shape(KC - KCs, prm.lanes_per_eig, prm.points_per_lane);
-        BisectShape Lcs = pick_shape_staged(KCs, prm.lanes_per_eig);
-        if (const char* cs = std::getenv("MR3_CHILD_SHAPE")) {  // development aid: lanes
-            int l = 0;
-            if (std::sscanf(cs, "%d", &l) == 1) Lcs = pick_shape_staged(KCs, l);
+        // one wave per workgroup: the clusters of a level are many and small
+        const int cwaves = 1;
+        BisectShape Lcs;
+        {
+            std::vector<int64_t> sizes;
+            for (int64_t c = 0; c < C; ++c)
+                if (job_n[c] >= STAGE_MIN_N && !no_stage()) sizes.push_back(crec[c].last - crec[c].head + 1);
+            Lcs = pick_shape_groups(sizes, prm.lanes_per_eig);
         }
         BisectPlan cplan;
         {
             std::vector<int64_t> rest;
             for (int64_t c = 0; c < C; ++c)
                 cplan.add(jobs[c].child, job_n[c], crec[c].head, crec[c].last - crec[c].head + 1,
-                          4 * (64 / Lcs.L), rest);
+                          cwaves * (64 / Lcs.L), rest);
             cplan.finish(rest);
         }
         HIPCHK(upload(B[B_LIST], cplan.list, st));
@@ -1217,7 +1244,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         launch_bisect_staged(Lcs, B[B_BWG].as<BisWG>(), (int64_t)cplan.wgs.size(),
                              B[B_LIST].as<int64_t>(), dslots, dnodes, dblocks,
                              B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel,
-                             widen_root, work, 1, st);
+                             widen_root, work, 1, st, cwaves);
         launch_bisect(L, B[B_LIST].as<int64_t>() + cplan.n_staged, KC - cplan.n_staged, dslots,
                       dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
                       prm.bisect_rel, widen_root, work, INT64_MAX, st);
