@@ -67,7 +67,7 @@ def cpu_baseline(d, e, n, budget_s=20.0):
     import oracle
 
     threads = min(16, os.cpu_count() or 1)
-    chunk = 64
+    chunk = 512  # about 10-20 s of oracle work on 16 cores
     starts = [1, n // 4, n // 2, 3 * n // 4, n - chunk + 1]
     done = 0
     t0 = time.perf_counter()
