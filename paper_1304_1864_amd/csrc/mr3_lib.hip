@@ -1051,8 +1051,13 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             // (they share rows through L1); one when many small problems'
             // chunks of unequal lengths would hold each other's CU slots
             const int wpg = nchunk <= 2048 ? RQI_WAVES : 1;
+            // a multi-wave workgroup also asks for 48 KB of unused LDS: with its
+            // 34 KB of windows that is more than half of a CU's 160 KB, so each
+            // CU holds one such workgroup and its waves get a SIMD each (two
+            // workgroups on one CU would share SIMDs while other CUs idle)
+            const unsigned pad = wpg > 1 ? 48u * 1024u : 0u;
             hipLaunchKernelGGL(k_rqi<Y>, dim3((unsigned)((nchunk + wpg - 1) / wpg)), dim3(64 * wpg),
-                               0, side, SCK.as<ChunkInfo>(), (int64_t)nchunk,
+                               pad, side, SCK.as<ChunkInfo>(), (int64_t)nchunk,
                                SL.as<int64_t>(), STO.as<int64_t>(),
                                STI.rows<double>(32), dslots,
                                dnodes, dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
