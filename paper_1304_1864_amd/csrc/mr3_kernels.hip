@@ -2206,7 +2206,8 @@ k_zout(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
             // eigenvalue of T: lambda[M] + sigma, rounded to x, unscaled
             Y lam = add_acc(mk_y<Y>(o.lam_hi, o.lam_lo), mk_y<Y>(nd.sigma_hi, nd.sigma_lo));
             const ProbDesc pd = probs[p];
-            reinterpret_cast<X*>(pd.wout)[sl.out] = (X)__builtin_ldexp(to_double(lam), -sexp);
+            if (blockIdx.y == 0)
+                reinterpret_cast<X*>(pd.wout)[sl.out] = (X)__builtin_ldexp(to_double(lam), -sexp);
             s_n[t] = bk.n;
             s_r[t] = o.r;
             s_fT[t] = o.fT;
@@ -2231,10 +2232,18 @@ k_zout(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
     if (!any_z) return;
     const int64_t rows = s_rows;
     const int wv = t >> 6, ln = t & 63;
-    for (int64_t r0 = 0; r0 < rows; r0 += 64) {
+    // only the columns of the chunk's pairs are read (a chunk of a small
+    // cluster child fills few of its 32); the rows are split over gridDim.y
+    // workgroups in blocks of 64
+    const int ncol = ck.count;
+    const int64_t nblk = (rows + 63) / 64;
+    const int64_t bper = (nblk + gridDim.y - 1) / gridDim.y;
+    const int64_t rbeg = min<int64_t>(rows, (int64_t)blockIdx.y * bper * 64);
+    const int64_t rend = min<int64_t>(rows, rbeg + bper * 64);
+    for (int64_t r0 = rbeg; r0 < rend; r0 += 64) {
         for (int e = t; e < 64 * 32; e += 256) {
             const int rr = e >> 5, cc = e & 31;
-            buf[rr][cc] = (r0 + rr < rows) ? tile[(r0 + rr) * 32 + cc] : 0.0;
+            if (cc < ncol) buf[rr][cc] = (r0 + rr < rows) ? tile[(r0 + rr) * 32 + cc] : 0.0;
         }
         __syncthreads();
         for (int cc = wv * 8; cc < wv * 8 + 8; ++cc) {

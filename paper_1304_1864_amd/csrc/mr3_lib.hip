@@ -919,6 +919,9 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             HIPCHK(hipStreamSynchronize(st));
         }
     }
+    int64_t nmax_blocks = 1;
+    for (const Block& bk : blocks) nmax_blocks = std::max(nmax_blocks, bk.n);
+    const int zsplit = (int)std::min<int64_t>(16, std::max<int64_t>(1, nmax_blocks / 2048));
     // ---- levels of the representation trees ----
     std::vector<int64_t> level_nodes((size_t)NB);
     std::iota(level_nodes.begin(), level_nodes.end(), 0);
@@ -1066,7 +1069,9 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                                (double)YEps<Y>::v, SRE.as<RqiResult>(), counters, work);
             prof.end(side);
             prof.begin(MR3_STAGE_ZOUT, side);
-            hipLaunchKernelGGL((k_zout<X, Y>), dim3((unsigned)nchunk), dim3(256), 0, side,
+            // rows of a chunk are split over zsplit workgroups (blocks of 64
+            // rows), so that large nodes' output is not one serial loop
+            hipLaunchKernelGGL((k_zout<X, Y>), dim3((unsigned)nchunk, (unsigned)zsplit), dim3(256), 0, side,
                                SCK.as<ChunkInfo>(), SL.as<int64_t>(), STO.as<int64_t>(),
                                STI.rows<double>(32), dslots,
                                dnodes, dblocks, B[B_PINFO].as<ProbInfo>(), SRE.as<RqiResult>(),
