@@ -613,7 +613,7 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
     // relative gaps there only lose what a 10^-3 spdiam move of the origin
     // takes
     double delta = fmax(fmax(2.0 * (s_hi - s_lo), 8.0 * (double)n * 1.1102230246251565e-16),
-                        1e-3 * spd);
+                        prm.root_gap * spd);
     for (int attempt = 0; attempt < 40; ++attempt) {
         const double mu = right ? s_hi + delta : s_lo - delta;
         int ok = 1;
@@ -1338,6 +1338,11 @@ k_slice(const Block* __restrict__ blocks, int b, const Node* __restrict__ nodes,
     int c[1];
     staged_counts<1>(d64 + nd.rep, lld64 + nd.rep, blk.n, xs, c, true, win);
     cnt[m] = c[0];
+    // the root interval, for k_slice_assign (which rewrites the slots)
+    if (m == 0) {
+        reinterpret_cast<double*>(cnt + M)[0] = lo;
+        reinterpret_cast<double*>(cnt + M)[1] = hi;
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -1346,7 +1351,10 @@ k_slice_assign(const Block* __restrict__ blocks, int b, Slot* __restrict__ slots
     const Block blk = blocks[b];
     const int64_t s = blk.slot0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= blk.slot0 + blk.nslot) return;
-    const double lo = slots[blk.slot0].lo, hi = slots[blk.slot0].hi;  // same for all slots
+    // the root interval as k_slice saw it (slots[slot0] may already be rewritten
+    // by another workgroup of this launch)
+    const double lo = reinterpret_cast<const double*>(cnt + M)[0];
+    const double hi = reinterpret_cast<const double*>(cnt + M)[1];
     const int64_t j = slots[s].idx;
     // first point whose count reaches j
     int64_t a = 0, z = M;

@@ -410,6 +410,7 @@ static Params effective(const mr3_handle_s* h, int precision) {
     p.k_elg = (h->have_user && u.k_elg > 0) ? u.k_elg : d.k_elg;
     p.k_rs = (h->have_user && u.k_rs > 0) ? u.k_rs : d.k_rs;
     p.eps_x = (precision == 32) ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
+    p.root_gap = 1e-3;
     p.max_depth = (h->have_user && u.max_depth > 0) ? u.max_depth : d.max_depth;
     p.rqi_max_iter = (h->have_user && u.rqi_max_iter > 0) ? u.rqi_max_iter : d.rqi_max_iter;
     p.lanes_per_eig = h->have_user ? u.lanes_per_eig : 0;
@@ -850,7 +851,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         for (int64_t b = 0; b < NB; ++b) {
             soff.push_back(tot);
             if (blocks[b].n >= STAGE_MIN_N && blocks[b].nslot > 0 && !is_dq[b])
-                tot += slice_points(blocks[b].nslot);
+                tot += slice_points(blocks[b].nslot) + 4;  // counts, then the interval
         }
         if (tot > 0) {
             HIPCHK(B[B_SLICE].ensure(sizeof(int) * tot));

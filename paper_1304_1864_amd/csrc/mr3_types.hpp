@@ -111,6 +111,7 @@ struct Params {
     double k_elg;
     double k_rs;
     double eps_x;
+    double root_gap;      // mu stays root_gap * spdiam outside the spectrum
     int max_depth;
     int rqi_max_iter;
     int lanes_per_eig;
