@@ -1042,9 +1042,10 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             HIPCHK(SRE.ensure(sizeof(RqiResult) * S));
         }
         // RQI and output of this level's singletons go to the side stream of
-        // the level's parity once the level's cluster work has been issued:
-        // the cluster work is the longer chain, so it gets the device first,
-        // and the singleton work then overlaps the next level.
+        // the level's parity once the level's cluster work up to the child
+        // multisection has been issued: that chain leads the critical path, so
+        // it gets the device first, and the singleton work then overlaps the
+        // bracket check and the next level.
         auto fork_singletons = [&]() -> int {
             if (S == 0) return MR3_OK;
             hipStream_t side = h->side[par];
@@ -1266,6 +1267,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             std::fprintf(stderr, "[mr3]   child bisection: %lld intervals, staged lanes %d, passes max %.0f total %.0f\n",
                          (long long)KC, Lcs.L, wk[6], wk[7]);
         }
+        // the level's singleton work goes to the side stream now: the bracket
+        // check (few waves) then shares the device with it, while the shift
+        // choice, child transform and child multisection before it (which
+        // fill the device and lead the critical path) do not
+        {
+            const int rc = fork_singletons();
+            if (rc) return rc;
+        }
         prof.begin(MR3_STAGE_VERIFY, st);
         if (is_dd) {
             // A child accepted within the strict growth bound k_elg * spdiam
@@ -1296,10 +1305,6 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         }
         prof.end(st);
         HIPCHK(hipGetLastError());
-        {
-            const int rc = fork_singletons();
-            if (rc) return rc;
-        }
         for (int64_t c = 0; c < C; ++c) level_nodes.push_back(jobs[c].child);
     }
     // ---- join the side stream; diagnostics and the ascending-order check ----
