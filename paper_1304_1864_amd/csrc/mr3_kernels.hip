@@ -1799,8 +1799,9 @@ __device__ void prepass_staged(bool top, const double* __restrict__ D,
 // with steps == 0 only help with the loads).  The top lane runs the
 // stationary transform over rows 0..r, the bottom lane the progressive one
 // over rows n-1..r, each storing its part of z in its tile column.  Steps go
-// in groups of four: the pair (a, b) is rescaled after each group, and the
-// storage frame is checked on the group's last value (and on the twist row).
+// in groups of four: the storage frame is checked on the group's last value
+// (and on the twist row), and the pair (a, b) is rescaled after every second
+// group.
 // Between checks a stored value grows by at most four rows' growth of z, so
 // values stay far below overflow (and their squares in ss) for per-row growth
 // up to 2^50.  Book-keeping is by step index (32-bit), turned into rows at
@@ -1820,8 +1821,8 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
     int ev1 = 0, ev2 = 0, ev2e = 0;      // steps of the last two rebasings, last shift
     Y a = neg(tau), b = y_from(1.0, Y());
     if (!top && steps > 0) a = sub(D[n - 1], tau);
-    int eb = 0;    // binary exponent carried by b
-    int eref = 0;  // storage frame exponent
+    // binary exponent carried by b, less the storage frame's exponent
+    int ebr = 0;
     const int nsteps = (int)steps;
     int smax = nsteps;
 #pragma unroll
@@ -1834,12 +1835,12 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
     // the value of z at a step, after the storage check when `check`
     auto zvalue = [&](const SweepStep<Y>& w, int it, bool check) -> double {
         const double pb = prod_hi(w.pq, b);
-        int ex = w.pqe + eb - eref;
+        int ex = w.pqe + ebr;
         if (check) {
             const int ez = dexp(pb) + ex;
             const bool rb = ez > 300;
             const int dlt = rb ? ez : 0;
-            eref += dlt;
+            ebr -= dlt;
             ex -= dlt;
             ss = __builtin_ldexp(ss, -2 * dlt);
             zmax = __builtin_ldexp(zmax, -dlt);
@@ -1849,7 +1850,7 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
         }
         return __builtin_ldexp(pb, ex);
     };
-    auto body = [&](const SweepStep<Y>& w, int it, bool last_of_group) {
+    auto body = [&](const SweepStep<Y>& w, int it, bool last_of_group, bool rescale) {
         const double zv = zvalue(w, it, last_of_group);
         if (store) *zp = zv;
         zp += zstep;
@@ -1860,11 +1861,11 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
         const Y c = mul_add(w.f, b, a);
         a = mul_sub(w.g, a, tau, c);
         b = c;
-        if (last_of_group) {
+        if (rescale) {
             const int em = max(y_exp(a), y_exp(b));
             a = y_ldexp(a, -em);
             b = y_ldexp(b, -em);
-            eb += em;
+            ebr += em;
         }
     };
     for (int it0 = 0; it0 < smax; it0 += SW) {
@@ -1877,14 +1878,14 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
 #pragma unroll
                 for (int v = 0; v < 4; ++v) w[v] = get_sweep_step<Y>(win, cur, side, u + v);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) body(w[v], it0 + u + v, v == 3);
+                for (int v = 0; v < 4; ++v) body(w[v], it0 + u + v, v == 3, v == 3 && (u & 4));
             }
         } else if (it0 < nsteps) {
             // the window that ends with the twist row (step nsteps - 1)
             for (int u = 0; u < SW; ++u) {
                 const int it = it0 + u;
                 if (it + 1 < nsteps) {
-                    body(get_sweep_step<Y>(win, cur, side, u), it, (u & 3) == 3);
+                    body(get_sweep_step<Y>(win, cur, side, u), it, (u & 3) == 3, (u & 7) == 7);
                 } else if (it + 1 == nsteps) {
                     h.zr = zvalue(get_sweep_step<Y>(win, cur, side, u), it, true);
                 }
