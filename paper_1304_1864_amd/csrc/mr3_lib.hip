@@ -794,9 +794,13 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     // ---- a3: bisection of every slot on its root ----
     // the slot list is the identity; staged workgroups of a large block
     // serve its slot range directly, and the per-lane kernel skips those slots
+    // every root is bisected by the staged kernel (a root's rows are shared by
+    // all its eigenvalues; for small roots too this beats per-lane row reads);
+    // only roots of at least STAGE_MIN_N rows are sliced first
+    const int64_t root_stage_n = 1;
     int64_t k_staged = 0;
     for (int64_t b = 0; b < NB; ++b)
-        if (blocks[b].n >= STAGE_MIN_N && !no_stage()) k_staged += blocks[b].nslot;
+        if (blocks[b].n >= root_stage_n && !no_stage()) k_staged += blocks[b].nslot;
     // roots whose whole spectrum is wanted may start from dqds values instead
     // (one lane per root); their brackets are then checked by Sturm counts
     std::vector<int> dq_blocks;
@@ -807,7 +811,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             if (blocks[b].nslot > 0 && blocks[b].nslot == blocks[b].n && blocks[b].n <= MR3_DQDS_MAX_N) {
                 dq_blocks.push_back((int)b);
                 is_dq[b] = 1;
-                dq_staged |= blocks[b].n >= STAGE_MIN_N && !no_stage();
+                dq_staged |= blocks[b].n >= root_stage_n && !no_stage();
             }
     stats.n_dqds_roots = (int64_t)dq_blocks.size();
     BisectShape L = pick_shape(K - k_staged, prm.lanes_per_eig, prm.points_per_lane);
@@ -815,7 +819,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     std::vector<BisWG> rwgs;
     int64_t k_small = 0;
     for (int64_t b = 0; b < NB; ++b) {
-        if (blocks[b].n >= STAGE_MIN_N && !no_stage()) {
+        if (blocks[b].n >= root_stage_n && !no_stage()) {
             const int G = 4 * (64 / Ls.L);
             for (int64_t o = 0; o < blocks[b].nslot; o += G)
                 rwgs.push_back(BisWG{blocks[b].slot0 + o,
@@ -873,7 +877,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     if (k_small > 0)
         launch_bisect(L, B[B_LIST].as<int64_t>(), K, dslots, dnodes, dblocks,
                       B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel, widen_root,
-                      work, no_stage() ? INT64_MAX : STAGE_MIN_N, st);
+                      work, no_stage() ? INT64_MAX : root_stage_n, st);
     prof.end(st);
     HIPCHK(hipGetLastError());
     if (debug_on()) {
