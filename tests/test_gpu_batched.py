@@ -150,3 +150,32 @@ def test_batched_dqds_initial_values(mr3, dtype):
     for i, (p, r) in enumerate(zip(probs, ranges)):
         _check_problem(p[0], p[1], r, Wb[i].double().cpu().numpy(), Zb[i].double().cpu().numpy(),
                        f"dqds problem {i} n={p[0].size} range={r}")
+
+
+def test_batched_large_and_small_roots(mr3):
+    """A batch mixing a root large enough to be sliced (n = 2500) with small
+    roots and a split problem, all pairs and an index window: the same gates
+    against the oracle, and the same eigenvalues as solving each alone."""
+    dl, el, _ = W.prescribed_spectrum(2500, 3)
+    ds, es = W.uniform(90, 4, np.float64)
+    es[29] = 0.0
+    es[59] = 1e-300
+    probs = [(dl, el), W.uniform(300, 5, np.float64), W.toeplitz_121(200, np.float64), (ds, es)]
+    for ranges in ([("all", 0.0, 0.0, 1, p[0].size) for p in probs],
+                   [("index", 0.0, 0.0, 700, 1300), ("all", 0.0, 0.0, 1, 300),
+                    ("index", 0.0, 0.0, 1, 20), ("all", 0.0, 0.0, 1, 90)]):
+        kinds = {"all": 0, "value": 1, "index": 2}
+        desc = [(kinds[r[0]], r[1], r[2], r[3], r[4]) for r in ranges]
+        print(f"batched large+small ranges={[r[0] for r in ranges]}", flush=True)
+        h = mr3.Handle(0)
+        Wb, Zb = mr3.solve_batched([_dev(p[0]) for p in probs], [_dev(p[1]) for p in probs],
+                                   ranges=desc, handle=h)
+        torch.cuda.synchronize()
+        for i, (p, r) in enumerate(zip(probs, ranges)):
+            w = Wb[i].double().cpu().numpy()
+            _check_problem(p[0], p[1], r, w, Zb[i].double().cpu().numpy(),
+                           f"problem {i} n={p[0].size} range={r}")
+            ws, _ = mr3.solve(_dev(p[0]), _dev(p[1]), range=r[0], il=r[3], iu=r[4], vectors=False,
+                              handle=h)
+            tn = M.tnorm(p[0], p[1])
+            assert np.max(np.abs(ws.double().cpu().numpy() - w)) <= 8 * p[0].size * 2.0 ** -53 * tn, i
