@@ -1128,6 +1128,23 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                     }
                     std::fprintf(stderr, "[mr3]   sweep length / n: pair mean %.3f, chunk max (pair-weighted) %.3f, chunks %lld; iterations: mean %.2f, chunk max %.2f\n",
                                  sp / sn, sc / sn, (long long)nchunk, it_mean / S, it_cmax / S);
+                    // pairs by RQI iterations and by the log10 bucket of
+                    // their relative gap
+                    int64_t gh[6][12] = {{0}};
+                    for (int64_t i = 0; i < S; ++i) {
+                        const Slot& q = sl[ls[i]];
+                        double g = 1e300;
+                        if (q.lgap > 0.0) g = std::min(g, q.lgap);
+                        if (q.rgap > 0.0) g = std::min(g, q.rgap);
+                        const double lam = std::max(std::fabs(q.lo), std::fabs(q.hi));
+                        const int b = (int)std::min(11.0, std::max(0.0, -std::log10(std::max(g / lam, 1e-300))));
+                        gh[std::min(std::max(rr[i].iters, 0), 5)][b]++;
+                    }
+                    for (int it = 1; it < 6; ++it) {
+                        std::fprintf(stderr, "[mr3]   iters %d by -log10(relgap):", it);
+                        for (int b = 0; b < 12; ++b) std::fprintf(stderr, " %lld", (long long)gh[it][b]);
+                        std::fprintf(stderr, "\n");
+                    }
                 }
                 if (std::getenv("MR3_DEBUG")[0] == '2') {
                     std::vector<RqiResult> rr;
