@@ -1285,8 +1285,10 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         if (debug_on()) {
             std::vector<double> wk;
             HIPCHK(download(wk, work, 8, st));
-            std::fprintf(stderr, "[mr3]   child bisection: %lld intervals, staged lanes %d, passes max %.0f total %.0f\n",
-                         (long long)KC, Lcs.L, wk[6], wk[7]);
+            int nstrict = 0;
+            for (int64_t c = 0; c < C; ++c) nstrict += done_jobs[c].strict;
+            std::fprintf(stderr, "[mr3]   child bisection: %lld intervals, staged lanes %d, passes max %.0f total %.0f; strict children %d of %lld\n",
+                         (long long)KC, Lcs.L, wk[6], wk[7], nstrict, (long long)C);
         }
         // the level's singleton work goes to the side stream now: the bracket
         // check (few waves) then shares the device with it, while the shift
