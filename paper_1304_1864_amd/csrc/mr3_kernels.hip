@@ -1674,9 +1674,11 @@ __device__ __forceinline__ SweepStep<Y> get_sweep_step(const SweepWin<Y>& win, i
     return w;
 }
 
-// k_rqi runs up to RQI_WAVES independent waves per workgroup, one chunk each
-// (blockDim.x / 64 of them); the waves of a workgroup share the CU's L1, which
-// pays when their chunks sweep the same representation.  A wave synchronises
+// k_rqi<Y, NW> runs NW (1 or RQI_WAVES) independent waves per workgroup, one
+// chunk each; the waves of a workgroup share the CU's L1, which pays when
+// their chunks sweep the same representation.  The LDS windows are sized for
+// NW waves, so one-wave workgroups keep their footprint (and the occupancy
+// it allows) to one wave's windows.  A wave synchronises
 // only with itself: its lanes exchange data through its own LDS windows and
 // its tile.
 constexpr int RQI_WAVES = 4;
@@ -1906,8 +1908,10 @@ __device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __re
     return h;
 }
 
-template <class Y>
-__global__ void __launch_bounds__(64 * RQI_WAVES)
+// (two waves per SIMD: the binary64 instance would otherwise take more than
+// half the register file and run alone on its SIMD)
+template <class Y, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
 k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __restrict__ list,
       const int64_t* __restrict__ tile_off, double* __restrict__ tiles, const Slot* __restrict__ slots, const Node* __restrict__ nodes,
       const Block* __restrict__ blocks, const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld,
@@ -1915,10 +1919,10 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
       const int* __restrict__ Pe, const Y* __restrict__ Q, const int* __restrict__ Qe, Params prm,
       double eps_y, RqiResult* __restrict__ res, unsigned long long* __restrict__ counters,
       double* __restrict__ work) {
-    __shared__ SweepWin<Y> wins[RQI_WAVES];
-    __shared__ TwistWin twins[RQI_WAVES];
-    const int wv = threadIdx.x >> 6;
-    const int64_t cidx = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+    __shared__ SweepWin<Y> wins[NW];
+    __shared__ TwistWin twins[NW];
+    const int wv = NW == 1 ? 0 : (int)(threadIdx.x >> 6);
+    const int64_t cidx = (int64_t)blockIdx.x * NW + wv;
     if (cidx >= nchunks) return;  // the whole wave: no workgroup barrier follows
     SweepWin<Y>& win = wins[wv];
     TwistWin& twin = twins[wv];

@@ -1065,7 +1065,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             // CU holds one such workgroup and its waves get a SIMD each (two
             // workgroups on one CU would share SIMDs while other CUs idle)
             const unsigned pad = wpg > 1 ? 48u * 1024u : 0u;
-            hipLaunchKernelGGL(k_rqi<Y>, dim3((unsigned)((nchunk + wpg - 1) / wpg)), dim3(64 * wpg),
+            auto rqi = wpg > 1 ? k_rqi<Y, RQI_WAVES> : k_rqi<Y, 1>;
+            hipLaunchKernelGGL(rqi, dim3((unsigned)((nchunk + wpg - 1) / wpg)), dim3(64 * wpg),
                                pad, side, SCK.as<ChunkInfo>(), (int64_t)nchunk,
                                SL.as<int64_t>(), STO.as<int64_t>(),
                                STI.rows<double>(32), dslots,
