@@ -1021,6 +1021,55 @@ __device__ __forceinline__ void staged_counts(const double* __restrict__ D,
     }
 }
 
+// Sturm counts at P shifts from rows already resident in LDS (nodes of at
+// most 2 * STAGE_ROWS rows stay there for all passes of a workgroup, which
+// then needs no barrier and no global load per pass).
+template <int P>
+__device__ __forceinline__ void resident_counts(const double2* __restrict__ rows, int n,
+                                                const double (&x)[P], int (&neg)[P], bool on) {
+    double a[P], b[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        a[p] = -x[p];
+        b[p] = 1.0;
+        neg[p] = 0;
+    }
+    if (!on) return;
+    auto step = [&](const double2& r) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double c = __fma_rn(r.x, b[p], a[p]);
+            neg[p] += sign_differs(c, b[p]);
+            a[p] = __fma_rn(-x[p], c, r.y * a[p]);
+            b[p] = c;
+        }
+    };
+    auto rescale = [&]() {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int em = max(dexp(a[p]), dexp(b[p]));
+            a[p] = __builtin_ldexp(a[p], -em);
+            b[p] = __builtin_ldexp(b[p], -em);
+        }
+    };
+    int i = 0;
+    for (; i + 8 <= n; i += 8) {
+        double2 r[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) r[u] = rows[i + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) step(r[u]);
+        rescale();
+#pragma unroll
+        for (int u = 4; u < 8; ++u) step(r[u]);
+        rescale();
+    }
+    for (; i < n; ++i) {
+        step(rows[i]);
+        if ((i & 3) == 3) rescale();
+    }
+}
+
 template <int L, int PTS>
 __global__ void __launch_bounds__(256)
 k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
@@ -1052,6 +1101,13 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
         hi = sl.hi;
     }
     const int gbase = (lg < GW ? lg : 0) * L;  // first lane of this group
+    // small nodes: all rows resident in the (flattened) window
+    const bool resident = n <= 2 * STAGE_ROWS;
+    double2* rows = &win[0][0];
+    if (resident) {
+        for (int i = threadIdx.x; i < (int)n; i += blockDim.x) rows[i] = make_double2(D[i], LL[i]);
+        __syncthreads();
+    }
     // make sure the bracket holds: count(lo) <= j-1 < count(hi) (skipped when
     // the caller has verified every bracket with counts already)
     bool fix = active && check;
@@ -1059,7 +1115,8 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
         if (!__syncthreads_or(fix)) break;
         const double xs2[2] = {lo, hi};
         int c2[2];
-        staged_counts<2>(D, LL, n, xs2, c2, fix && q == 0, win);
+        if (resident) resident_counts<2>(rows, (int)n, xs2, c2, fix && q == 0);
+        else staged_counts<2>(D, LL, n, xs2, c2, fix && q == 0, win);
         const int cl0 = __shfl(c2[0], gbase, 64);
         const int ch0 = __shfl(c2[1], gbase, 64);
         const bool okb = !fix || (cl0 <= j - 1 && ch0 >= j);
@@ -1087,7 +1144,8 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
         int cs[PTS];
 #pragma unroll
         for (int p = 0; p < PTS; ++p) xs[p] = lo + h * (double)(q * PTS + p + 1);
-        staged_counts<PTS>(D, LL, n, xs, cs, busy, win);
+        if (resident) resident_counts<PTS>(rows, (int)n, xs, cs, busy);
+        else staged_counts<PTS>(D, LL, n, xs, cs, busy, win);
         int fp = PTS;
 #pragma unroll
         for (int p = PTS - 1; p >= 0; --p)
