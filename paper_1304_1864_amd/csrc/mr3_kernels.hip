@@ -1441,7 +1441,7 @@ k_slice_assign(const Block* __restrict__ blocks, int b, Slot* __restrict__ slots
 // Sturm count in y at x for threads with on == true; the node's rows stream
 // through an LDS window filled by the 64 threads of the workgroup (all call).
 template <class Y>
-__device__ int staged_count_y(const Y* __restrict__ D, const Y* __restrict__ LL, int64_t n, Y x,
+__device__ __forceinline__ int staged_count_y(const Y* __restrict__ D, const Y* __restrict__ LL, int64_t n, Y x,
                               bool on, Y (*wd)[STAGE_ROWS], Y (*wl)[STAGE_ROWS]) {
     constexpr int PER = STAGE_ROWS / 64;
     const int t = threadIdx.x;
@@ -1761,7 +1761,7 @@ struct TwistWin {
 // p_k) is stored in the lane's tile column; with it, the value the other lane
 // stored for row k is combined into |gamma_k| = |s_k + p_k + tau| and the
 // minimum is tracked.  The tile values are read one block of 8 steps ahead.
-__device__ void prepass_staged(bool top, const double* __restrict__ D,
+__device__ __forceinline__ void prepass_staged(bool top, const double* __restrict__ D,
                                const double* __restrict__ LL, int64_t n, double tau, int64_t s0t,
                                int64_t s0b, int64_t cnt, double& a, double& b, bool combine,
                                double* __restrict__ col, double& gmin, int64_t& rmin,
@@ -1866,8 +1866,11 @@ __device__ void prepass_staged(bool top, const double* __restrict__ D,
 // values stay far below overflow (and their squares in ss) for per-row growth
 // up to 2^50.  Book-keeping is by step index (32-bit), turned into rows at
 // the end.
+// (always inlined, like every function here that takes an LDS window: as a
+// called function it would reach the window through generic pointers, whose
+// accesses also wait for the outstanding global stores)
 template <class Y>
-__device__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __restrict__ LL,
+__device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __restrict__ LL,
                                 const Y* __restrict__ P, const int* __restrict__ Pe,
                                 const Y* __restrict__ Q, const int* __restrict__ Qe, int64_t n,
                                 int64_t r, Y tau, double* __restrict__ col, bool store,
