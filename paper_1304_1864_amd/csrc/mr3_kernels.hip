@@ -2281,7 +2281,8 @@ k_zout(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
             Y lam = add_acc(mk_y<Y>(o.lam_hi, o.lam_lo), mk_y<Y>(nd.sigma_hi, nd.sigma_lo));
             const ProbDesc pd = probs[p];
             if (blockIdx.y == 0)
-                reinterpret_cast<X*>(pd.wout)[sl.out] = (X)__builtin_ldexp(to_double(lam), -sexp);
+                ((__attribute__((address_space(1))) X*)pd.wout)[sl.out] =
+                    (X)__builtin_ldexp(to_double(lam), -sexp);
             s_n[t] = bk.n;
             s_r[t] = o.r;
             s_fT[t] = o.fT;
@@ -2336,7 +2337,10 @@ k_zout(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
                 if (k > s_evB2[cc]) f = (k <= s_evB1[cc]) ? f * s_evB2f[cc] : 0.0;
                 v = buf[ln][cc] * f;
             }
-            s_z[cc][k] = (X)v;
+            // a global store (the pointer came through memory, so the
+            // compiler cannot tell its address space; a generic store would
+            // also be counted with this workgroup's LDS accesses)
+            ((__attribute__((address_space(1))) X*)s_z[cc])[k] = (X)v;
         }
         __syncthreads();
     }
