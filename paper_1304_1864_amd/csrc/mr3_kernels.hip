@@ -1022,8 +1022,9 @@ __device__ __forceinline__ void staged_counts(const double* __restrict__ D,
 }
 
 // Sturm counts at P shifts from rows already resident in LDS (nodes of at
-// most 2 * STAGE_ROWS rows stay there for all passes of a workgroup, which
+// most RESIDENT_ROWS rows stay there for all passes of a workgroup, which
 // then needs no barrier and no global load per pass).
+constexpr int RESIDENT_ROWS = 4 * STAGE_ROWS;
 template <int P>
 __device__ __forceinline__ void resident_counts(const double2* __restrict__ rows, int n,
                                                 const double (&x)[P], int (&neg)[P], bool on) {
@@ -1077,7 +1078,8 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
                 const Block* __restrict__ blocks, const double* __restrict__ d64,
                 const double* __restrict__ lld64, double rtol, double widen,
                 double* __restrict__ work, int check) {
-    __shared__ double2 win[2][STAGE_ROWS];
+    // the staging window, or the whole node when it has at most RESIDENT_ROWS rows
+    __shared__ double2 win[RESIDENT_ROWS / STAGE_ROWS][STAGE_ROWS];
     const BisWG w = wgs[blockIdx.x];
     // groups of L lanes never straddle a wave: 64 / L groups per wave (the
     // last 64 mod L lanes of a wave only help with the loads)
@@ -1102,7 +1104,7 @@ k_bisect_staged(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list,
     }
     const int gbase = (lg < GW ? lg : 0) * L;  // first lane of this group
     // small nodes: all rows resident in the (flattened) window
-    const bool resident = n <= 2 * STAGE_ROWS;
+    const bool resident = n <= RESIDENT_ROWS;
     double2* rows = &win[0][0];
     if (resident) {
         for (int i = threadIdx.x; i < (int)n; i += blockDim.x) rows[i] = make_double2(D[i], LL[i]);
