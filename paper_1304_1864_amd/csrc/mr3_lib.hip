@@ -818,9 +818,15 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     const BisectShape Ls = pick_shape_staged(k_staged, prm.lanes_per_eig);
     std::vector<BisWG> rwgs;
     int64_t k_small = 0;
+    // one-wave workgroups when every root is resident in LDS (each then loads
+    // its node once, and a small node leaves no idle waves behind its few
+    // eigenvalues); four-wave ones share the staged windows of large roots
+    int64_t nmax_root = 0;
+    for (int64_t b = 0; b < NB; ++b) nmax_root = std::max(nmax_root, blocks[b].n);
+    const int rwaves = nmax_root <= RESIDENT_ROWS ? 1 : 4;
     for (int64_t b = 0; b < NB; ++b) {
         if (blocks[b].n >= root_stage_n && !no_stage()) {
-            const int G = 4 * (64 / Ls.L);
+            const int G = rwaves * (64 / Ls.L);
             for (int64_t o = 0; o < blocks[b].nslot; o += G)
                 rwgs.push_back(BisWG{blocks[b].slot0 + o,
                                      (int)std::min<int64_t>(G, blocks[b].nslot - o), (int)b});
@@ -873,7 +879,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     }
     launch_bisect_staged(Ls, B[B_BWG].as<BisWG>(), (int64_t)rwgs.size(), B[B_LIST].as<int64_t>(),
                          dslots, dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
-                         prm.bisect_rel, widen_root, work, dq_staged ? 1 : 0, st);
+                         prm.bisect_rel, widen_root, work, dq_staged ? 1 : 0, st, rwaves);
     if (k_small > 0)
         launch_bisect(L, B[B_LIST].as<int64_t>(), K, dslots, dnodes, dblocks,
                       B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel, widen_root,
