@@ -179,3 +179,28 @@ def test_batched_large_and_small_roots(mr3):
                               handle=h)
             tn = M.tnorm(p[0], p[1])
             assert np.max(np.abs(ws.double().cpu().numpy() - w)) <= 8 * p[0].size * 2.0 ** -53 * tn, i
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_resident_boundary(mr3, dtype):
+    """Roots of 1024 rows stay resident in LDS for the whole multisection (and
+    a batch of such roots uses one-wave workgroups), roots of 1025 rows stream
+    through the staged windows: single solves on both sides of the boundary,
+    and a batch mixing them with a small root (four-wave workgroups, resident
+    and staged nodes side by side), all against the oracle."""
+    probs = [W.uniform(1024, 11, dtype), W.uniform(1025, 12, dtype), W.uniform(33, 13, dtype)]
+    for d, e in probs[:2]:
+        n = d.size
+        print(f"resident boundary single n={n} dtype={np.dtype(dtype).name}", flush=True)
+        Wg, Zg = mr3.solve(_dev(d), _dev(e))
+        torch.cuda.synchronize()
+        _check_problem(d, e, ("all", 0.0, 0.0, 1, n), Wg.double().cpu().numpy(),
+                       Zg.double().cpu().numpy(), f"single n={n}")
+    for group in (probs[:1] + probs[2:], probs):
+        sizes = [p[0].size for p in group]
+        print(f"resident boundary batch sizes={sizes} dtype={np.dtype(dtype).name}", flush=True)
+        Wb, Zb = mr3.solve_batched([_dev(p[0]) for p in group], [_dev(p[1]) for p in group])
+        torch.cuda.synchronize()
+        for i, (d, e) in enumerate(group):
+            _check_problem(d, e, ("all", 0.0, 0.0, 1, d.size), Wb[i].double().cpu().numpy(),
+                           Zb[i].double().cpu().numpy(), f"batch {sizes} problem {i}")
