@@ -1433,6 +1433,65 @@ k_slice_assign(const Block* __restrict__ blocks, int b, Slot* __restrict__ slots
     atomicAdd(&work[0], log2((hi - lo) / fmax(nhi - nlo, 1e-300)) * (double)blk.n);
 }
 
+// Spectrum slicing of small roots (at most RESIDENT_ROWS rows), one workgroup
+// per root: the rows stay in LDS, and M counts at equally spaced points of the
+// root interval are shared by the root's eigenvalues.  M is the power of two
+// from 64 to SLICE_SMALL_MAX that is at least twice the wanted eigenvalues, and
+// each eigenvalue takes the slice its counts prove, as with k_slice and
+// k_slice_assign for large roots (a bracket the counts do not prove keeps the
+// root interval).
+constexpr int SLICE_SMALL_MAX = 2048;
+
+__global__ void __launch_bounds__(256)
+k_slice_small(const int* __restrict__ blist, const Block* __restrict__ blocks,
+              const Node* __restrict__ nodes, Slot* __restrict__ slots,
+              const double* __restrict__ d64, const double* __restrict__ lld64,
+              double* __restrict__ work) {
+    __shared__ double2 rows[RESIDENT_ROWS];
+    __shared__ int cnt[SLICE_SMALL_MAX];
+    __shared__ double s_lo, s_hi;
+    const int b = blist[blockIdx.x];
+    const Block blk = blocks[b];
+    const Node nd = nodes[b];
+    const int n = (int)blk.n;  // at most RESIDENT_ROWS (the host's choice)
+    const int t = threadIdx.x;
+    int M = 64;
+    while (M < 2 * blk.nslot && M < SLICE_SMALL_MAX) M *= 2;
+    // every slot of the root starts from the root interval
+    if (t == 0) {
+        s_lo = slots[blk.slot0].lo;
+        s_hi = slots[blk.slot0].hi;
+    }
+    for (int i = t; i < n; i += blockDim.x) rows[i] = make_double2(d64[nd.rep + i], lld64[nd.rep + i]);
+    __syncthreads();
+    const double lo = s_lo, hi = s_hi;
+    for (int m = t; m < M; m += blockDim.x) {
+        const double xs[1] = {slice_point(lo, hi, m, M)};
+        int c[1];
+        resident_counts<1>(rows, n, xs, c, true);
+        cnt[m] = c[0];
+    }
+    __syncthreads();
+    for (int64_t s = blk.slot0 + t; s < blk.slot0 + blk.nslot; s += blockDim.x) {
+        const int64_t j = slots[s].idx;
+        // first point whose count reaches j
+        int a = 0, z = M;
+        while (a < z) {
+            const int mid = (a + z) >> 1;
+            if (cnt[mid] >= j) z = mid;
+            else a = mid + 1;
+        }
+        const bool ok = (a == M || cnt[a] >= j) && (a == 0 || cnt[a - 1] <= j - 1);
+        if (!ok) continue;  // counts not monotone here: keep the root interval
+        const double nlo = (a == 0) ? lo : slice_point(lo, hi, a - 1, M);
+        const double nhi = (a == M) ? hi : slice_point(lo, hi, a, M);
+        slots[s].lo = nlo;
+        slots[s].hi = nhi;
+        // algorithmic work: the halvings plain bisection needs for this narrowing
+        atomicAdd(&work[0], log2((hi - lo) / fmax(nhi - nlo, 1e-300)) * (double)n);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Verification of binary64-copy intervals in working precision y (Sec. 3.2:
 // results of x-bit eigenvalue computations may be verified or refined in y).

@@ -286,7 +286,7 @@ enum BufId {
     B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BLOCKS, B_SLOTS, B_NODES, B_REPD, B_REPL, B_REPE,
     B_D64, B_L64, B_P, B_PE, B_Q, B_QE, B_LIST, B_LIST2, B_CNT, B_TILEOFF, B_TILES, B_RES,
     B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_M, B_BAD, B_COUNTERS,
-    B_BOFF, B_CREC, B_CHECK, B_NSLOT, B_SLOT0, B_GKEY, B_GVAL, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_DQDS, B_DQB, B_NBUF
+    B_BOFF, B_CREC, B_CHECK, B_NSLOT, B_SLOT0, B_GKEY, B_GVAL, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SLB, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_DQDS, B_DQB, B_NBUF
 };
 
 // singleton work of tree level d runs on the handle's side stream with the
@@ -875,6 +875,24 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                 hipLaunchKernelGGL(k_slice_assign, dim3((unsigned)((blocks[b].nslot + 255) / 256)),
                                    dim3(256), 0, st, dblocks, (int)b, dslots, M, cnt, work);
             }
+        }
+    }
+    // small roots (resident in LDS) with enough wanted eigenvalues, when the
+    // multisection is throughput bound (at most two lanes per eigenvalue, as
+    // in a large batch): sliced by one workgroup each.  With more lanes per
+    // eigenvalue a pass is cheap and the serial slicing workgroup would cost
+    // more than the passes it saves.
+    if (Ls.L <= 2) {
+        std::vector<int> sb;
+        for (int64_t b = 0; b < NB; ++b)
+            if (blocks[b].n >= root_stage_n && blocks[b].n < STAGE_MIN_N && blocks[b].n <= RESIDENT_ROWS &&
+                blocks[b].nslot >= 16 && !is_dq[b] && !no_stage())
+                sb.push_back((int)b);
+        if (!sb.empty()) {
+            HIPCHK(upload(B[B_SLB], sb, st));
+            hipLaunchKernelGGL(k_slice_small, dim3((unsigned)sb.size()), dim3(256), 0, st,
+                               B[B_SLB].as<int>(), dblocks, dnodes, dslots, B[B_D64].rows<double>(),
+                               B[B_L64].rows<double>(), work);
         }
     }
     launch_bisect_staged(Ls, B[B_BWG].as<BisWG>(), (int64_t)rwgs.size(), B[B_LIST].as<int64_t>(),
