@@ -6,25 +6,26 @@
 //               per-block Gerschgorin bounds and requested index ranges
 //   k_root      root representation M_root = T - mu I (definite, mu just
 //               outside the spectrum) and its random relative perturbation
-//               (Alg. 1 lines 1-2; Sec. 3.2 "Random perturbations")
+//               (Alg. 1, root step; Sec. 3.2 "Random perturbations")
 //   k_pq        off-diagonal prefix/suffix products used by the eigenvector
 //               recurrences (shared by every node of a tree)
 //   k_bisect    multisection on Sturm counts of a binary64 copy of a
-//               representation (Alg. 1 lines 3 and 14; Sec. 3.2 "Arithmetic
-//               used to approximate eigenvalues"); k_bisect_staged streams
-//               the rows of large nodes through LDS, k_slice shares counts
-//               among all eigenvalues of a large root
+//               representation (Alg. 1, eigenvalue and refine steps;
+//               Sec. 3.2 "Arithmetic used to approximate eigenvalues");
+//               k_bisect_staged streams the rows of large nodes through LDS
+//               or keeps those of small ones resident, k_slice and
+//               k_slice_small share counts among all eigenvalues of a root
 //   k_dqds      optional initial eigenvalues of whole spectra by the dqds
 //               algorithm, one lane per root (Sec. 4.1), checked and refined
 //               by the multisection afterwards
-//   k_classify  singleton / cluster partition by reldist >= gaptol (Alg. 1
-//               line 7; Sec. 2 "Classification of the eigenvalues")
+//   k_classify  singleton / cluster partition by reldist >= gaptol (Alg. 1,
+//               classification step; Sec. 2 "Classification of the eigenvalues")
 //   k_rqi       Rayleigh quotient iteration with twisted factorizations
-//               (Alg. 1 lines 9-11; Sec. 2 "Rayleigh quotient iteration",
+//               (Alg. 1, singleton step; Sec. 2 "Rayleigh quotient iteration",
 //               Sec. 3.2 stopping criterion)
 //   k_zout      eigenvector normalisation, y -> x rounding, coalesced Z stores
 //   k_child_*   cluster shifts M - tau I by the stationary qd transform in y
-//               with an element-growth acceptance test (Alg. 1 line 13;
+//               with an element-growth acceptance test (Alg. 1, shift step;
 //               Sec. 2 "Shifting the spectrum", "Requirements on the
 //               representations")
 //
@@ -665,7 +666,7 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
         return;
     }
     const double mu = s_mu;
-    // random relative perturbation of the data in y (Alg. 1 line 2), keyed by
+    // random relative perturbation of the data in y (Alg. 1, root step), keyed by
     // the row index within the problem so that results do not depend on how
     // problems are batched
     const Y one = y_from(1.0, Y());

@@ -1270,7 +1270,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         }
         pool_rows += new_rows;
         n_nodes += C;
-        // ---- child bisection (Alg. 1 line 14): the members of every new
+        // ---- child bisection (Alg. 1, refine step): the members of every new
         // cluster, whose slots now belong to the child node ----
         int64_t KC = 0, KCs = 0;
         for (int64_t c = 0; c < C; ++c) {
