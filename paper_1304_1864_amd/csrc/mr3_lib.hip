@@ -1198,6 +1198,16 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             if (rc) return rc;
             break;
         }
+        // With many more chunks than SIMDs (a large batch) the singleton work
+        // is long and throughput bound while the cluster work is short: it
+        // goes first, and the cluster work fills in beside it.  With few
+        // chunks (one large problem) the cluster chain leads the critical path
+        // and goes first (below).
+        const bool fork_first = nchunk > 4096;
+        if (fork_first) {
+            const int rc = fork_singletons();
+            if (rc) return rc;
+        }
         // ---- a5: clusters -> child representations ----
         HIPCHK(B[B_CREC].ensure(sizeof(ClusterRec) * C));
         hipLaunchKernelGGL(k_cluster_recs, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, st,
@@ -1319,7 +1329,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         // check (few waves) then shares the device with it, while the shift
         // choice, child transform and child multisection before it (which
         // fill the device and lead the critical path) do not
-        {
+        if (!fork_first) {
             const int rc = fork_singletons();
             if (rc) return rc;
         }
