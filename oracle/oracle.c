@@ -142,7 +142,7 @@ static void prob_init(prob_t *p, int n, const double *d, const double *e)
         p->d[i] = from_d(d[i]);
         double left = (i > 0) ? fabs(e[i - 1]) : 0.0;
         double right = (i + 1 < n) ? fabs(e[i]) : 0.0;
-        double row = left + fabs(d[i]) + right;
+        double row = left + fabs(d[i]) + ((ORACLE_MUTANT == 7) ? 0.0 : right); /* mutant 7 */
         if (row > tn)
             tn = row;
         double lo = d[i] - (left + right), hi = d[i] + (left + right);
@@ -172,7 +172,11 @@ static void prob_free(prob_t *p)
 }
 
 /* number of eigenvalues of T strictly below sigma (number of negative pivots
- * of T - sigma I); an exactly zero pivot is replaced by -pivmin */
+ * of T - sigma I, Sylvester's law of inertia).  An exactly zero pivot is
+ * replaced by +pivmin: every pivot decreases as sigma grows, so this is the
+ * count at sigma - 0, and an eigenvalue equal to sigma (a zero last pivot) is
+ * not counted.  A zero pivot before the last row gives the same count with
+ * either sign. */
 static int sturm_count(const prob_t *p, xdd sigma)
 {
     int cnt = 0;
@@ -183,7 +187,7 @@ static int sturm_count(const prob_t *p, xdd sigma)
             t = (ORACLE_MUTANT == 1) ? x_sub(t, x_div(p->e[j - 1], q)) /* mutant: e, not e^2 */
                                      : x_sub(t, x_div(p->e2[j - 1], q));
         if (t.hi == 0.0 && t.lo == 0.0)
-            t = from_d(-p->pivmin);
+            t = from_d((ORACLE_MUTANT == 5) ? -p->pivmin : p->pivmin); /* mutant 5: sigma + 0 */
         if (t.hi < 0.0)
             ++cnt;
         q = t;
@@ -254,7 +258,7 @@ static void lu_factor(const prob_t *p, xdd lambda, lu_t *f)
             c = from_d(0.0);
         } else {
             f->swp[j] = 0;
-            if (a.hi == 0.0 && a.lo == 0.0)
+            if (a.hi == 0.0 && a.lo == 0.0 && ORACLE_MUTANT != 6) /* mutant 6: no guard */
                 a = from_d(tiny);
             xdd m = x_div(na, a);
             f->u0[j] = a;
@@ -269,7 +273,7 @@ static void lu_factor(const prob_t *p, xdd lambda, lu_t *f)
             c = from_d(0.0);
         }
     }
-    if (a.hi == 0.0 && a.lo == 0.0)
+    if (a.hi == 0.0 && a.lo == 0.0 && ORACLE_MUTANT != 6)
         a = from_d(tiny);
     f->u0[n - 1] = a;
     f->u1[n - 1] = from_d(0.0);

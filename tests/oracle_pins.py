@@ -303,6 +303,102 @@ def pin_value_range_counts(seed=8, n=120):
     return bad == 0, f"{bad} count mismatches"
 
 
+# --------------------------------------------------------------------------
+# zero-pivot guards and the norm
+# --------------------------------------------------------------------------
+def _strict_count_exact(d, e, sigma):
+    """#{lambda < sigma} in exact rationals: the inertia at sigma - delta for a
+    delta far below every gap of these small integer-valued cases (Sylvester:
+    the count only changes where sigma crosses an eigenvalue)."""
+    for k in (300, 301, 302, 303):
+        c = _exact_negcount(d, e, Fraction(sigma) - Fraction(1, 2 ** k))
+        if c is not None:
+            return c
+    raise AssertionError("no regular point below sigma")
+
+
+def pin_count_zero_pivot():
+    """The Sturm count where a pivot of T - sigma I is exactly zero.  Every
+    pivot decreases as sigma grows, so the count of eigenvalues strictly
+    below sigma is the inertia just below sigma: an eigenvalue equal to sigma
+    (a zero last pivot) is not counted, and a zero pivot before the last row
+    does not change the count.  Cases with exact rational eigenvalues (n = 1;
+    [[2,1],[1,2]] with eigenvalues 1 and 3; 1-2-1 of order 3 at 2; [[0,1],[1,0]]
+    at 0) and random integer matrices at sigma = d_1 (first pivot zero) and at
+    their integer eigenvalues found by exact count."""
+    cases = [
+        ([0.5], [], 0.5, 0),
+        ([2.0, 2.0], [1.0], 1.0, 0),
+        ([2.0, 2.0], [1.0], 3.0, 1),
+        ([2.0, 2.0, 2.0], [1.0, 1.0], 2.0, 1),
+        ([0.0, 0.0], [1.0], 0.0, 1),
+    ]
+    rng = np.random.default_rng(31)
+    for _ in range(40):
+        n = int(rng.integers(2, 7))
+        d = [float(x) for x in rng.integers(-3, 4, n)]
+        e = [float(x) for x in rng.integers(1, 3, n - 1)]
+        cases.append((d, e, d[0], _strict_count_exact(d, e, d[0])))
+        # integer sigmas that are eigenvalues: count jumps across sigma
+        for s in range(-6, 7):
+            lo = _strict_count_exact(d, e, s)
+            hi = _exact_negcount(d, e, Fraction(s) + Fraction(1, 2 ** 300))
+            if hi is not None and hi > lo:
+                cases.append((d, e, float(s), lo))
+    bad = [(d, e, s, want, oracle.count(np.array(d), np.array(e or [0.0]), s))
+           for d, e, s, want in cases
+           if oracle.count(np.array(d), np.array(e or [0.0]), s) != want]
+    return not bad, f"{len(bad)} of {len(cases)} wrong" + (f", first {bad[0]}" if bad else "")
+
+
+def pin_inverse_iteration_zero_pivot():
+    """Inverse iteration at an eigenvalue that is exact, so that elimination
+    of T - lambda I meets an exactly zero pivot: the guarded pivot must still
+    give the exact eigenvector (finite, to FP64 accuracy)."""
+    cases = [
+        ([2.0, 2.0], [1.0], [1.0, 3.0], [[1, -1], [1, 1]]),
+        ([2.0, 2.0, 2.0], [1.0, 1.0], [2.0], [[1, 0, -1]]),
+        ([0.0, 0.0], [1.0], [-1.0, 1.0], [[1, -1], [1, 1]]),
+        ([1.0, 1.0, 1.0], [0.0, 0.0], [1.0, 1.0, 1.0], None),
+    ]
+    worst = 0.0
+    for d, e, lam, vecs in cases:
+        d, e, lam = np.array(d), np.array(e), np.array(lam)
+        Z = oracle.eigvecs(d, e, lam, np.zeros_like(lam))
+        if not np.all(np.isfinite(Z)):
+            return False, f"non-finite vector for d={d.tolist()} lambda={lam.tolist()}"
+        if vecs is None:  # identity: any orthonormal basis of the whole space
+            worst = max(worst, float(np.max(np.abs(Z.T @ Z - np.eye(d.size)))))
+            continue
+        for k, v in enumerate(vecs):
+            worst = max(worst, _sin_angle(np.array(v, dtype=np.float64), Z[:, k]))
+    return worst <= 1e-15, f"worst {worst:.2e}"
+
+
+def pin_tnorm(seed=32):
+    """||T||_1 = max_i (|e_{i-1}| + |d_i| + |e_i|), the norm of the gates,
+    against the exact rational row sums (the oracle adds in FP64: two
+    roundings)."""
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for n in (1, 2, 3, 7, 100):
+        for _ in range(5):
+            d = rng.uniform(-1, 1, n) * 2.0 ** rng.integers(-3, 4, n)
+            e = rng.uniform(-1, 1, max(n - 1, 0)) * 2.0 ** rng.integers(-3, 4, max(n - 1, 0))
+            rows = []
+            for i in range(n):
+                r = abs(Fraction(d[i]))
+                if i > 0:
+                    r += abs(Fraction(e[i - 1]))
+                if i + 1 < n:
+                    r += abs(Fraction(e[i]))
+                rows.append(r)
+            exact = max(rows)
+            got = oracle.tnorm(d, e if n > 1 else np.zeros(1))
+            worst = max(worst, abs(float((Fraction(got) - exact) / exact)))
+    return worst <= 2 * U, f"worst relative error {worst:.2e}"
+
+
 ALL_PINS = [
     pin_dd_ops,
     pin_sturm_inertia,
@@ -316,4 +412,7 @@ ALL_PINS = [
     pin_residual_exact,
     pin_repeated_eigenvalues,
     pin_value_range_counts,
+    pin_count_zero_pivot,
+    pin_inverse_iteration_zero_pivot,
+    pin_tnorm,
 ]

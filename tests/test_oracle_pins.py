@@ -18,6 +18,9 @@ MUTANTS = {
     2: "sign error in the LU elimination of T - lambda I",
     3: "no Gram-Schmidt inside groups",
     4: "double-double product drops a cross term",
+    5: "a zero pivot of the Sturm count counted as negative (count at sigma + 0)",
+    6: "a zero pivot of the elimination left unguarded",
+    7: "||T||_1 without the right off-diagonal of each row",
 }
 
 
