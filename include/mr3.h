@@ -140,6 +140,12 @@ typedef struct {
     double twist_row_steps;
     int64_t n_dqds_roots;     /* roots whose initial eigenvalues came from dqds */
     int64_t dqds_transforms;  /* shifted qd transforms summed over those roots */
+    int64_t n_sliced_roots;   /* roots whose multisection started from spectrum
+                                 slicing (shared Sturm counts at equally spaced
+                                 points) */
+    int n_singleton_first_levels; /* tree levels whose singleton work was
+                                     issued before their cluster work (the
+                                     throughput-bound order of large batches) */
 } mr3_stats;
 
 /* stage indices of mr3_stats.stage_ms */

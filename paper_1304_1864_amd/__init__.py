@@ -75,6 +75,8 @@ class mr3_stats(ctypes.Structure):
         ("twist_row_steps", ctypes.c_double),
         ("n_dqds_roots", ctypes.c_int64),
         ("dqds_transforms", ctypes.c_int64),
+        ("n_sliced_roots", ctypes.c_int64),
+        ("n_singleton_first_levels", ctypes.c_int),
     ]
 
 

@@ -868,6 +868,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             for (int64_t b = 0; b < NB; ++b) {
                 if (blocks[b].n < STAGE_MIN_N || blocks[b].nslot <= 0 || is_dq[b]) continue;
                 const int64_t M = slice_points(blocks[b].nslot);
+                stats.n_sliced_roots++;
                 int* cnt = B[B_SLICE].as<int>() + soff[b];
                 hipLaunchKernelGGL(k_slice, dim3((unsigned)(M / STAGE_ROWS)), dim3(STAGE_ROWS), 0, st,
                                    dblocks, (int)b, dnodes, dslots, B[B_D64].rows<double>(),
@@ -889,6 +890,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                 blocks[b].nslot >= 16 && !is_dq[b] && !no_stage())
                 sb.push_back((int)b);
         if (!sb.empty()) {
+            stats.n_sliced_roots += (int64_t)sb.size();
             HIPCHK(upload(B[B_SLB], sb, st));
             hipLaunchKernelGGL(k_slice_small, dim3((unsigned)sb.size()), dim3(256), 0, st,
                                B[B_SLB].as<int>(), dblocks, dnodes, dslots, B[B_D64].rows<double>(),
@@ -1205,6 +1207,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         // and goes first (below).
         const bool fork_first = nchunk > 4096;
         if (fork_first) {
+            stats.n_singleton_first_levels++;
             const int rc = fork_singletons();
             if (rc) return rc;
         }

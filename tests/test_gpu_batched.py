@@ -111,23 +111,104 @@ def test_batched_values_only_and_empty(mr3):
     assert Wb[0].numel() == 0 and Wb[1].numel() == 100
 
 
-def test_batched_c3_shape_sampled(mr3):
+def _device_gates(mr3, d, e, Wt, Zt, h):
+    """(O, R) of one problem's results on the device: the FP64 MFMA Gram
+    matrix and the residual kernel, with FP32 results promoted exactly."""
+    (off, diag), res = mr3.check(_dev(d.astype(np.float64)), _dev(e.astype(np.float64)),
+                                 Wt.double(), Zt.double(), handle=h)
+    return max(off, diag), res
+
+
+def test_batched_c3_shape(mr3):
     """The full 4096-problem batch (n log-uniform in [32, 1024], N(0,1),
-    FP32): all problems solved in one call; eigenvalue gate on a sample of
-    problems, residual and orthogonality through the device check on FP64
-    copies of the sampled results."""
+    FP32): all problems solved in one call; residual and orthogonality of
+    every problem on the device, eigenvalues of 64 problems against the
+    oracle."""
     probs = W.batch_normal(4096, 32, 1024, seed=0, dtype=np.float32)
     sizes = np.array([p[0].size for p in probs])
     assert int(sizes.sum()) == 1157710
     print("batched C3 shape: 4096 problems, sum n", int(sizes.sum()), flush=True)
-    Wb, Zb = mr3.solve_batched([_dev(p[0]) for p in probs], [_dev(p[1]) for p in probs])
+    h = mr3.Handle(0)
+    Wb, Zb = mr3.solve_batched([_dev(p[0]) for p in probs], [_dev(p[1]) for p in probs], handle=h)
     torch.cuda.synchronize()
+    st = h.stats()
+    print("   sliced roots", st["n_sliced_roots"], "singleton-first levels", st["n_singleton_first_levels"],
+          flush=True)
+    assert st["n_sliced_roots"] > 0 and st["n_singleton_first_levels"] > 0
+    eps = 2.0 ** -24
+    worst_o = worst_r = 0.0
     for i in range(4096):
-        assert Wb[i].numel() == sizes[i]
-    for i in np.linspace(0, 4095, 12).astype(int):
+        n = int(sizes[i])
+        assert Wb[i].numel() == n
+        assert bool((Wb[i][1:] >= Wb[i][:-1]).all())
+        O, R = _device_gates(mr3, probs[i][0], probs[i][1], Wb[i], Zb[i], h)
+        assert O <= 10 * n * eps and R <= 10 * n * eps, (i, O, R)
+        worst_o, worst_r = max(worst_o, O / (n * eps)), max(worst_r, R / (n * eps))
+    print(f"   worst O {worst_o:.3g} n eps, worst R {worst_r:.3g} n eps", flush=True)
+    for i in np.linspace(0, 4095, 64).astype(int):
         p = probs[i]
         _check_problem(p[0], p[1], ("all", 0.0, 0.0, 1, p[0].size), Wb[i].double().cpu().numpy(),
-                       Zb[i].double().cpu().numpy(), f"C3 problem {i}")
+                       None, f"C3 problem {i}")
+
+
+def test_batched_fp64_small_roots_throughput_regime(mr3):
+    """An FP64 (double-double) batch large enough to take the paths of the
+    throughput-bound regime: 1600 roots of 32 to 256 rows hold more than
+    28,800 wanted eigenvalues, so the root multisection runs at two lanes per
+    eigenvalue or fewer and roots with at least 16 wanted eigenvalues are
+    sliced one workgroup each; and more than 4096 node-pure RQI chunks, so
+    each level's singleton work is forked before its cluster work (32 glued
+    Wilkinson problems of 84 rows make sure the first level has clusters).
+    Residual and orthogonality of every problem on the device, eigenvalues and
+    vectors of 24 problems against the oracle."""
+    probs = W.batch_normal(1600, 32, 256, seed=21, dtype=np.float64)
+    probs[::50] = [W.glued_wilkinson(84) for _ in probs[::50]]
+    sizes = np.array([p[0].size for p in probs])
+    print("fp64 small-root batch: sum n", int(sizes.sum()), flush=True)
+    h = mr3.Handle(0)
+    Wb, Zb = mr3.solve_batched([_dev(p[0]) for p in probs], [_dev(p[1]) for p in probs], handle=h)
+    torch.cuda.synchronize()
+    st = h.stats()
+    print("   sliced roots", st["n_sliced_roots"], "singleton-first levels", st["n_singleton_first_levels"],
+          "clusters", st["n_clusters"], flush=True)
+    assert st["n_sliced_roots"] > 0 and st["n_singleton_first_levels"] > 0
+    eps = 2.0 ** -53
+    for i, (d, e) in enumerate(probs):
+        n = d.size
+        O, R = _device_gates(mr3, d, e, Wb[i], Zb[i], h)
+        assert O <= 10 * n * eps and R <= 10 * n * eps, (i, O, R)
+    for i in np.linspace(0, len(probs) - 1, 24).astype(int):
+        d, e = probs[i]
+        _check_problem(d, e, ("all", 0.0, 0.0, 1, d.size), Wb[i].cpu().numpy(), Zb[i].cpu().numpy(),
+                       f"fp64 small-root problem {i}")
+        hi, lo = oracle.eigvals(d, e)
+        Zr = oracle.eigvecs(d, e, hi, lo)
+        tn = M.tnorm(d, e)
+        R = M.residual(d, e, Wb[i].cpu().numpy(), Zb[i].cpu().numpy())
+        ratio, worst = M.subspace_sines(hi + lo, Zr, Zb[i].cpu().numpy(), R, tn, 1e-8 * tn)
+        assert ratio <= 1.0, (i, worst, ratio)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_deterministic(mr3, dtype):
+    """The same call twice gives bitwise-equal eigenvalues and eigenvectors
+    (single solves with clusters, and a batch): the perturbation comes from a
+    counter-based generator keyed by the row, and no kernel accumulates in an
+    order that depends on scheduling."""
+    h = mr3.Handle(0)
+    if dtype == np.float64:
+        d, e = W.glued_wilkinson(336)
+    else:
+        d, e = W.toeplitz_121_noisy(2000, 3, 1e-6, np.float32)
+    W0, Z0 = mr3.solve(_dev(d), _dev(e), handle=h)
+    W1, Z1 = mr3.solve(_dev(d), _dev(e), handle=h)
+    assert torch.equal(W0, W1) and torch.equal(Z0, Z1)
+    probs = W.batch_normal(64, 32, 400, seed=8, dtype=dtype)
+    ds, es = [_dev(p[0]) for p in probs], [_dev(p[1]) for p in probs]
+    Wa, Za = mr3.solve_batched(ds, es, handle=h)
+    Wc, Zc = mr3.solve_batched(ds, es, handle=mr3.Handle(0))
+    for i in range(len(probs)):
+        assert torch.equal(Wa[i], Wc[i]) and torch.equal(Za[i], Zc[i]), i
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
