@@ -29,9 +29,18 @@
  * --------------------------------------
  * Memory.  d, e, W, Z are DEVICE pointers on the handle's device, owned by
  *   the caller; the library keeps no pointer after returning.  m (the count
- *   of eigenpairs found) is a HOST pointer.  Workspace is allocated by the
- *   library from a per-handle pool that grows on demand and is released by
- *   mr3_destroy.
+ *   of eigenpairs found) is a HOST pointer.  Workspace (the O(p n) working
+ *   storage of Sec. 3.3) comes either from the caller, as `work` (device
+ *   memory of work_bytes bytes, any alignment, sized with
+ *   mr3_workspace_bytes), in which case the call allocates no device memory,
+ *   or, with work == NULL, from a per-handle pool that grows on demand and is
+ *   released by mr3_destroy.  A work region smaller than the query's value is
+ *   accepted down to mr3_workspace_min_bytes: the representation tree is
+ *   then walked in groups of clusters whose child representations fit, each
+ *   group's subtree finished before the next (Sec. 3.2, "The representation
+ *   tree"), and the eigenvectors of a level are computed in rounds.  Below
+ *   the minimum the call fails with the position of work_bytes.  The caller
+ *   must not touch the region until the call has returned.
  * Layout.  d has length n, e has length n-1 (e may be NULL when n <= 1).
  *   W receives m eigenvalues in ascending order.  Z (column-major, leading
  *   dimension ldz >= max(1, n)) receives the m unit eigenvectors; Z == NULL
@@ -41,11 +50,14 @@
  *   the half-open interval [vl, vu).  MR3_RANGE_INDEX: indices il..iu,
  *   1-based, inclusive (the index set I of Section 1).
  * Synchronisation.  All device work is issued on `stream` (a hipStream_t, or
- *   NULL for the null stream).  Calls return after the results are complete
- *   (the library synchronises `stream` internally to size its work lists).
+ *   NULL for the null stream).  Calls are synchronous: they return after the
+ *   results are complete, because the host sizes every level's launches from
+ *   counts it reads back (how many singletons and clusters the
+ *   classification found).
  * Errors.  0 on success.  -k: argument k (1-based position in the call) is
  *   invalid (negative n, NULL pointer where one is required, non-finite
- *   input, vl >= vu, il < 1 or iu > n or il > iu + 1, ldz < n, unknown range).
+ *   input, vl >= vu, il < 1 or iu > n or il > iu + 1, ldz < n, unknown range,
+ *   work region too small).
  *   MR3_ERR_NUMERIC (+1): internal numerical failure after every fallback.
  *   MR3_ERR_HIP (+2): a HIP runtime call failed.  MR3_ERR_NO_DEVICE (+3):
  *   no usable GPU.  On a nonzero status the outputs are undefined.
@@ -74,6 +86,13 @@ extern "C" {
 typedef enum { MR3_RANGE_ALL = 0, MR3_RANGE_VALUE = 1, MR3_RANGE_INDEX = 2 } mr3_range;
 
 typedef struct mr3_handle_s *mr3_handle;
+
+/* Per-problem range of a batched call. */
+typedef struct {
+    int range;      /* mr3_range */
+    double vl, vu;  /* MR3_RANGE_VALUE */
+    int64_t il, iu; /* MR3_RANGE_INDEX */
+} mr3_range_desc;
 
 /* Tunable parameters (Section 3.2, Section 4.1).  Zero in a field selects the
  * per-precision default given in brackets [f32 path / f64 path]. */
@@ -173,23 +192,38 @@ int mr3_get_stats(mr3_handle h, mr3_stats *s);
 /* Single problem, FP32 input/output with binary64 internal arithmetic
  * (Section 4.1, single/double).  Arguments (1-based positions, used in the
  * -k error codes): 1 h, 2 n, 3 d, 4 e, 5 range, 6 vl, 7 vu, 8 il, 9 iu,
- * 10 m, 11 W, 12 Z, 13 ldz, 14 stream. */
+ * 10 m, 11 W, 12 Z, 13 ldz, 14 work (device, or NULL for the handle's pool),
+ * 15 work_bytes, 16 stream. */
 int mr3_solve_f32(mr3_handle h, int64_t n, const float *d, const float *e, int range,
                   double vl, double vu, int64_t il, int64_t iu, int64_t *m, float *W,
-                  float *Z, int64_t ldz, void *stream);
+                  float *Z, int64_t ldz, void *work, size_t work_bytes, void *stream);
 
 /* Single problem, FP64 input/output with double-double internal arithmetic
  * (Section 4.1, double/quadruple, with double-double as y).  Same arguments. */
 int mr3_solve_f64(mr3_handle h, int64_t n, const double *d, const double *e, int range,
                   double vl, double vu, int64_t il, int64_t iu, int64_t *m, double *W,
-                  double *Z, int64_t ldz, void *stream);
+                  double *Z, int64_t ldz, void *work, size_t work_bytes, void *stream);
 
-/* Per-problem range of a batched call. */
-typedef struct {
-    int range;      /* mr3_range */
-    double vl, vu;  /* MR3_RANGE_VALUE */
-    int64_t il, iu; /* MR3_RANGE_INDEX */
-} mr3_range_desc;
+/* Device bytes of a work region with which a single solve of order n runs at
+ * full speed (the whole root level's eigenvectors in one round, and up to
+ * 512 clusters per level expanded at once), for any matrix of that order:
+ * range is an mr3_range, k_max bounds the wanted eigenpairs of INDEX and
+ * VALUE ranges (<= 0: unknown, taken as n), precision is 32 or 64.  The size
+ * follows the handle's parameters (depth cap, dqds option); h may be NULL for
+ * the defaults.  Returns 0 for invalid arguments or n = 0 (no work region
+ * needed). */
+size_t mr3_workspace_bytes(mr3_handle h, int64_t n, int range, int64_t k_max, int precision);
+
+/* The smallest work region with which every single solve of order n runs
+ * (arguments as for mr3_workspace_bytes): the roots plus one child
+ * representation per tree level, and eigenvectors in rounds of one chunk of
+ * 32.  Any size between the two is accepted and runs at a speed between. */
+size_t mr3_workspace_min_bytes(mr3_handle h, int64_t n, int range, int64_t k_max, int precision);
+
+/* The same for a batched call of `count` problems with orders n[count] and
+ * ranges[count] (host; NULL = all pairs). */
+size_t mr3_workspace_bytes_batched(mr3_handle h, int64_t count, int precision, const int64_t *n,
+                                   const mr3_range_desc *ranges);
 
 /* Many independent problems of one precision in one pass of the pipeline
  * (every stage is a single launch over all problems).
@@ -198,11 +232,13 @@ typedef struct {
  * 6 d, 7 e (device, float or double per precision), 8 ranges[count] (host,
  * NULL = all), 9 m[count] (host, output), 10 W (device), 11 w_off[count]
  * (host), 12 Z (device, may be NULL), 13 z_off[count] (host), 14 ldz[count]
- * (host), 15 stream. */
+ * (host), 15 work (device, or NULL for the handle's pool), 16 work_bytes,
+ * 17 stream. */
 int mr3_solve_batched(mr3_handle h, int64_t count, int precision, const int64_t *n,
                       const int64_t *de_off, const void *d, const void *e,
                       const mr3_range_desc *ranges, int64_t *m, void *W, const int64_t *w_off,
-                      void *Z, const int64_t *z_off, const int64_t *ldz, void *stream);
+                      void *Z, const int64_t *z_off, const int64_t *ldz, void *work,
+                      size_t work_bytes, void *stream);
 
 /* Verification (not part of a solve; Section 1, eq. (1)).  For the FP64
  * eigenpairs (W, Z) of the FP64 tridiagonal (d, e), all device pointers:

@@ -122,6 +122,7 @@ EXECUTOR_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
 EXPORTS = [
     "mr3_create", "mr3_destroy", "mr3_default_params", "mr3_set_params", "mr3_get_stats",
     "mr3_solve_f32", "mr3_solve_f64", "mr3_solve_batched", "mr3_check_f64", "mr3_version",
+    "mr3_workspace_bytes", "mr3_workspace_min_bytes", "mr3_workspace_bytes_batched",
     "mr3_request_bytes", "mr3_server_create", "mr3_server_create_with_executor",
     "mr3_server_submit", "mr3_server_poll", "mr3_server_wait", "mr3_server_destroy",
 ]
@@ -145,11 +146,16 @@ def load_library(path: str | None = None):
     lib.mr3_default_params.argtypes = [ctypes.POINTER(mr3_params), i32]
     lib.mr3_set_params.argtypes = [vp, ctypes.POINTER(mr3_params)]
     lib.mr3_get_stats.argtypes = [vp, ctypes.POINTER(mr3_stats)]
+    sz = ctypes.c_size_t
     for name in ("mr3_solve_f32", "mr3_solve_f64"):
-        getattr(lib, name).argtypes = [vp, i64, vp, vp, i32, dbl, dbl, i64, i64, pi64, vp, vp, i64, vp]
+        getattr(lib, name).argtypes = [vp, i64, vp, vp, i32, dbl, dbl, i64, i64, pi64, vp, vp, i64,
+                                       vp, sz, vp]
     lib.mr3_solve_batched.argtypes = [vp, i64, i32, pi64, pi64, vp, vp,
                                       ctypes.POINTER(mr3_range_desc), pi64, vp, pi64, vp, pi64,
-                                      pi64, vp]
+                                      pi64, vp, sz, vp]
+    lib.mr3_workspace_bytes.argtypes = [vp, i64, i32, i64, i32]
+    lib.mr3_workspace_min_bytes.argtypes = [vp, i64, i32, i64, i32]
+    lib.mr3_workspace_bytes_batched.argtypes = [vp, i64, i32, pi64, ctypes.POINTER(mr3_range_desc)]
     lib.mr3_check_f64.argtypes = [vp, i64, i64, vp, vp, vp, vp, i64,
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
     lib.mr3_request_bytes.argtypes = [i64, i64, i32]
@@ -164,7 +170,9 @@ def load_library(path: str | None = None):
     for name in EXPORTS:
         if name != "mr3_version":
             getattr(lib, name).restype = ctypes.c_int
-    lib.mr3_request_bytes.restype = ctypes.c_size_t
+    for name in ("mr3_request_bytes", "mr3_workspace_bytes", "mr3_workspace_min_bytes",
+                 "mr3_workspace_bytes_batched"):
+        getattr(lib, name).restype = ctypes.c_size_t
     if path is None:
         _lib = lib
     return lib
@@ -249,20 +257,53 @@ def default_handle() -> Handle:
 # --------------------------------------------------------------------------
 # same-name wrappers of the C entry points
 # --------------------------------------------------------------------------
-def mr3_solve_f32(h, n, d, e, range_, vl, vu, il, iu, W, Z, ldz, stream=None) -> int:
+def _work(work):
+    """(pointer, bytes) of a work region: None, or a device tensor (uint8)."""
+    if work is None:
+        return None, 0
+    return ctypes.c_void_p(work.data_ptr()), work.numel() * work.element_size()
+
+
+def mr3_solve_f32(h, n, d, e, range_, vl, vu, il, iu, W, Z, ldz, stream=None, work=None) -> int:
     m = ctypes.c_int64(0)
+    wp, wb = _work(work)
     rc = load_library().mr3_solve_f32(h.ptr, n, _ptr(d), _ptr(e), range_, vl, vu, il, iu,
-                                      ctypes.byref(m), _ptr(W), _ptr(Z), ldz, _stream_ptr(stream))
+                                      ctypes.byref(m), _ptr(W), _ptr(Z), ldz, wp, wb,
+                                      _stream_ptr(stream))
     _check("mr3_solve_f32", rc)
     return m.value
 
 
-def mr3_solve_f64(h, n, d, e, range_, vl, vu, il, iu, W, Z, ldz, stream=None) -> int:
+def mr3_solve_f64(h, n, d, e, range_, vl, vu, il, iu, W, Z, ldz, stream=None, work=None) -> int:
     m = ctypes.c_int64(0)
+    wp, wb = _work(work)
     rc = load_library().mr3_solve_f64(h.ptr, n, _ptr(d), _ptr(e), range_, vl, vu, il, iu,
-                                      ctypes.byref(m), _ptr(W), _ptr(Z), ldz, _stream_ptr(stream))
+                                      ctypes.byref(m), _ptr(W), _ptr(Z), ldz, wp, wb,
+                                      _stream_ptr(stream))
     _check("mr3_solve_f64", rc)
     return m.value
+
+
+def mr3_workspace_bytes(h, n: int, range_: int, k_max: int, precision: int) -> int:
+    return int(load_library().mr3_workspace_bytes(h.ptr if h is not None else None, n, range_,
+                                                  k_max, precision))
+
+
+def mr3_workspace_min_bytes(h, n: int, range_: int, k_max: int, precision: int) -> int:
+    return int(load_library().mr3_workspace_min_bytes(h.ptr if h is not None else None, n, range_,
+                                                      k_max, precision))
+
+
+def mr3_workspace_bytes_batched(h, precision: int, n, ranges=None) -> int:
+    count = len(n)
+    n_a = (ctypes.c_int64 * count)(*n)
+    rg = None
+    if ranges is not None:
+        rg = (mr3_range_desc * count)()
+        for p, r in enumerate(ranges):
+            rg[p].range, rg[p].vl, rg[p].vu, rg[p].il, rg[p].iu = r
+    return int(load_library().mr3_workspace_bytes_batched(h.ptr if h is not None else None, count,
+                                                          precision, n_a, rg))
 
 
 def mr3_check_f64(h, n, m, d, e, W, Z, ldz, stream=None):
@@ -275,7 +316,7 @@ def mr3_check_f64(h, n, m, d, e, W, Z, ldz, stream=None):
 
 
 def mr3_solve_batched(h, count, precision, n, de_off, d, e, ranges, W, w_off, Z, z_off, ldz,
-                      stream=None):
+                      stream=None, work=None):
     i64a = ctypes.c_int64 * count
     n_a, de_a, wo_a = i64a(*n), i64a(*de_off), i64a(*w_off)
     zo_a = i64a(*z_off) if Z is not None else None
@@ -286,8 +327,9 @@ def mr3_solve_batched(h, count, precision, n, de_off, d, e, ranges, W, w_off, Z,
         rg = (mr3_range_desc * count)()
         for p, r in enumerate(ranges):
             rg[p].range, rg[p].vl, rg[p].vu, rg[p].il, rg[p].iu = r
+    wp, wb = _work(work)
     rc = load_library().mr3_solve_batched(h.ptr, count, precision, n_a, de_a, _ptr(d), _ptr(e), rg,
-                                          m_a, _ptr(W), wo_a, _ptr(Z), zo_a, ld_a,
+                                          m_a, _ptr(W), wo_a, _ptr(Z), zo_a, ld_a, wp, wb,
                                           _stream_ptr(stream))
     _check("mr3_solve_batched", rc)
     return list(m_a)
@@ -301,8 +343,10 @@ _RANGES = {"all": RANGE_ALL, "value": RANGE_VALUE, "index": RANGE_INDEX}
 
 def solve(d: torch.Tensor, e: torch.Tensor, range: str = "all", vl: float = 0.0, vu: float = 0.0,
           il: int = 1, iu: int | None = None, vectors: bool = True, handle: Handle | None = None,
-          stream=None):
-    """Eigenpairs of the tridiagonal (d, e); returns (W[m], Z[n, m] or None)."""
+          stream=None, work: torch.Tensor | None = None):
+    """Eigenpairs of the tridiagonal (d, e); returns (W[m], Z[n, m] or None).
+    work: a device tensor used as the call's work region (None: the handle's
+    pool)."""
     if not d.is_cuda:
         raise ValueError("d and e must be device tensors")
     h = handle or default_handle()
@@ -317,15 +361,15 @@ def solve(d: torch.Tensor, e: torch.Tensor, range: str = "all", vl: float = 0.0,
     fn = mr3_solve_f32 if d.dtype == torch.float32 else mr3_solve_f64
     if d.dtype not in (torch.float32, torch.float64) or e.dtype != d.dtype:
         raise ValueError("d and e must both be float32 or both float64")
-    m = fn(h, n, d.contiguous(), e.contiguous() if n > 1 else None, rk, vl, vu, il, iu, W, Zt,
-           max(n, 1), stream)
+    dc, ec = d.contiguous(), (e.contiguous() if n > 1 else None)
+    m = fn(h, n, dc, ec, rk, vl, vu, il, iu, W, Zt, max(n, 1), stream, work)
     W = W[:m]
     Z = Zt[:m].T if vectors else None
     return W, Z
 
 
 def solve_batched(ds, es, ranges=None, vectors: bool = True, handle: Handle | None = None,
-                  stream=None):
+                  stream=None, work: torch.Tensor | None = None):
     """Solve many problems (lists of 1-D device tensors of one dtype) in one
     pass.  Returns lists of W and Z (Z[p] is n_p x m_p)."""
     h = handle or default_handle()
@@ -358,7 +402,7 @@ def solve_batched(ds, es, ranges=None, vectors: bool = True, handle: Handle | No
     Z = torch.empty(max(acc_z, 1), dtype=dtype, device=dev) if vectors else None
     ldz = [max(k, 1) for k in n]
     ms = mr3_solve_batched(h, count, 32 if dtype == torch.float32 else 64, n, off, dcat, ecat,
-                           ranges, W, w_off, Z, z_off, ldz, stream)
+                           ranges, W, w_off, Z, z_off, ldz, stream, work)
     Ws = [W[w_off[p]:w_off[p] + ms[p]] for p in range(count)]
     Zs = None
     if vectors:

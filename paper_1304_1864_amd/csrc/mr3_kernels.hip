@@ -2036,7 +2036,8 @@ __device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ 
 template <class Y, int NW>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
 k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __restrict__ list,
-      const int64_t* __restrict__ tile_off, double* __restrict__ tiles, const Slot* __restrict__ slots, const Node* __restrict__ nodes,
+      const int64_t* __restrict__ tile_off, int64_t tile_base, double* __restrict__ tiles,
+      const Slot* __restrict__ slots, const Node* __restrict__ nodes,
       const Block* __restrict__ blocks, const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld,
       const double* __restrict__ d64, const double* __restrict__ lld64, const Y* __restrict__ P,
       const int* __restrict__ Pe, const Y* __restrict__ Q, const int* __restrict__ Qe, Params prm,
@@ -2055,7 +2056,9 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
     const ChunkInfo ck = chunks[cidx];
     const int64_t idx = ck.begin + pair;
     const bool active = pair < ck.count;
-    double* tile = tiles + tile_off[cidx] + pair;
+    // tiles of this launch's chunks start at tile_off[0] - tile_base = 0 of
+    // `tiles` (one round of a level whose tiles take several)
+    double* tile = tiles + (tile_off[cidx] - tile_base) + pair;
     // every pair of the chunk belongs to the same node
     const Node nd = nodes[slots[list[ck.begin]].node];
     const Block bk = blocks[nd.block];
@@ -2317,7 +2320,8 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
 template <class X, class Y>
 __global__ void __launch_bounds__(256)
 k_zout(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
-       const int64_t* __restrict__ tile_off, const double* __restrict__ tiles, const Slot* __restrict__ slots,
+       const int64_t* __restrict__ tile_off, int64_t tile_base, const double* __restrict__ tiles,
+       const Slot* __restrict__ slots,
        const Node* __restrict__ nodes, const Block* __restrict__ blocks,
        const ProbInfo* __restrict__ pinfo, const RqiResult* __restrict__ res,
        const ProbDesc* __restrict__ probs, bool any_z) {
@@ -2328,7 +2332,7 @@ k_zout(const ChunkInfo* __restrict__ chunks, const int64_t* __restrict__ list,
     __shared__ int64_t s_rows;
     const int t = threadIdx.x;
     const ChunkInfo ck = chunks[blockIdx.x];
-    const double* tile = tiles + tile_off[blockIdx.x];
+    const double* tile = tiles + (tile_off[blockIdx.x] - tile_base);
     if (t < 32) {
         const int64_t idx = ck.begin + t;
         s_n[t] = 0;

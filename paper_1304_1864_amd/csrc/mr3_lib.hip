@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <vector>
 
@@ -27,23 +28,15 @@ namespace mr3 {
 // --------------------------------------------------------------------------
 // small device utilities used only by the driver
 // --------------------------------------------------------------------------
+// slots of one kind whose node lies in [node_lo, node_hi): the nodes of one
+// level of one group of the tree walk
 struct SelectKind {
     const Slot* slots;
-    const Node* nodes;
     int kind;
-    int depth;
+    int64_t node_lo, node_hi;
     __host__ __device__ bool operator()(const int64_t& s) const {
         const Slot& sl = slots[s];
-        return sl.kind == kind && nodes[sl.node].depth == depth;
-    }
-};
-
-struct SelectDepth {
-    const Slot* slots;
-    const Node* nodes;
-    int depth;
-    __host__ __device__ bool operator()(const int64_t& s) const {
-        return nodes[slots[s].node].depth == depth;
+        return sl.kind == kind && sl.node >= node_lo && sl.node < node_hi;
     }
 };
 
@@ -220,8 +213,10 @@ constexpr int64_t GUARD = 64;
 struct Buf {
     void* p = nullptr;
     size_t cap = 0;
+    bool fixed = false;  // carved from a caller's work region: never grown or freed
     hipError_t ensure(size_t bytes, bool keep = false, hipStream_t st = 0) {
         if (bytes <= cap) return hipSuccess;
+        if (fixed) return hipErrorOutOfMemory;  // the plan covers every request
         size_t nc = std::max(bytes, cap + cap / 2);
         void* q = nullptr;
         hipError_t e = hipMalloc(&q, nc);
@@ -242,9 +237,25 @@ struct Buf {
     // past either end of a representation without bounds arithmetic
     template <class T> T* rows(int64_t width = 1) const { return as<T>() + GUARD * width; }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !fixed) (void)hipFree(p);
         p = nullptr;
         cap = 0;
+        fixed = false;
+    }
+};
+
+// A caller's work region, handed out front to back in 256-byte aligned pieces.
+struct Region {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    bool carve(Buf& b, size_t bytes) {
+        const size_t off = (used + 255) & ~(size_t)255;
+        if (off > cap || bytes > cap - off) return false;
+        b.p = base + off;
+        b.cap = bytes;
+        b.fixed = true;
+        used = off + bytes;
+        return true;
     }
 };
 
@@ -258,6 +269,7 @@ struct Staging {
         size_t cap, used;
     };
     std::vector<Chunk> chunks;
+    bool grow = true;  // false: a solve on a caller's work region allocates nothing
     void* get(size_t bytes) {
         bytes = (bytes + 255) & ~(size_t)255;
         for (auto& c : chunks)
@@ -266,6 +278,7 @@ struct Staging {
                 c.used += bytes;
                 return r;
             }
+        if (!grow) return nullptr;  // the caller copies from pageable memory
         size_t cap = std::max<size_t>(bytes, (size_t)4 << 20);
         if (!chunks.empty()) cap = std::max(cap, 2 * chunks.back().cap);
         void* p = nullptr;
@@ -297,6 +310,164 @@ constexpr int B_SIDE_TOFF[2] = {B_TILEOFF, B_TILEOFF1};
 constexpr int B_SIDE_TILES[2] = {B_TILES, B_TILES1};
 constexpr int B_SIDE_RES[2] = {B_RES, B_RES1};
 constexpr int B_SIDE_CHUNK[2] = {B_CHUNK0, B_CHUNK1};
+
+// nodes of at least this many rows are bisected by the LDS-staged kernel with
+// node-pure workgroups; shorter ones (which stay in cache) by the per-lane one
+constexpr int64_t STAGE_MIN_N = 2048;
+
+// counters: 8 x u64 (RQI iterations, fallbacks, failures), 8 x double
+// (algorithmic row steps), 8 x int (status)
+constexpr size_t COUNTER_BYTES = sizeof(unsigned long long) * 8 + sizeof(double) * 8 + sizeof(int) * 8;
+
+// status of a solve on a caller's work region that is too small (mapped to
+// the position of the work_bytes argument by the entry points)
+constexpr int ERR_WORK_SMALL = -100000;
+
+// --------------------------------------------------------------------------
+// Workspace plan: the size of every buffer of one call, from the call's
+// shape.  A solve on a caller's work region carves all of them up front, so
+// it never allocates; the handle's pool grows the same buffers on demand.
+// --------------------------------------------------------------------------
+struct Shape {
+    int64_t count = 0;     // problems
+    int64_t R = 0;         // rows of all problems
+    int64_t NB = 0;        // irreducible blocks
+    int64_t K = 0;         // slots: wanted eigenvalues plus helpers
+    int64_t nmax = 0;      // rows of the largest block with wanted eigenvalues
+    int max_depth = 6;
+    bool dd = false;       // y = double-double
+    bool dqds = false;
+    size_t xsize = 8;
+    int64_t rep_rows = 0;  // representation stack: root rows plus child rows
+    int64_t tile_rows = 0; // eigenvector tile rows per side-stream parity
+};
+
+// hipcub temporary storage of the scans, selects and radix sorts over at most
+// c items: the sort's key and value copies, plus a fixed allowance for
+// histograms and look-back state
+static size_t cub_bound(int64_t c) { return (size_t)40 * (size_t)(c + 1) + ((size_t)4 << 20); }
+
+// at most NB roots plus, per level below the depth cap, disjoint clusters of
+// at least two slots each
+static int64_t node_bound(const Shape& s) {
+    return s.NB + (int64_t)std::max(1, s.max_depth) * s.K / 2 + 1;
+}
+
+// buffers sized before the blocks are known (from count and R only)
+static const int PREP_BUFS[] = {B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BOFF,
+                                B_BLOCKS, B_NSLOT, B_SLOT0, B_CUBTMP};
+static bool is_prep_buf(int b) {
+    for (int q : PREP_BUFS)
+        if (q == b) return true;
+    return false;
+}
+
+static void prep_sizes(const Shape& s, size_t* sz) {
+    const int64_t G2 = 2 * GUARD;
+    sz[B_PROBS] = sizeof(ProbDesc) * std::max<int64_t>(s.count, 1);
+    sz[B_PINFO] = sizeof(ProbInfo) * std::max<int64_t>(s.count, 1);
+    sz[B_TD] = sz[B_TE] = sizeof(double) * (s.R + G2);
+    sz[B_BINFO] = sizeof(BlockInfo) * std::max<int64_t>(s.R, 1);
+    sz[B_BOFF] = sizeof(int64_t) * (s.count + 1);
+    sz[B_BLOCKS] = sizeof(Block) * std::max<int64_t>(s.R, 1);  // at most one block per row
+    sz[B_NSLOT] = sz[B_SLOT0] = sizeof(int64_t) * (s.R + 1);
+    sz[B_CUBTMP] = cub_bound(s.R + 1) + 256;  // every scan, select and sort covers <= R + 1 items
+}
+
+static void solve_sizes(const Shape& s, size_t* sz) {
+    const int64_t G2 = 2 * GUARD, K = std::max<int64_t>(s.K, 1);
+    const int64_t NB = std::max<int64_t>(s.NB, 1), KN = std::max(K, NB);
+    const size_t ys = s.dd ? 16 : 8;
+    const int64_t tmp_rows = std::max<int64_t>(s.rep_rows - s.R, 1);
+    sz[B_SLOTS] = sizeof(Slot) * K;
+    sz[B_NODES] = sizeof(Node) * node_bound(s);
+    sz[B_REPD] = sz[B_REPL] = ys * (s.rep_rows + G2);
+    sz[B_D64] = sz[B_L64] = sizeof(double) * (s.rep_rows + G2);
+    sz[B_REPE] = ys * std::max<int64_t>(s.R, 1);
+    sz[B_P] = sz[B_Q] = ys * (s.R + G2);
+    sz[B_PE] = sz[B_QE] = sizeof(int) * (s.R + G2);
+    sz[B_LIST] = sizeof(int64_t) * KN;  // level nodes, identity and bisection lists
+    sz[B_LIST2] = sizeof(int64_t) * K;
+    sz[B_CNT] = sizeof(int64_t) * 4;
+    sz[B_FLAGS] = sizeof(int64_t) * (K + 1);  // flags per slot, then tile rows per chunk
+    sz[B_COUNTERS] = COUNTER_BYTES;
+    sz[B_BWG] = sizeof(BisWG) * KN;
+    // slice counts: at most max(1024, 6k) + 4 per root of >= STAGE_MIN_N rows
+    sz[B_SLICE] = sizeof(int) * (6 * K + 1028 * (s.R / STAGE_MIN_N + 1));
+    sz[B_SLB] = sz[B_DQB] = sizeof(int) * NB;
+    sz[B_DQDS] = s.dqds ? sizeof(double) * 6 * s.R : 0;
+    for (int q = 0; q < 2; ++q) {
+        sz[B_SIDE_LIST[q]] = sizeof(int64_t) * K;
+        sz[B_SIDE_TOFF[q]] = sizeof(int64_t) * (K + 1);
+        sz[B_SIDE_TILES[q]] = sizeof(double) * (std::max<int64_t>(s.tile_rows, 1) + 2 * 32 * GUARD);
+        sz[B_SIDE_RES[q]] = sizeof(RqiResult) * K;
+        sz[B_SIDE_CHUNK[q]] = sizeof(ChunkInfo) * K;
+    }
+    sz[B_GKEY] = sizeof(unsigned long long) * 2 * K;
+    sz[B_GVAL] = sz[B_SEG] = sz[B_CMARK] = sz[B_CID] = sizeof(int64_t) * K;
+    sz[B_CREC] = sizeof(ClusterRec) * K;
+    sz[B_JOBS] = sizeof(ChildJob) * K;
+    sz[B_TMPC] = ys * tmp_rows;
+    sz[B_TMPE] = sizeof(int) * tmp_rows;
+    sz[B_VLIST] = sizeof(int64_t) * K;
+    sz[B_VWG] = sizeof(BisWG) * K;
+    sz[B_M] = sizeof(int64_t) * std::max<int64_t>(s.count, 1);
+    sz[B_BAD] = sizeof(int) * std::max<int64_t>(s.count, 1);
+    sz[B_CHECK] = s.xsize * std::max<int64_t>(s.nmax, 1);
+}
+
+// bytes the buffers of one phase take in a region, with their alignment
+static size_t phase_bytes(const size_t* sz, bool prep) {
+    size_t t = 256;
+    for (int b = 0; b < B_NBUF; ++b)
+        if (is_prep_buf(b) == prep) t += (sz[b] + 255) & ~(size_t)255;
+    return t;
+}
+
+// The least the tree walk can run with: the roots plus one child of the
+// largest block per level, and the tiles of one chunk of 32 eigenvectors.
+static int64_t min_rep_rows(const Shape& s) { return s.R + (int64_t)std::max(1, s.max_depth) * s.nmax; }
+static int64_t min_tile_rows(const Shape& s) { return 32 * std::max<int64_t>(s.nmax, 1); }
+// Full speed: up to 512 clusters of the largest block on each of two levels
+// at once, and the tiles of a whole level in one round (tile_full: the sum
+// over blocks of n (wanted + 32)).
+static int64_t full_rep_rows(const Shape& s) {
+    return std::max(min_rep_rows(s), s.R + 2 * std::min<int64_t>(s.K / 2, 512) * s.nmax);
+}
+
+// Representation-stack and tile capacity for a region of `avail` bytes after
+// the preprocessing buffers: the minimum first, then both towards full speed
+// in proportion, and any rest to the stack.  False if the minimum does not fit.
+static bool plan_region(Shape& s, size_t avail, int64_t tile_full) {
+    s.rep_rows = min_rep_rows(s);
+    s.tile_rows = min_tile_rows(s);
+    size_t sz[B_NBUF] = {0};
+    solve_sizes(s, sz);
+    const size_t base = phase_bytes(sz, false) + 256 * (size_t)B_NBUF;  // rounding slack
+    if (base > avail) return false;
+    size_t left = avail - base;
+    const size_t ys = s.dd ? 16 : 8;
+    const size_t per_tile = 2 * sizeof(double);  // both side-stream parities
+    const size_t per_rep = 3 * ys + 2 * sizeof(double) + sizeof(int);  // d, lld, scratch; copies
+    const double want_t = (double)std::max<int64_t>(tile_full - s.tile_rows, 0) * per_tile;
+    const double want_r = (double)(full_rep_rows(s) - s.rep_rows) * per_rep;
+    const double f = (want_t + want_r <= (double)left) ? 1.0 : (double)left / (want_t + want_r);
+    const int64_t t = (int64_t)(f * want_t / per_tile);
+    s.tile_rows += t;
+    left -= (size_t)t * per_tile;
+    s.rep_rows += (int64_t)(left / per_rep);
+    return true;
+}
+
+// Bytes a call of this shape needs at full speed (the workspace query).
+static size_t full_bytes(Shape s, int64_t tile_full) {
+    size_t sz[B_NBUF] = {0};
+    prep_sizes(s, sz);
+    s.rep_rows = full_rep_rows(s);
+    s.tile_rows = std::max(min_tile_rows(s), tile_full);
+    solve_sizes(s, sz);
+    return 256 + phase_bytes(sz, true) + phase_bytes(sz, false) + 256 * (size_t)B_NBUF;
+}
 
 }  // namespace mr3
 
@@ -518,10 +689,6 @@ static bool no_stage() {
     return v;
 }
 
-// nodes of at least this many rows are bisected by the LDS-staged kernel with
-// node-pure workgroups; shorter ones (which stay in cache) by the per-lane one
-constexpr int64_t STAGE_MIN_N = 2048;
-
 // slot list for a bisection launch: the slots of staged nodes first (with one
 // workgroup per G of them), then the rest
 struct BisectPlan {
@@ -605,21 +772,27 @@ static BisectShape pick_shape_staged(int64_t count, int user_lanes) {
 template <class X, class Y>
 static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const X* const* d_p,
                       const X* const* e_p, const mr3_range_desc* ranges, int64_t* m_out,
-                      X* const* W_p, X* const* Z_p, const int64_t* ldz_h, hipStream_t st) {
+                      X* const* W_p, X* const* Z_p, const int64_t* ldz_h, hipStream_t st,
+                      void* work_region, size_t work_bytes) {
     const int precision = sizeof(X) == 4 ? 32 : 64;
     const Params prm = effective(h, precision);
     const double t_start = now_ms();
     const bool is_dd = sizeof(Y) == 16;
-    Buf* B = h->buf;
+    // a caller's work region: every buffer is carved from it up front and
+    // nothing is allocated; otherwise the handle's pool grows on demand
+    const bool fixed = work_region != nullptr;
+    Buf Bf[B_NBUF];
+    Buf* B = fixed ? Bf : h->buf;
+    Region reg;
+    if (fixed) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(work_region);
+        const uintptr_t al = (a + 255) & ~(uintptr_t)255;
+        reg.base = reinterpret_cast<char*>(al);
+        reg.cap = work_bytes > (size_t)(al - a) ? work_bytes - (size_t)(al - a) : 0;
+    }
+    int64_t rep_cap = INT64_MAX, tile_cap = INT64_MAX;  // bounded on a work region
     mr3_stats stats{};
     HIPCHK(hipSetDevice(h->device));
-    if (!h->side[0]) {
-        HIPCHK(hipStreamCreateWithFlags(&h->side[0], hipStreamNonBlocking));
-        HIPCHK(hipStreamCreateWithFlags(&h->side[1], hipStreamNonBlocking));
-        HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&h->ev_side[0], hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&h->ev_side[1], hipEventDisableTiming));
-    }
     // work a failed earlier call left on the side stream must end before
     // buffers are reused
     if (h->side_pending[0] || h->side_pending[1]) {
@@ -632,6 +805,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     if (!h->clean_exit) HIPCHK(hipDeviceSynchronize());
     h->clean_exit = false;
     h->stage.reset();
+    h->stage.grow = !fixed;
     struct StageScope {
         StageScope(Staging* s) { g_stage = s; }
         ~StageScope() { g_stage = nullptr; }
@@ -676,6 +850,15 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         m_out[p] = 0;
     }
     if (R == 0) { h->stats = stats; h->clean_exit = true; return MR3_OK; }
+    if (fixed) {
+        Shape sh;
+        sh.count = count;
+        sh.R = R;
+        size_t sz[B_NBUF] = {0};
+        prep_sizes(sh, sz);
+        for (int b : PREP_BUFS)
+            if (!reg.carve(B[b], sz[b])) { h->clean_exit = true; return ERR_WORK_SMALL; }
+    }
     HIPCHK(upload(B[B_PROBS], probs, st));
     HIPCHK(B[B_PINFO].ensure(sizeof(ProbInfo) * count));
     HIPCHK(B[B_TD].ensure(sizeof(double) * (R + 2 * GUARD)));
@@ -739,14 +922,45 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             return MR3_ERR_GAPTOL;
         }
     }
+    if (fixed) {
+        // the rest of the plan, now that blocks and slots are known
+        Shape sh;
+        sh.count = count;
+        sh.R = R;
+        sh.NB = NB;
+        sh.K = K;
+        sh.max_depth = prm.max_depth;
+        sh.dd = is_dd;
+        sh.dqds = prm.initial == MR3_INITIAL_DQDS;
+        sh.xsize = sizeof(X);
+        int64_t tile_full = 0;
+        for (const Block& bk : blocks)
+            if (bk.nslot > 0) {
+                sh.nmax = std::max(sh.nmax, bk.n);
+                tile_full += bk.n * (bk.nslot + 32);
+            }
+        if (!plan_region(sh, reg.cap - std::min(reg.cap, reg.used), tile_full)) {
+            h->clean_exit = true;
+            return ERR_WORK_SMALL;
+        }
+        size_t sz[B_NBUF] = {0};
+        solve_sizes(sh, sz);
+        for (int b = 0; b < B_NBUF; ++b)
+            if (!is_prep_buf(b) && !reg.carve(B[b], sz[b])) { h->clean_exit = true; return ERR_WORK_SMALL; }
+        rep_cap = sh.rep_rows;
+        tile_cap = sh.tile_rows;
+        if (debug_on())
+            std::fprintf(stderr, "[mr3] work region: %zu of %zu bytes, representation rows %lld (roots %lld), tile rows %lld of %lld\n",
+                         reg.used, reg.cap, (long long)rep_cap, (long long)R, (long long)tile_cap, (long long)tile_full);
+    }
     HIPCHK(B[B_SLOTS].ensure(sizeof(Slot) * (size_t)K));
     hipLaunchKernelGGL(k_slots, dim3((unsigned)NB), dim3(256), 0, st, B[B_BLOCKS].as<Block>(),
                        B[B_PINFO].as<ProbInfo>(), B[B_SLOTS].as<Slot>());
     // nodes: roots first (node index == block index), children appended
-    int64_t node_cap = NB + K;  // each cluster head creates at most one node per level
+    int64_t node_cap = NB + K;  // grows with the tree on the handle's pool
+    if (fixed) node_cap = (int64_t)(B[B_NODES].cap / sizeof(Node));
     HIPCHK(B[B_NODES].ensure(sizeof(Node) * (size_t)std::max<int64_t>(node_cap, 1)));
-    // representation pool: root rows first
-    int64_t pool_rows = R;
+    // representation stack: root rows first
     HIPCHK(B[B_REPD].ensure(sizeof(Y) * (R + 2 * GUARD)));
     HIPCHK(B[B_REPL].ensure(sizeof(Y) * (R + 2 * GUARD)));
     HIPCHK(B[B_D64].ensure(sizeof(double) * (R + 2 * GUARD)));
@@ -756,11 +970,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(B[B_Q].ensure(sizeof(Y) * (R + 2 * GUARD)));
     HIPCHK(B[B_PE].ensure(sizeof(int) * (R + 2 * GUARD)));
     HIPCHK(B[B_QE].ensure(sizeof(int) * (R + 2 * GUARD)));
-    // counters: 8 x u64 (RQI iterations, fallbacks, failures), 8 x double
-    // (algorithmic row steps), 8 x int (status)
-    const size_t cnt_bytes = sizeof(unsigned long long) * 8 + sizeof(double) * 8 + sizeof(int) * 8;
-    HIPCHK(B[B_COUNTERS].ensure(cnt_bytes));
-    HIPCHK(hipMemsetAsync(B[B_COUNTERS].p, 0, cnt_bytes, st));
+    HIPCHK(B[B_COUNTERS].ensure(COUNTER_BYTES));
+    HIPCHK(hipMemsetAsync(B[B_COUNTERS].p, 0, COUNTER_BYTES, st));
     unsigned long long* counters = B[B_COUNTERS].as<unsigned long long>();
     double* work = reinterpret_cast<double*>(counters + 8);
     int* status = reinterpret_cast<int*>(work + 8);
@@ -953,17 +1164,28 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     int64_t nmax_blocks = 1;
     for (const Block& bk : blocks) nmax_blocks = std::max(nmax_blocks, bk.n);
     const int zsplit = (int)std::min<int64_t>(16, std::max<int64_t>(1, nmax_blocks / 2048));
-    // ---- levels of the representation trees ----
-    std::vector<int64_t> level_nodes((size_t)NB);
-    std::iota(level_nodes.begin(), level_nodes.end(), 0);
+    // ---- the representation trees ----
+    // visit(lo, hi, depth) runs one level for the nodes [lo, hi): classify;
+    // RQI and output of the singletons on a side stream; child representations
+    // and child bisection of the clusters; then the children, recursively.
+    // With the handle's pool every cluster of a level is expanded at once (one
+    // group: the walk is breadth first).  On a caller's work region the
+    // clusters are expanded in groups whose child rows fit the representation
+    // stack, and each group's subtree is finished before the next group reuses
+    // its rows (Sec. 3.2 / The representation tree: depth first bounds the
+    // memory).
     int64_t n_nodes = NB;
+    int64_t rep_top = R;  // first free row of the representation stack
+    bool rows_recycled = false;
     HIPCHK(B[B_FLAGS].ensure(sizeof(int) * K));
     HIPCHK(B[B_LIST2].ensure(sizeof(int64_t) * K));
     HIPCHK(B[B_CNT].ensure(sizeof(int64_t) * 4));
     int64_t* dcnt = B[B_CNT].as<int64_t>();
     hipcub::CountingInputIterator<int64_t> iter(0);
-    for (int depth = 0; !level_nodes.empty(); ++depth) {
+    std::function<int(int64_t, int64_t, int)> visit = [&](int64_t node_lo, int64_t node_hi, int depth) -> int {
         stats.d_max = std::max(stats.d_max, depth);
+        std::vector<int64_t> level_nodes((size_t)(node_hi - node_lo));
+        std::iota(level_nodes.begin(), level_nodes.end(), node_lo);
         HIPCHK(upload(B[B_LIST], level_nodes, st));
         const int force_single = depth >= prm.max_depth;
         prof.begin(MR3_STAGE_CLASSIFY, st);
@@ -972,9 +1194,9 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                            B[B_FLAGS].as<int>(), prm.gaptol, prm.gaptol_abs, force_single);
         HIPCHK(hipGetLastError());
         // compact the singletons (into the side list of this level's parity)
-        // and the cluster heads of this level
+        // and the cluster heads of these nodes
         const int par = depth & 1;
-        if (h->side_pending[par]) {  // level depth-2 still owns these buffers
+        if (h->side_pending[par]) {  // an earlier level still owns these buffers
             HIPCHK(hipEventSynchronize(h->ev_side[par]));
             h->side_pending[par] = false;
         }
@@ -985,8 +1207,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         Buf& SCK = B[B_SIDE_CHUNK[par]];
         HIPCHK(SL.ensure(sizeof(int64_t) * K));
         size_t tmp_bytes = 0, tb2 = 0;
-        SelectKind sel_s{dslots, dnodes, KIND_SINGLETON, depth};
-        SelectKind sel_c{dslots, dnodes, KIND_CLUSTER_HEAD, depth};
+        SelectKind sel_s{dslots, KIND_SINGLETON, node_lo, node_hi};
+        SelectKind sel_c{dslots, KIND_CLUSTER_HEAD, node_lo, node_hi};
         HIPCHK(hipcub::DeviceSelect::If(nullptr, tmp_bytes, iter, SL.as<int64_t>(), dcnt, K,
                                         sel_s, st));
         HIPCHK(hipcub::DeviceSelect::If(nullptr, tb2, iter, B[B_LIST2].as<int64_t>(), dcnt + 1, K,
@@ -1027,6 +1249,9 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             HIPCHK(hipMemcpyAsync(SL.p, v1, sizeof(int64_t) * S, hipMemcpyDeviceToDevice, st));
         }
         int64_t nchunk = 0;
+        // host copy of the tile offsets when the tiles of the level take
+        // several rounds (work region smaller than the level's tiles)
+        std::vector<int64_t> toff_h;
         if (S > 0) {
             // node-pure chunks (at most S of them)
             HIPCHK(B[B_SEG].ensure(sizeof(int64_t) * S));
@@ -1040,14 +1265,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             {
                 size_t tb = 0;
                 HIPCHK(hipcub::DeviceScan::InclusiveScan(nullptr, tb, seg, seg, MaxOp(), S, st));
-                size_t tb2 = 0;
-                HIPCHK(hipcub::DeviceScan::InclusiveSum(nullptr, tb2, cmark, cid, S, st));
-                HIPCHK(B[B_CUBTMP].ensure(std::max(tb, tb2) + 256));
+                size_t tb3 = 0;
+                HIPCHK(hipcub::DeviceScan::InclusiveSum(nullptr, tb3, cmark, cid, S, st));
+                HIPCHK(B[B_CUBTMP].ensure(std::max(tb, tb3) + 256));
                 tb = B[B_CUBTMP].cap;
                 HIPCHK(hipcub::DeviceScan::InclusiveScan(B[B_CUBTMP].p, tb, seg, seg, MaxOp(), S, st));
                 hipLaunchKernelGGL(k_chunk_marks, dim3(gS), dim3(256), 0, st, seg, S, cmark);
-                tb2 = B[B_CUBTMP].cap;
-                HIPCHK(hipcub::DeviceScan::InclusiveSum(B[B_CUBTMP].p, tb2, cmark, cid, S, st));
+                tb3 = B[B_CUBTMP].cap;
+                HIPCHK(hipcub::DeviceScan::InclusiveSum(B[B_CUBTMP].p, tb3, cmark, cid, S, st));
             }
             std::vector<int64_t> nck;
             HIPCHK(download(nck, cid + S - 1, 1, st));
@@ -1068,7 +1293,12 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                                                     nchunk + 1, st));
             std::vector<int64_t> tot;
             HIPCHK(download(tot, STO.as<int64_t>() + nchunk, 1, st));
-            HIPCHK(STI.ensure(sizeof(double) * (std::max<int64_t>(tot[0], 1) + 2 * 32 * GUARD)));
+            int64_t tile_need = tot[0];
+            if (tile_need > tile_cap) {
+                HIPCHK(download(toff_h, STO.p, (size_t)(nchunk + 1), st));
+                tile_need = tile_cap;
+            }
+            HIPCHK(STI.ensure(sizeof(double) * (std::max<int64_t>(tile_need, 1) + 2 * 32 * GUARD)));
             HIPCHK(SRE.ensure(sizeof(RqiResult) * S));
         }
         // RQI and output of this level's singletons go to the side stream of
@@ -1081,7 +1311,6 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             hipStream_t side = h->side[par];
             HIPCHK(hipEventRecord(h->ev_fork, st));
             HIPCHK(hipStreamWaitEvent(side, h->ev_fork, 0));
-            prof.begin(MR3_STAGE_RQI, side);
             // several waves per workgroup when few chunks sweep large nodes
             // (they share rows through L1); one when many small problems'
             // chunks of unequal lengths would hold each other's CU slots
@@ -1092,25 +1321,39 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             // workgroups on one CU would share SIMDs while other CUs idle)
             const unsigned pad = wpg > 1 ? 48u * 1024u : 0u;
             auto rqi = wpg > 1 ? k_rqi<Y, RQI_WAVES> : k_rqi<Y, 1>;
-            hipLaunchKernelGGL(rqi, dim3((unsigned)((nchunk + wpg - 1) / wpg)), dim3(64 * wpg),
-                               pad, side, SCK.as<ChunkInfo>(), (int64_t)nchunk,
-                               SL.as<int64_t>(), STO.as<int64_t>(),
-                               STI.rows<double>(32), dslots,
-                               dnodes, dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
-                               B[B_D64].rows<double>(), B[B_L64].rows<double>(), B[B_P].rows<Y>(),
-                               B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>(), prm,
-                               (double)YEps<Y>::v, SRE.as<RqiResult>(), counters, work);
-            prof.end(side);
-            prof.begin(MR3_STAGE_ZOUT, side);
-            // rows of a chunk are split over zsplit workgroups (blocks of 64
-            // rows), so that large nodes' output is not one serial loop
-            hipLaunchKernelGGL((k_zout<X, Y>), dim3((unsigned)nchunk, (unsigned)zsplit), dim3(256), 0, side,
-                               SCK.as<ChunkInfo>(), SL.as<int64_t>(), STO.as<int64_t>(),
-                               STI.rows<double>(32), dslots,
-                               dnodes, dblocks, B[B_PINFO].as<ProbInfo>(), SRE.as<RqiResult>(),
-                               B[B_PROBS].as<ProbDesc>(), any_z);
-            prof.end(side);
-            HIPCHK(hipGetLastError());
+            // one round of consecutive chunks whose tiles fit the tile buffer
+            // (all chunks unless the work region is smaller than the level's
+            // tiles); the rounds reuse the buffer in stream order
+            for (int64_t c0 = 0; c0 < nchunk;) {
+                int64_t c1 = nchunk, base = 0;
+                if (!toff_h.empty()) {
+                    c1 = c0 + 1;
+                    while (c1 < nchunk && toff_h[c1 + 1] - toff_h[c0] <= tile_cap) ++c1;
+                    base = toff_h[c0];
+                }
+                const int64_t nc = c1 - c0;
+                prof.begin(MR3_STAGE_RQI, side);
+                hipLaunchKernelGGL(rqi, dim3((unsigned)((nc + wpg - 1) / wpg)), dim3(64 * wpg),
+                                   pad, side, SCK.as<ChunkInfo>() + c0, nc,
+                                   SL.as<int64_t>(), STO.as<int64_t>() + c0, base,
+                                   STI.rows<double>(32), dslots,
+                                   dnodes, dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
+                                   B[B_D64].rows<double>(), B[B_L64].rows<double>(), B[B_P].rows<Y>(),
+                                   B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>(), prm,
+                                   (double)YEps<Y>::v, SRE.as<RqiResult>(), counters, work);
+                prof.end(side);
+                prof.begin(MR3_STAGE_ZOUT, side);
+                // rows of a chunk are split over zsplit workgroups (blocks of
+                // 64 rows), so that large nodes' output is not one serial loop
+                hipLaunchKernelGGL((k_zout<X, Y>), dim3((unsigned)nc, (unsigned)zsplit), dim3(256), 0, side,
+                                   SCK.as<ChunkInfo>() + c0, SL.as<int64_t>(), STO.as<int64_t>() + c0, base,
+                                   STI.rows<double>(32), dslots,
+                                   dnodes, dblocks, B[B_PINFO].as<ProbInfo>(), SRE.as<RqiResult>(),
+                                   B[B_PROBS].as<ProbDesc>(), any_z);
+                prof.end(side);
+                HIPCHK(hipGetLastError());
+                c0 = c1;
+            }
             HIPCHK(hipEventRecord(h->ev_side[par], side));
             h->side_pending[par] = true;
             if (debug_on()) {
@@ -1137,21 +1380,21 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                     HIPCHK(download(ls, SL.p, (size_t)S, st));
                     HIPCHK(download(nds, dnodes, (size_t)n_nodes, st));
                     double sp = 0, sc = 0, sn = 0, it_mean = 0, it_cmax = 0;
-                    for (const ChunkInfo& c : cks) {
-                        const int64_t nn = blocks[nds[sl[ls[c.begin]].node].block].n;
+                    for (const ChunkInfo& ck : cks) {
+                        const int64_t nn = blocks[nds[sl[ls[ck.begin]].node].block].n;
                         int64_t mx = 0;
                         int imx = 0;
-                        for (int q = 0; q < c.count; ++q) {
-                            const int64_t r = rr[c.begin + q].r;
+                        for (int q = 0; q < ck.count; ++q) {
+                            const int64_t r = rr[ck.begin + q].r;
                             const int64_t len = std::max(r + 1, nn - r);
                             sp += (double)len;
                             mx = std::max(mx, len);
-                            imx = std::max(imx, rr[c.begin + q].iters);
-                            it_mean += rr[c.begin + q].iters;
+                            imx = std::max(imx, rr[ck.begin + q].iters);
+                            it_mean += rr[ck.begin + q].iters;
                         }
-                        sc += (double)mx * c.count;
-                        sn += (double)nn * c.count;
-                        it_cmax += (double)imx * c.count;
+                        sc += (double)mx * ck.count;
+                        sn += (double)nn * ck.count;
+                        it_cmax += (double)imx * ck.count;
                     }
                     std::fprintf(stderr, "[mr3]   sweep length / n: pair mean %.3f, chunk max (pair-weighted) %.3f, chunks %lld; iterations: mean %.2f, chunk max %.2f\n",
                                  sp / sn, sc / sn, (long long)nchunk, it_mean / S, it_cmax / S);
@@ -1164,12 +1407,12 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                         if (q.lgap > 0.0) g = std::min(g, q.lgap);
                         if (q.rgap > 0.0) g = std::min(g, q.rgap);
                         const double lam = std::max(std::fabs(q.lo), std::fabs(q.hi));
-                        const int b = (int)std::min(11.0, std::max(0.0, -std::log10(std::max(g / lam, 1e-300))));
-                        gh[std::min(std::max(rr[i].iters, 0), 5)][b]++;
+                        const int bk = (int)std::min(11.0, std::max(0.0, -std::log10(std::max(g / lam, 1e-300))));
+                        gh[std::min(std::max(rr[i].iters, 0), 5)][bk]++;
                     }
                     for (int it = 1; it < 6; ++it) {
                         std::fprintf(stderr, "[mr3]   iters %d by -log10(relgap):", it);
-                        for (int b = 0; b < 12; ++b) std::fprintf(stderr, " %lld", (long long)gh[it][b]);
+                        for (int bk = 0; bk < 12; ++bk) std::fprintf(stderr, " %lld", (long long)gh[it][bk]);
                         std::fprintf(stderr, "\n");
                     }
                 }
@@ -1194,22 +1437,19 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             }
             return MR3_OK;
         };
-        level_nodes.clear();
-        if (C == 0) {
-            const int rc = fork_singletons();
-            if (rc) return rc;
-            break;
-        }
+        if (C == 0) return fork_singletons();
         // With many more chunks than SIMDs (a large batch) the singleton work
         // is long and throughput bound while the cluster work is short: it
         // goes first, and the cluster work fills in beside it.  With few
         // chunks (one large problem) the cluster chain leads the critical path
         // and goes first (below).
         const bool fork_first = nchunk > 4096;
+        bool forked = false;
         if (fork_first) {
             stats.n_singleton_first_levels++;
             const int rc = fork_singletons();
             if (rc) return rc;
+            forked = true;
         }
         // ---- a5: clusters -> child representations ----
         HIPCHK(B[B_CREC].ensure(sizeof(ClusterRec) * C));
@@ -1217,156 +1457,186 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                            B[B_LIST2].as<int64_t>(), C, dslots, B[B_CREC].as<ClusterRec>());
         std::vector<ClusterRec> crec;
         HIPCHK(download(crec, B[B_CREC].p, (size_t)C, st));
-        std::vector<Node> pnodes;
-        // parent node info (block of each cluster) from the device
-        std::vector<ChildJob> jobs((size_t)C);
-        std::vector<int64_t> job_n((size_t)C);
-        int64_t new_rows = 0, tmp_rows = 0;
+        std::vector<int64_t> cl_n((size_t)C);  // rows of each cluster's block
         {
             std::vector<Node> allnodes;
             HIPCHK(download(allnodes, dnodes, (size_t)n_nodes, st));
             for (int64_t c = 0; c < C; ++c) {
-                const Node& pn = allnodes[crec[c].parent];
-                const int64_t nb = blocks[pn.block].n;
-                ChildJob j{};
-                j.head = crec[c].head;
-                j.last = crec[c].last;
-                j.parent = crec[c].parent;
-                j.child = (int)(n_nodes + c);
-                j.rep = pool_rows + new_rows;
-                j.tmp = tmp_rows;
-                new_rows += nb;
-                tmp_rows += nb;
-                jobs[c] = j;
-                job_n[c] = nb;
-                stats.largest_cluster = std::max<int64_t>(stats.largest_cluster, j.last - j.head + 1);
+                cl_n[c] = blocks[allnodes[crec[c].parent].block].n;
+                stats.largest_cluster = std::max<int64_t>(stats.largest_cluster, crec[c].last - crec[c].head + 1);
             }
         }
         stats.n_clusters += C;
-        // the side stream reads nodes and representations: it must be idle
-        // before any of these buffers is reallocated
-        const int64_t need = pool_rows + new_rows;
-        if (n_nodes + C > node_cap || B[B_REPD].cap < sizeof(Y) * (need + 2 * GUARD) ||
-            B[B_REPL].cap < sizeof(Y) * (need + 2 * GUARD) ||
-            B[B_D64].cap < sizeof(double) * (need + 2 * GUARD) ||
-            B[B_L64].cap < sizeof(double) * (need + 2 * GUARD))
-            HIPCHK(quiesce());
-        if (n_nodes + C > node_cap) {
-            node_cap = n_nodes + C + K;
-            HIPCHK(B[B_NODES].ensure(sizeof(Node) * node_cap, true, st));
-            dnodes = B[B_NODES].as<Node>();
-        }
-        HIPCHK(B[B_REPD].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
-        HIPCHK(B[B_REPL].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
-        HIPCHK(B[B_D64].ensure(sizeof(double) * (need + 2 * GUARD), true, st));
-        HIPCHK(B[B_L64].ensure(sizeof(double) * (need + 2 * GUARD), true, st));
-        HIPCHK(B[B_TMPC].ensure(sizeof(Y) * tmp_rows));
-        HIPCHK(B[B_TMPE].ensure(sizeof(int) * tmp_rows));
-        HIPCHK(upload(B[B_JOBS], jobs, st));
-        prof.begin(MR3_STAGE_CHILD, st);
-        hipLaunchKernelGGL(k_child_select, dim3((unsigned)C), dim3(64), 0, st,
-                           B[B_JOBS].as<ChildJob>(), C, dslots, dnodes, dblocks,
-                           B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm,
-                           prm.eps_x / (double)YEps<Y>::v);
-        hipLaunchKernelGGL(k_child_rep<Y>, dim3((unsigned)C), dim3(64), 0, st,
-                           B[B_JOBS].as<ChildJob>(), C, dslots, dnodes, dblocks, B[B_REPD].rows<Y>(),
-                           B[B_REPL].rows<Y>(), B[B_REPE].as<Y>(), B[B_D64].rows<double>(),
-                           B[B_L64].rows<double>(), B[B_TMPC].as<Y>(), B[B_TMPE].as<int>(),
-                           widen_root / prm.eps_x, prm.eps_x);
-        prof.end(st);
-        HIPCHK(hipGetLastError());
-        std::vector<ChildJob> done_jobs;
-        HIPCHK(download(done_jobs, B[B_JOBS].p, (size_t)C, st));
-        for (auto& j : done_jobs) {
-            if (j.best == 1) stats.n_best_candidate++;
-            if (j.best == 2) return MR3_ERR_NUMERIC;
-        }
-        pool_rows += new_rows;
-        n_nodes += C;
-        // ---- child bisection (Alg. 1, refine step): the members of every new
-        // cluster, whose slots now belong to the child node ----
-        int64_t KC = 0, KCs = 0;
-        for (int64_t c = 0; c < C; ++c) {
-            KC += crec[c].last - crec[c].head + 1;
-            if (job_n[c] >= STAGE_MIN_N && !no_stage()) KCs += crec[c].last - crec[c].head + 1;
-        }
-        L = pick_shape(KC - KCs, prm.lanes_per_eig, prm.points_per_lane);
-        // one wave per workgroup: the clusters of a level are many and small
-        const int cwaves = 1;
-        BisectShape Lcs;
-        {
-            std::vector<int64_t> sizes;
-            for (int64_t c = 0; c < C; ++c)
-                if (job_n[c] >= STAGE_MIN_N && !no_stage()) sizes.push_back(crec[c].last - crec[c].head + 1);
-            Lcs = pick_shape_groups(sizes, prm.lanes_per_eig);
-        }
-        BisectPlan cplan;
-        {
-            std::vector<int64_t> rest;
-            for (int64_t c = 0; c < C; ++c)
-                cplan.add(jobs[c].child, job_n[c], crec[c].head, crec[c].last - crec[c].head + 1,
-                          cwaves * (64 / Lcs.L), rest);
-            cplan.finish(rest);
-        }
-        HIPCHK(upload(B[B_LIST], cplan.list, st));
-        HIPCHK(upload(B[B_BWG], cplan.wgs, st));
-        if (debug_on()) HIPCHK(hipMemsetAsync(work + 6, 0, 2 * sizeof(double), st));
-        prof.begin(MR3_STAGE_CBISECT, st);
-        launch_bisect_staged(Lcs, B[B_BWG].as<BisWG>(), (int64_t)cplan.wgs.size(),
-                             B[B_LIST].as<int64_t>(), dslots, dnodes, dblocks,
-                             B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel,
-                             widen_root, work, 1, st, cwaves);
-        launch_bisect(L, B[B_LIST].as<int64_t>() + cplan.n_staged, KC - cplan.n_staged, dslots,
-                      dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
-                      prm.bisect_rel, widen_root, work, INT64_MAX, st);
-        prof.end(st);
-        if (debug_on()) {
-            std::vector<double> wk;
-            HIPCHK(download(wk, work, 8, st));
-            int nstrict = 0;
-            for (int64_t c = 0; c < C; ++c) nstrict += done_jobs[c].strict;
-            std::fprintf(stderr, "[mr3]   child bisection: %lld intervals, staged lanes %d, passes max %.0f total %.0f; strict children %d of %lld\n",
-                         (long long)KC, Lcs.L, wk[6], wk[7], nstrict, (long long)C);
-        }
-        // the level's singleton work goes to the side stream now: the bracket
-        // check (few waves) then shares the device with it, while the shift
-        // choice, child transform and child multisection before it (which
-        // fill the device and lead the critical path) do not
-        if (!fork_first) {
-            const int rc = fork_singletons();
+        // rows that groups below this level may need: one cluster of the
+        // largest block per level down to the depth cap
+        const int64_t reserve = (int64_t)std::max(0, prm.max_depth - 1 - depth) * nmax_blocks;
+        for (int64_t g0 = 0; g0 < C;) {
+            // ---- one group of clusters: [g0, g1) ----
+            int64_t g1 = g0, new_rows = 0;
+            while (g1 < C && (!fixed || rep_top + new_rows + cl_n[g1] + reserve <= rep_cap))
+                new_rows += cl_n[g1++];
+            if (g1 == g0) return MR3_ERR_HIP;  // cannot happen: the plan keeps room for one cluster
+            const int64_t CG = g1 - g0;
+            std::vector<ChildJob> jobs((size_t)CG);
+            int64_t off = 0;
+            for (int64_t c = 0; c < CG; ++c) {
+                ChildJob j{};
+                j.head = crec[g0 + c].head;
+                j.last = crec[g0 + c].last;
+                j.parent = crec[g0 + c].parent;
+                j.child = (int)(n_nodes + c);
+                j.rep = rep_top + off;
+                j.tmp = off;
+                off += cl_n[g0 + c];
+                jobs[c] = j;
+            }
+            // the side stream reads nodes and representations: it must be idle
+            // before any of these buffers is reallocated (handle's pool), and
+            // before rows that an earlier group's subtree used are overwritten
+            // (work region)
+            const int64_t need = rep_top + new_rows;
+            if (n_nodes + CG > node_cap || B[B_REPD].cap < sizeof(Y) * (need + 2 * GUARD) ||
+                B[B_REPL].cap < sizeof(Y) * (need + 2 * GUARD) ||
+                B[B_D64].cap < sizeof(double) * (need + 2 * GUARD) ||
+                B[B_L64].cap < sizeof(double) * (need + 2 * GUARD))
+                HIPCHK(quiesce());
+            if (rows_recycled) {
+                for (int q = 0; q < 2; ++q)
+                    if (h->side_pending[q]) HIPCHK(hipStreamWaitEvent(st, h->ev_side[q], 0));
+                rows_recycled = false;
+            }
+            if (n_nodes + CG > node_cap) {
+                node_cap = n_nodes + CG + K;
+                HIPCHK(B[B_NODES].ensure(sizeof(Node) * node_cap, true, st));
+                dnodes = B[B_NODES].as<Node>();
+            }
+            HIPCHK(B[B_REPD].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
+            HIPCHK(B[B_REPL].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
+            HIPCHK(B[B_D64].ensure(sizeof(double) * (need + 2 * GUARD), true, st));
+            HIPCHK(B[B_L64].ensure(sizeof(double) * (need + 2 * GUARD), true, st));
+            HIPCHK(B[B_TMPC].ensure(sizeof(Y) * new_rows));
+            HIPCHK(B[B_TMPE].ensure(sizeof(int) * new_rows));
+            HIPCHK(upload(B[B_JOBS], jobs, st));
+            prof.begin(MR3_STAGE_CHILD, st);
+            hipLaunchKernelGGL(k_child_select, dim3((unsigned)CG), dim3(64), 0, st,
+                               B[B_JOBS].as<ChildJob>(), CG, dslots, dnodes, dblocks,
+                               B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm,
+                               prm.eps_x / (double)YEps<Y>::v);
+            hipLaunchKernelGGL(k_child_rep<Y>, dim3((unsigned)CG), dim3(64), 0, st,
+                               B[B_JOBS].as<ChildJob>(), CG, dslots, dnodes, dblocks, B[B_REPD].rows<Y>(),
+                               B[B_REPL].rows<Y>(), B[B_REPE].as<Y>(), B[B_D64].rows<double>(),
+                               B[B_L64].rows<double>(), B[B_TMPC].as<Y>(), B[B_TMPE].as<int>(),
+                               widen_root / prm.eps_x, prm.eps_x);
+            prof.end(st);
+            HIPCHK(hipGetLastError());
+            std::vector<ChildJob> done_jobs;
+            HIPCHK(download(done_jobs, B[B_JOBS].p, (size_t)CG, st));
+            for (auto& j : done_jobs) {
+                if (j.best == 1) stats.n_best_candidate++;
+                if (j.best == 2) return MR3_ERR_NUMERIC;
+            }
+            const int64_t child0 = n_nodes, top_saved = rep_top;
+            rep_top += new_rows;
+            n_nodes += CG;
+            // ---- child bisection (Alg. 1, refine step): the members of every
+            // new cluster, whose slots now belong to the child node ----
+            int64_t KC = 0, KCs = 0;
+            for (int64_t c = 0; c < CG; ++c) {
+                const int64_t m = jobs[c].last - jobs[c].head + 1;
+                KC += m;
+                if (cl_n[g0 + c] >= STAGE_MIN_N && !no_stage()) KCs += m;
+            }
+            BisectShape L = pick_shape(KC - KCs, prm.lanes_per_eig, prm.points_per_lane);
+            // one wave per workgroup: the clusters of a level are many and small
+            const int cwaves = 1;
+            BisectShape Lcs;
+            {
+                std::vector<int64_t> sizes;
+                for (int64_t c = 0; c < CG; ++c)
+                    if (cl_n[g0 + c] >= STAGE_MIN_N && !no_stage()) sizes.push_back(jobs[c].last - jobs[c].head + 1);
+                Lcs = pick_shape_groups(sizes, prm.lanes_per_eig);
+            }
+            BisectPlan cplan;
+            {
+                std::vector<int64_t> rest;
+                for (int64_t c = 0; c < CG; ++c)
+                    cplan.add(jobs[c].child, cl_n[g0 + c], jobs[c].head, jobs[c].last - jobs[c].head + 1,
+                              cwaves * (64 / Lcs.L), rest);
+                cplan.finish(rest);
+            }
+            HIPCHK(upload(B[B_LIST], cplan.list, st));
+            HIPCHK(upload(B[B_BWG], cplan.wgs, st));
+            if (debug_on()) HIPCHK(hipMemsetAsync(work + 6, 0, 2 * sizeof(double), st));
+            prof.begin(MR3_STAGE_CBISECT, st);
+            launch_bisect_staged(Lcs, B[B_BWG].as<BisWG>(), (int64_t)cplan.wgs.size(),
+                                 B[B_LIST].as<int64_t>(), dslots, dnodes, dblocks,
+                                 B[B_D64].rows<double>(), B[B_L64].rows<double>(), prm.bisect_rel,
+                                 widen_root, work, 1, st, cwaves);
+            launch_bisect(L, B[B_LIST].as<int64_t>() + cplan.n_staged, KC - cplan.n_staged, dslots,
+                          dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
+                          prm.bisect_rel, widen_root, work, INT64_MAX, st);
+            prof.end(st);
+            if (debug_on()) {
+                std::vector<double> wk;
+                HIPCHK(download(wk, work, 8, st));
+                int nstrict = 0;
+                for (int64_t c = 0; c < CG; ++c) nstrict += done_jobs[c].strict;
+                std::fprintf(stderr, "[mr3]   child bisection: %lld intervals, staged lanes %d, passes max %.0f total %.0f; strict children %d of %lld\n",
+                             (long long)KC, Lcs.L, wk[6], wk[7], nstrict, (long long)CG);
+            }
+            // the level's singleton work goes to the side stream now: the
+            // bracket check (few waves) then shares the device with it, while
+            // the shift choice, child transform and child multisection before
+            // it (which fill the device and lead the critical path) do not
+            if (!forked) {
+                const int rc = fork_singletons();
+                if (rc) return rc;
+                forked = true;
+            }
+            prof.begin(MR3_STAGE_VERIFY, st);
+            if (is_dd) {
+                // A child accepted within the strict growth bound k_elg *
+                // spdiam is relatively robust like the root (Sec. 2,
+                // "Requirements on the representations"), so its binary64
+                // copy brackets its eigenvalues after the widening.  A child
+                // accepted under the relaxed bound or as least-growth
+                // candidate may not be: check its brackets with counts in y.
+                // one workgroup per 32 slots of one child node
+                std::vector<int64_t> vlist;
+                std::vector<BisWG> vwg;
+                for (int64_t c = 0; c < CG; ++c) {
+                    if (done_jobs[c].strict) continue;
+                    const int64_t m = jobs[c].last - jobs[c].head + 1;
+                    for (int64_t o = 0; o < m; o += 32)
+                        vwg.push_back(BisWG{(int64_t)vlist.size() + o, (int)std::min<int64_t>(32, m - o),
+                                            jobs[c].child});
+                    for (int64_t sidx = jobs[c].head; sidx <= jobs[c].last; ++sidx) vlist.push_back(sidx);
+                }
+                if (!vwg.empty()) {
+                    HIPCHK(upload(B[B_VLIST], vlist, st));
+                    HIPCHK(upload(B[B_VWG], vwg, st));
+                    hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)vwg.size()), dim3(64), 0, st,
+                                       B[B_VWG].as<BisWG>(), B[B_VLIST].as<int64_t>(), dslots, dnodes,
+                                       dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
+                                       prm.bisect_rel, counters + 3);
+                }
+            }
+            prof.end(st);
+            HIPCHK(hipGetLastError());
+            // ---- the children of this group, recursively ----
+            const int rc = visit(child0, child0 + CG, depth + 1);
             if (rc) return rc;
-        }
-        prof.begin(MR3_STAGE_VERIFY, st);
-        if (is_dd) {
-            // A child accepted within the strict growth bound k_elg * spdiam
-            // is relatively robust like the root (Sec. 2, "Requirements on
-            // the representations"), so its binary64 copy brackets its
-            // eigenvalues after the widening.  A child accepted under the
-            // relaxed bound or as least-growth candidate may not be: check
-            // its brackets with counts in y.
-            // one workgroup per 32 slots of one child node
-            std::vector<int64_t> vlist;
-            std::vector<BisWG> vwg;
-            for (int64_t c = 0; c < C; ++c) {
-                if (done_jobs[c].strict) continue;
-                const int64_t m = crec[c].last - crec[c].head + 1;
-                for (int64_t o = 0; o < m; o += 32)
-                    vwg.push_back(BisWG{(int64_t)vlist.size() + o, (int)std::min<int64_t>(32, m - o),
-                                        jobs[c].child});
-                for (int64_t sidx = crec[c].head; sidx <= crec[c].last; ++sidx) vlist.push_back(sidx);
+            if (fixed) {  // pop the group's rows; their readers finish first
+                rep_top = top_saved;
+                rows_recycled = true;
             }
-            if (!vwg.empty()) {
-                HIPCHK(upload(B[B_VLIST], vlist, st));
-                HIPCHK(upload(B[B_VWG], vwg, st));
-                hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)vwg.size()), dim3(64), 0, st,
-                                   B[B_VWG].as<BisWG>(), B[B_VLIST].as<int64_t>(), dslots, dnodes,
-                                   dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
-                                   prm.bisect_rel, counters + 3);
-            }
+            g0 = g1;
         }
-        prof.end(st);
-        HIPCHK(hipGetLastError());
-        for (int64_t c = 0; c < C; ++c) level_nodes.push_back(jobs[c].child);
+        return MR3_OK;
+    };
+    {
+        const int rc = visit(0, NB, 0);
+        if (rc) return rc;
     }
     // ---- join the side stream; diagnostics and the ascending-order check ----
     for (int q = 0; q < 2; ++q)
@@ -1470,10 +1740,20 @@ static int check_single(int64_t n, const void* d, const void* e, int range, doub
     return 0;
 }
 
+// After a failed solve on a caller's work region, device work of the call may
+// still read or write the region: it ends before the caller gets it back.
+static int finish_on_region(mr3_handle h, int rc, void* work, void* stream) {
+    if (rc != MR3_OK && work) {
+        (void)hipSetDevice(h->device);
+        (void)hipStreamSynchronize((hipStream_t)stream);
+    }
+    return rc;
+}
+
 template <class X, class Y>
 static int solve_single(mr3_handle h, int64_t n, const X* d, const X* e, int range, double vl,
                         double vu, int64_t il, int64_t iu, int64_t* m, X* W, X* Z, int64_t ldz,
-                        void* stream) {
+                        void* work, size_t work_bytes, void* stream, int work_small_rc) {
     if (!h) return -1;
     int rc = check_single(n, d, e, range, vl, vu, il, iu, m, W, Z, ldz);
     if (rc) return rc;
@@ -1485,8 +1765,10 @@ static int solve_single(mr3_handle h, int64_t n, const X* d, const X* e, int ran
     rd.il = il;
     rd.iu = iu;
     const int64_t nn = n, lz = ldz;
-    rc = solve_impl<X, Y>(h, 1, &nn, &d, &e, &rd, m, &W, &Z, &lz, (hipStream_t)stream);
-    return rc;
+    rc = solve_impl<X, Y>(h, 1, &nn, &d, &e, &rd, m, &W, &Z, &lz, (hipStream_t)stream, work,
+                          work_bytes);
+    if (rc == ERR_WORK_SMALL) rc = work_small_rc;
+    return finish_on_region(h, rc, work, stream);
 }
 
 // base pointers + element offsets -> per-problem pointers
@@ -1494,7 +1776,7 @@ template <class X, class Y>
 static int batched_ptrs(mr3_handle h, int64_t count, const int64_t* n, const int64_t* de_off,
                         const X* d, const X* e, const mr3_range_desc* ranges, int64_t* m, X* W,
                         const int64_t* w_off, X* Z, const int64_t* z_off, const int64_t* ldz,
-                        hipStream_t st) {
+                        void* work, size_t work_bytes, hipStream_t st) {
     std::vector<const X*> dp((size_t)count), ep((size_t)count);
     std::vector<X*> wp((size_t)count), zp((size_t)count, nullptr);
     for (int64_t p = 0; p < count; ++p) {
@@ -1503,8 +1785,10 @@ static int batched_ptrs(mr3_handle h, int64_t count, const int64_t* n, const int
         wp[p] = W + w_off[p];
         if (Z) zp[p] = Z + z_off[p];
     }
-    return solve_impl<X, Y>(h, count, n, dp.data(), ep.data(), ranges, m, wp.data(),
-                            Z ? zp.data() : nullptr, ldz, st);
+    int rc = solve_impl<X, Y>(h, count, n, dp.data(), ep.data(), ranges, m, wp.data(),
+                              Z ? zp.data() : nullptr, ldz, st, work, work_bytes);
+    if (rc == ERR_WORK_SMALL) rc = -16;
+    return finish_on_region(h, rc, work, st);
 }
 
 template <class X, class Y>
@@ -1520,7 +1804,7 @@ static int solve_ptrs_typed(mr3_handle h, int64_t count, const int64_t* n, const
         if (Z) zp[p] = static_cast<X*>(Z[p]);
     }
     return solve_impl<X, Y>(h, count, n, dp.data(), ep.data(), ranges, m, wp.data(),
-                            Z ? zp.data() : nullptr, ldz, st);
+                            Z ? zp.data() : nullptr, ldz, st, nullptr, 0);
 }
 
 int mr3_solve_ptrs(mr3_handle h, int precision, int64_t count, const int64_t* n,
@@ -1548,6 +1832,23 @@ int mr3_create(mr3_handle* h, int device) {
     if (device < 0 || device >= nd) return -2;
     mr3_handle_s* x = new mr3_handle_s();
     x->device = device;
+    // set-up on the device: the side streams and their events, and a first
+    // pinned staging chunk (a solve on a caller's work region does not grow it)
+    bool ok = hipSetDevice(device) == hipSuccess &&
+              hipStreamCreateWithFlags(&x->side[0], hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&x->side[1], hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&x->ev_side[0], hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&x->ev_side[1], hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+        x->stage.reset();
+        ok = x->stage.get(1) != nullptr;
+        x->stage.reset();
+    }
+    if (!ok) {
+        (void)mr3_destroy(x);
+        return MR3_ERR_HIP;
+    }
     *h = x;
     return MR3_OK;
 }
@@ -1596,20 +1897,84 @@ int mr3_get_stats(mr3_handle h, mr3_stats* s) {
 
 int mr3_solve_f32(mr3_handle h, int64_t n, const float* d, const float* e, int range, double vl,
                   double vu, int64_t il, int64_t iu, int64_t* m, float* W, float* Z, int64_t ldz,
-                  void* stream) {
-    return solve_single<float, double>(h, n, d, e, range, vl, vu, il, iu, m, W, Z, ldz, stream);
+                  void* work, size_t work_bytes, void* stream) {
+    return solve_single<float, double>(h, n, d, e, range, vl, vu, il, iu, m, W, Z, ldz, work,
+                                       work_bytes, stream, -15);
 }
 
 int mr3_solve_f64(mr3_handle h, int64_t n, const double* d, const double* e, int range, double vl,
                   double vu, int64_t il, int64_t iu, int64_t* m, double* W, double* Z, int64_t ldz,
-                  void* stream) {
-    return solve_single<double, dd>(h, n, d, e, range, vl, vu, il, iu, m, W, Z, ldz, stream);
+                  void* work, size_t work_bytes, void* stream) {
+    return solve_single<double, dd>(h, n, d, e, range, vl, vu, il, iu, m, W, Z, ldz, work,
+                                    work_bytes, stream, -15);
+}
+
+// Shape of a single problem for the workspace query: every row its own block
+// at worst; k wanted eigenvalues plus at most two helpers per block that has
+// wanted eigenvalues (no more slots than rows).
+static Shape query_shape(mr3_handle h, int64_t n, int range, int64_t k_max, int precision) {
+    const Params prm = h ? effective(h, precision) : Params{};
+    Shape s;
+    s.count = 1;
+    s.R = n;
+    s.NB = n;
+    const int64_t k = (range == RANGE_ALL || k_max <= 0) ? n : std::min(n, k_max);
+    s.K = (range == RANGE_ALL || k == n) ? n : std::min(n, 3 * k);
+    s.nmax = n;
+    s.max_depth = h ? prm.max_depth : 6;
+    s.dd = precision == 64;
+    s.dqds = h && prm.initial == MR3_INITIAL_DQDS;
+    s.xsize = precision == 64 ? 8 : 4;
+    return s;
+}
+
+size_t mr3_workspace_bytes(mr3_handle h, int64_t n, int range, int64_t k_max, int precision) {
+    if (n <= 0 || range < 0 || range > 2 || (precision != 32 && precision != 64)) return 0;
+    const Shape s = query_shape(h, n, range, k_max, precision);
+    return full_bytes(s, n * (s.K + 32));
+}
+
+size_t mr3_workspace_min_bytes(mr3_handle h, int64_t n, int range, int64_t k_max, int precision) {
+    if (n <= 0 || range < 0 || range > 2 || (precision != 32 && precision != 64)) return 0;
+    Shape s = query_shape(h, n, range, k_max, precision);
+    size_t sz[B_NBUF] = {0};
+    prep_sizes(s, sz);
+    s.rep_rows = min_rep_rows(s);
+    s.tile_rows = min_tile_rows(s);
+    solve_sizes(s, sz);
+    return 256 + phase_bytes(sz, true) + phase_bytes(sz, false) + 256 * (size_t)B_NBUF;
+}
+
+size_t mr3_workspace_bytes_batched(mr3_handle h, int64_t count, int precision, const int64_t* n,
+                                   const mr3_range_desc* ranges) {
+    if (count <= 0 || !n || (precision != 32 && precision != 64)) return 0;
+    Shape s;
+    int64_t tile_full = 0;
+    for (int64_t p = 0; p < count; ++p) {
+        if (n[p] < 0) return 0;
+        const int r = ranges ? ranges[p].range : RANGE_ALL;
+        const int64_t k = (r == RANGE_INDEX) ? std::max<int64_t>(ranges[p].iu - ranges[p].il + 1, 0) : n[p];
+        const Shape q = query_shape(h, n[p], r, k, precision);
+        s.R += q.R;
+        s.NB += q.NB;
+        s.K += q.K;
+        s.nmax = std::max(s.nmax, q.nmax);
+        s.max_depth = q.max_depth;
+        s.dd = q.dd;
+        s.dqds = q.dqds;
+        s.xsize = q.xsize;
+        tile_full += q.R * (q.K + 32);
+    }
+    s.count = count;
+    if (s.R == 0) return 0;
+    return full_bytes(s, tile_full);
 }
 
 int mr3_solve_batched(mr3_handle h, int64_t count, int precision, const int64_t* n,
                       const int64_t* de_off, const void* d, const void* e,
                       const mr3_range_desc* ranges, int64_t* m, void* W, const int64_t* w_off,
-                      void* Z, const int64_t* z_off, const int64_t* ldz, void* stream) {
+                      void* Z, const int64_t* z_off, const int64_t* ldz, void* work,
+                      size_t work_bytes, void* stream) {
     if (!h) return -1;
     if (count < 0) return -2;
     if (precision != 32 && precision != 64) return -3;
@@ -1634,9 +1999,9 @@ int mr3_solve_batched(mr3_handle h, int64_t count, int precision, const int64_t*
     if (precision == 32)
         return batched_ptrs<float, double>(h, count, n, de_off, (const float*)d, (const float*)e,
                                            ranges, m, (float*)W, w_off, (float*)Z, z_off, ldz,
-                                           (hipStream_t)stream);
+                                           work, work_bytes, (hipStream_t)stream);
     return batched_ptrs<double, dd>(h, count, n, de_off, (const double*)d, (const double*)e, ranges,
-                                    m, (double*)W, w_off, (double*)Z, z_off, ldz,
+                                    m, (double*)W, w_off, (double*)Z, z_off, ldz, work, work_bytes,
                                     (hipStream_t)stream);
 }
 

@@ -52,6 +52,7 @@ int main(void) {
            sizeof(mr3_result));
     F(mr3_params, seed) F(mr3_params, profile) F(mr3_params, points_per_lane) F(mr3_params, gaptol_abs) F(mr3_params, initial)
     F(mr3_stats, stage_ms) F(mr3_stats, twist_row_steps) F(mr3_stats, dqds_transforms)
+    F(mr3_stats, n_sliced_roots) F(mr3_stats, n_singleton_first_levels)
     F(mr3_request, range) F(mr3_request, ldz) F(mr3_result, batch_size)
     return 0;
 }
@@ -91,9 +92,9 @@ def test_argument_errors_without_device_work():
     m = ctypes.c_int64(0)
     # null handle
     assert lib.mr3_solve_f64(None, 4, None, None, 0, 0.0, 0.0, 1, 4, ctypes.byref(m), None, None,
-                             4, None) == -1
+                             4, None, 0, None) == -1
     assert lib.mr3_solve_batched(None, 1, 64, None, None, None, None, None, None, None, None,
-                                 None, None, None, None) == -1
+                                 None, None, None, None, 0, None) == -1
     assert lib.mr3_check_f64(None, 1, 1, None, None, None, None, 1, None, None, None) == -1
     assert lib.mr3_destroy(None) == -1
     assert lib.mr3_server_destroy(None) == -1
@@ -107,3 +108,33 @@ def test_request_bytes_monotone():
     b = [mr3.mr3_request_bytes(n, k, 64) for n, k in ((0, 0), (64, 64), (1000, 100), (1000, 1000))]
     assert b[0] > 0 and b[1] < b[2] < b[3]
     assert mr3.mr3_request_bytes(20000, 20000, 64) >= 8 * 20000 * 20000
+
+
+def test_workspace_query():
+    """mr3_workspace_bytes (no handle needed for the defaults): zero for
+    invalid arguments and n = 0; at least the eigenvector tiles of a whole
+    level (n (k + 32) binary64 values per side-stream parity); growing with
+    n and with the wanted pairs; more for double-double than binary64
+    working precision; the batched query of one problem equals the single
+    one."""
+    q = mr3.mr3_workspace_bytes
+    A, V, I = mr3.RANGE_ALL, mr3.RANGE_VALUE, mr3.RANGE_INDEX
+    assert q(None, 0, A, 0, 64) == 0 and q(None, -1, A, 0, 64) == 0
+    assert q(None, 10, 7, 0, 64) == 0 and q(None, 10, A, 0, 16) == 0
+    for n in (1, 100, 4096, 20000):
+        full = q(None, n, A, 0, 64)
+        assert full >= 2 * 8 * n * (n + 32)
+        assert q(None, n, A, 0, 32) < full
+        assert q(None, n, I, max(1, n // 10), 64) <= full
+        assert n == 1 or q(None, n, I, n // 10, 64) < full
+        assert q(None, n, V, 0, 64) == full  # unknown count: all pairs
+        assert mr3.mr3_workspace_bytes_batched(None, 64, [n]) == full
+        low = mr3.mr3_workspace_min_bytes(None, n, A, 0, 64)
+        assert 0 < low <= full and (n < 1000 or low < full / 8)
+    assert q(None, 2000, A, 0, 64) < q(None, 4000, A, 0, 64)
+    assert q(None, 4000, I, 100, 64) < q(None, 4000, I, 1000, 64)
+    two = mr3.mr3_workspace_bytes_batched(None, 32, [300, 500], [(A, 0.0, 0.0, 1, 300),
+                                                              (I, 0.0, 0.0, 1, 50)])
+    assert two > q(None, 500, I, 50, 32)
+    assert mr3.mr3_workspace_bytes_batched(None, 32, []) == 0
+
