@@ -240,6 +240,27 @@ int mr3_solve_batched(mr3_handle h, int64_t count, int precision, const int64_t 
                       void *Z, const int64_t *z_off, const int64_t *ldz, void *work,
                       size_t work_bytes, void *stream);
 
+/* ---- Single solve that allocates nothing ----
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it).  The same solve as
+ * mr3_solve_f32 (precision 32) or mr3_solve_f64 (precision 64) with the work
+ * region taken from a static device array of the library,
+ * MR3_NOALLOC_SCRATCH_BYTES long, one per GPU, allocated when the library's
+ * code object is loaded on that GPU and held until the process ends; its
+ * device address is resolved once per device by mr3_create.  The call
+ * allocates no device or pinned host memory.  Every call on a GPU shares that
+ * GPU's array (within one process; each process has its own copy), which
+ * keeps the last call's contents, so calls that overlap on one GPU, from
+ * several host threads or handles, race: serialise them.  Arguments: 1 h, 2 precision (32 or 64), 3 n (at most
+ * MR3_NOALLOC_MAX_N), 4 d, 5 e, 6 range, 7 vl, 8 vu, 9 il, 10 iu, 11 m, 12 W,
+ * 13 Z, 14 ldz, 15 stream, as for mr3_solve_f32 / mr3_solve_f64.  Errors as
+ * there; n above MR3_NOALLOC_MAX_N returns -3. */
+#define MR3_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+#define MR3_NOALLOC_MAX_N 16384
+int mr3_solve_noalloc(mr3_handle h, int precision, int64_t n, const void *d, const void *e,
+                      int range, double vl, double vu, int64_t il, int64_t iu, int64_t *m, void *W,
+                      void *Z, int64_t ldz, void *stream);
+
 /* Verification (not part of a solve; Section 1, eq. (1)).  For the FP64
  * eigenpairs (W, Z) of the FP64 tridiagonal (d, e), all device pointers:
  * orth_out[0] = max_{i != j} |z_i^T z_j| and orth_out[1] = max_i |z_i^T z_i - 1|,

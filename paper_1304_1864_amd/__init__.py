@@ -30,6 +30,8 @@ STAGES = ["prep", "bisect", "classify", "rqi", "zout", "child", "cbisect", "veri
 MR3_OK, MR3_ERR_NUMERIC, MR3_ERR_HIP, MR3_ERR_NO_DEVICE, MR3_ERR_GAPTOL = 0, 1, 2, 3, 4
 MR3_INITIAL_BISECTION, MR3_INITIAL_DQDS = 0, 1
 MR3_DQDS_MAX_N = 4096
+MR3_NOALLOC_SCRATCH_BYTES = 128 << 20
+MR3_NOALLOC_MAX_N = 16384
 
 
 class MR3Error(RuntimeError):
@@ -123,6 +125,7 @@ EXPORTS = [
     "mr3_create", "mr3_destroy", "mr3_default_params", "mr3_set_params", "mr3_get_stats",
     "mr3_solve_f32", "mr3_solve_f64", "mr3_solve_batched", "mr3_check_f64", "mr3_version",
     "mr3_workspace_bytes", "mr3_workspace_min_bytes", "mr3_workspace_bytes_batched",
+    "mr3_solve_noalloc",
     "mr3_request_bytes", "mr3_server_create", "mr3_server_create_with_executor",
     "mr3_server_submit", "mr3_server_poll", "mr3_server_wait", "mr3_server_destroy",
 ]
@@ -156,6 +159,8 @@ def load_library(path: str | None = None):
     lib.mr3_workspace_bytes.argtypes = [vp, i64, i32, i64, i32]
     lib.mr3_workspace_min_bytes.argtypes = [vp, i64, i32, i64, i32]
     lib.mr3_workspace_bytes_batched.argtypes = [vp, i64, i32, pi64, ctypes.POINTER(mr3_range_desc)]
+    lib.mr3_solve_noalloc.argtypes = [vp, i32, i64, vp, vp, i32, dbl, dbl, i64, i64, pi64, vp, vp,
+                                      i64, vp]
     lib.mr3_check_f64.argtypes = [vp, i64, i64, vp, vp, vp, vp, i64,
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
     lib.mr3_request_bytes.argtypes = [i64, i64, i32]
@@ -284,6 +289,15 @@ def mr3_solve_f64(h, n, d, e, range_, vl, vu, il, iu, W, Z, ldz, stream=None, wo
     return m.value
 
 
+def mr3_solve_noalloc(h, precision, n, d, e, range_, vl, vu, il, iu, W, Z, ldz, stream=None) -> int:
+    m = ctypes.c_int64(0)
+    rc = load_library().mr3_solve_noalloc(h.ptr, precision, n, _ptr(d), _ptr(e), range_, vl, vu,
+                                          il, iu, ctypes.byref(m), _ptr(W), _ptr(Z), ldz,
+                                          _stream_ptr(stream))
+    _check("mr3_solve_noalloc", rc)
+    return m.value
+
+
 def mr3_workspace_bytes(h, n: int, range_: int, k_max: int, precision: int) -> int:
     return int(load_library().mr3_workspace_bytes(h.ptr if h is not None else None, n, range_,
                                                   k_max, precision))
@@ -343,10 +357,10 @@ _RANGES = {"all": RANGE_ALL, "value": RANGE_VALUE, "index": RANGE_INDEX}
 
 def solve(d: torch.Tensor, e: torch.Tensor, range: str = "all", vl: float = 0.0, vu: float = 0.0,
           il: int = 1, iu: int | None = None, vectors: bool = True, handle: Handle | None = None,
-          stream=None, work: torch.Tensor | None = None):
+          stream=None, work: torch.Tensor | None = None, noalloc: bool = False):
     """Eigenpairs of the tridiagonal (d, e); returns (W[m], Z[n, m] or None).
     work: a device tensor used as the call's work region (None: the handle's
-    pool)."""
+    pool); noalloc: run mr3_solve_noalloc (the library's static scratch)."""
     if not d.is_cuda:
         raise ValueError("d and e must be device tensors")
     h = handle or default_handle()
@@ -362,7 +376,11 @@ def solve(d: torch.Tensor, e: torch.Tensor, range: str = "all", vl: float = 0.0,
     if d.dtype not in (torch.float32, torch.float64) or e.dtype != d.dtype:
         raise ValueError("d and e must both be float32 or both float64")
     dc, ec = d.contiguous(), (e.contiguous() if n > 1 else None)
-    m = fn(h, n, dc, ec, rk, vl, vu, il, iu, W, Zt, max(n, 1), stream, work)
+    if noalloc:
+        prec = 32 if d.dtype == torch.float32 else 64
+        m = mr3_solve_noalloc(h, prec, n, dc, ec, rk, vl, vu, il, iu, W, Zt, max(n, 1), stream)
+    else:
+        m = fn(h, n, dc, ec, rk, vl, vu, il, iu, W, Zt, max(n, 1), stream, work)
     W = W[:m]
     Z = Zt[:m].T if vectors else None
     return W, Z

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -485,6 +486,7 @@ struct mr3_handle_s {
     bool side_pending[2] = {false, false};
     mr3::Staging stage;      // pinned host staging
     bool clean_exit = true;  // the last solve synchronised its stream
+    void* scratch = nullptr; // device address of this device's no-allocation scratch
 };
 
 namespace mr3 {
@@ -1721,6 +1723,31 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
 }  // namespace mr3
 
 // --------------------------------------------------------------------------
+// Scratch of the entry point that allocates nothing (mr3_solve_noalloc): device
+// memory of the library's code object, one copy per GPU, held until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress, once per device at handle set-up,
+// and only that address is passed to kernels and copies.
+// --------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[MR3_NOALLOC_SCRATCH_BYTES];
+
+// device address of `scratch` on `device`, which must be current; nullptr if
+// the runtime cannot resolve it
+static void* scratch_address(int device) {
+    static std::mutex mu;
+    static std::vector<void*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) return nullptr;
+    if ((int)addr.size() <= device) addr.resize((size_t)device + 1, nullptr);
+    if (!addr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        addr[device] = p;
+    }
+    return addr[device];
+}
+
+// --------------------------------------------------------------------------
 // C ABI
 // --------------------------------------------------------------------------
 using namespace mr3;
@@ -1832,14 +1859,19 @@ int mr3_create(mr3_handle* h, int device) {
     if (device < 0 || device >= nd) return -2;
     mr3_handle_s* x = new mr3_handle_s();
     x->device = device;
-    // set-up on the device: the side streams and their events, and a first
-    // pinned staging chunk (a solve on a caller's work region does not grow it)
+    // set-up on the device: the side streams and their events, the device
+    // address of the no-allocation scratch array, and a first pinned staging
+    // chunk (a solve on a caller's work region does not grow it)
     bool ok = hipSetDevice(device) == hipSuccess &&
               hipStreamCreateWithFlags(&x->side[0], hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&x->side[1], hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&x->ev_side[0], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&x->ev_side[1], hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+        x->scratch = scratch_address(device);
+        ok = x->scratch != nullptr;
+    }
     if (ok) {
         x->stage.reset();
         ok = x->stage.get(1) != nullptr;
@@ -1907,6 +1939,26 @@ int mr3_solve_f64(mr3_handle h, int64_t n, const double* d, const double* e, int
                   void* work, size_t work_bytes, void* stream) {
     return solve_single<double, dd>(h, n, d, e, range, vl, vu, il, iu, m, W, Z, ldz, work,
                                     work_bytes, stream, -15);
+}
+
+int mr3_solve_noalloc(mr3_handle h, int precision, int64_t n, const void* d, const void* e,
+                      int range, double vl, double vu, int64_t il, int64_t iu, int64_t* m, void* W,
+                      void* Z, int64_t ldz, void* stream) {
+    if (!h) return -1;
+    if (precision != 32 && precision != 64) return -2;
+    if (n > MR3_NOALLOC_MAX_N) return -3;
+    const int rc = check_single(n, d, e, range, vl, vu, il, iu, m, W, Z, ldz);
+    if (rc) return rc - 1;  // positions after the extra `precision` argument
+    if (!h->scratch) return MR3_ERR_HIP;
+    // the scratch is the work region of an ordinary solve; one that does not
+    // fit it (n above the limit) is refused as a size error
+    if (precision == 32)
+        return solve_single<float, double>(h, n, (const float*)d, (const float*)e, range, vl, vu, il,
+                                           iu, m, (float*)W, (float*)Z, ldz, h->scratch,
+                                           MR3_NOALLOC_SCRATCH_BYTES, stream, -3);
+    return solve_single<double, dd>(h, n, (const double*)d, (const double*)e, range, vl, vu, il, iu,
+                                    m, (double*)W, (double*)Z, ldz, h->scratch,
+                                    MR3_NOALLOC_SCRATCH_BYTES, stream, -3);
 }
 
 // Shape of a single problem for the workspace query: every row its own block

@@ -95,6 +95,8 @@ def test_argument_errors_without_device_work():
                              4, None, 0, None) == -1
     assert lib.mr3_solve_batched(None, 1, 64, None, None, None, None, None, None, None, None,
                                  None, None, None, None, 0, None) == -1
+    assert lib.mr3_solve_noalloc(None, 64, 4, None, None, 0, 0.0, 0.0, 1, 4, ctypes.byref(m), None,
+                                 None, 4, None) == -1
     assert lib.mr3_check_f64(None, 1, 1, None, None, None, None, 1, None, None, None) == -1
     assert lib.mr3_destroy(None) == -1
     assert lib.mr3_server_destroy(None) == -1
@@ -138,3 +140,15 @@ def test_workspace_query():
     assert two > q(None, 500, I, 50, 32)
     assert mr3.mr3_workspace_bytes_batched(None, 32, []) == 0
 
+
+def test_noalloc_limits_declared():
+    text = open(HEADER).read()
+    assert "MR3_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)" in text
+    assert "MR3_NOALLOC_MAX_N 16384" in text
+    lib = mr3.load_library()
+    m = ctypes.c_int64(0)
+    # precision and size are checked before the handle is used
+    assert lib.mr3_solve_noalloc(ctypes.c_void_p(1), 16, 4, None, None, 0, 0.0, 0.0, 1, 4,
+                                 ctypes.byref(m), None, None, 4, None) == -2
+    assert lib.mr3_solve_noalloc(ctypes.c_void_p(1), 64, 16385, None, None, 0, 0.0, 0.0, 1, 4,
+                                 ctypes.byref(m), None, None, 16385, None) == -3
