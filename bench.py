@@ -61,12 +61,31 @@ def build_workload(n: int, seed: int):
     return d, e
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def alg_flops(st, y: str) -> float:
+    """Algorithmic FP64 flops of the last solve on a handle (its stats): Sturm
+    counts, twist pre-pass and RQI sweeps at the per-row counts above."""
+    return (st["bisect_row_steps"] * FLOPS_COUNT + st["twist_row_steps"] * FLOPS_TWIST
+            + st["rqi_row_steps"] * FLOPS_RQI[y])
+
+
 def cpu_baseline(d, e, n, budget_s=20.0):
     """Oracle (double-double bisection + inverse iteration) on a bounded
-    sample: contiguous index chunks spread over the spectrum."""
+    sample: contiguous index chunks spread over the spectrum, on the cores
+    this process may use (at most 16, the host share of one GPU)."""
     import oracle
 
-    threads = min(16, os.cpu_count() or 1)
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = min(16, avail)
     chunk = 512  # about 10-20 s of oracle work on 16 cores
     starts = [1, n // 4, n // 2, 3 * n // 4, n - chunk + 1]
     done = 0
@@ -80,7 +99,8 @@ def cpu_baseline(d, e, n, budget_s=20.0):
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "eigenpairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} eigenpairs (index chunks of {chunk} at {starts[:done // chunk]}) "
-                      f"of the same n={n} matrix, {dt:.1f} s"}
+                      f"of the same n={n} matrix, {dt:.1f} s",
+            "host": {"nproc": os.cpu_count(), "usable": avail, "model": cpu_model()}}
 
 
 def batched_c3(mr3, h, steps, warmup, plain_sample=512, seed=0):
@@ -123,6 +143,7 @@ def batched_c3(mr3, h, steps, warmup, plain_sample=512, seed=0):
         torch.cuda.synchronize()
         ms.append((time.perf_counter() - ts) * 1e3)
     assert sum(m) == total
+    batch_flops = alg_flops(h.stats(), "f64")
     # plain: one solve per problem, sequentially on one stream
     k = min(plain_sample, count)
     Wp = torch.empty(1024, dtype=torch.float32, device=dev)
@@ -132,6 +153,7 @@ def batched_c3(mr3, h, steps, warmup, plain_sample=512, seed=0):
                           Wp, Zp, n[i], stream)
     torch.cuda.synchronize()
     pm = []
+    plain_flops = 0.0
     t0 = time.perf_counter()
     for i in range(k):
         ts = time.perf_counter()
@@ -139,22 +161,29 @@ def batched_c3(mr3, h, steps, warmup, plain_sample=512, seed=0):
                           Wp, Zp, n[i], stream)
         torch.cuda.synchronize()
         pm.append((time.perf_counter() - ts) * 1e3)
+        plain_flops += alg_flops(h.stats(), "f64")
     plain_s = time.perf_counter() - t0
     pairs_k = int(sum(n[:k]))
     med = float(np.median(ms))
+    peak = FP64_VECTOR_PEAK_TFLOPS * 1e12
     return {
         "workload": "4096 tridiagonals, n log-uniform in [32, 1024] (sum n = %d), d, e ~ N(0,1), "
                     "fp32 I/O, fp64 internal, all eigenpairs, seed %d" % (total, seed),
         "batched": {"eigenpairs_per_s": round(total / (med / 1e3), 1), "p50_ms": round(med, 3),
-                    "p99_ms": round(float(np.percentile(ms, 99)), 3), "steps": steps},
+                    "p99_ms": round(float(np.percentile(ms, 99)), 3), "steps": steps,
+                    "roofline": {"bound": "alu", "achieved": round(batch_flops / (med / 1e3) / 1e12, 3),
+                                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": round(batch_flops / (med / 1e3) / peak, 4),
+                                 "what": "algorithmic FP64 flops of the whole solve / its time"}},
         "plain": {"eigenpairs_per_s": round(pairs_k / plain_s, 1),
                   "p50_ms_per_problem": round(float(np.median(pm)), 3),
                   "p99_ms_per_problem": round(float(np.percentile(pm, 99)), 3),
+                  "roofline_frac": round(plain_flops / plain_s / peak, 5),
                   "sample": f"first {k} problems ({pairs_k} eigenpairs), one mr3_solve_f32 each"},
     }
 
 
-def served_c5(mr3, n_req=2000, seed=0, window=64, calib=600):
+def served_c5(mr3, n_req=2000, seed=0, window=64, calib=600, slots=2):
     """Served stream: requests with n log-uniform in [64, 8192], half FP32 /
     half FP64, 30% INDEX ranges of ceil(0.1 n), half U(-1,1) and half 1-2-1
     plus N(0, (1e-6)^2) noise, all vectors.  Saturation S from a closed loop
@@ -168,8 +197,42 @@ def served_c5(mr3, n_req=2000, seed=0, window=64, calib=600):
     reqs = W.served_requests(n_req, seed=seed)
     inputs = [(torch.from_numpy(r["d"]).to(dev), torch.from_numpy(r["e"]).to(dev)) for r in reqs]
     torch.cuda.synchronize()
+    # plain: the same requests solved one call each, in sequence on one
+    # stream; their algorithmic flops (from the solver's counters) price the
+    # served throughput against the FP64 vector peak
+    hp = mr3.Handle(0)
+    nmax = max(r["n"] for r in reqs)
+    Wp = {dt: torch.empty(nmax, dtype=dt, device=dev) for dt in (torch.float32, torch.float64)}
+    Zp = {dt: torch.empty(nmax * nmax, dtype=dt, device=dev) for dt in (torch.float32, torch.float64)}
+
+    def plain(i):
+        kind, il, iu = reqs[i]["range"]
+        d_, e_ = inputs[i]
+        nn = d_.numel()
+        fn = mr3.mr3_solve_f32 if d_.dtype == torch.float32 else mr3.mr3_solve_f64
+        rk = mr3.RANGE_INDEX if kind == "index" else mr3.RANGE_ALL
+        return fn(hp, nn, d_, e_, rk, 0.0, 0.0, il, iu, Wp[d_.dtype], Zp[d_.dtype], nn)
+
+    for i in range(8):
+        plain(i)
+    torch.cuda.synchronize()
+    n_plain = min(calib, n_req)
+    flops_req, pl_ms, pairs_plain = [], [], 0
+    t0 = time.perf_counter()
+    for i in range(n_plain):
+        ts = time.perf_counter()
+        pairs_plain += plain(i)
+        torch.cuda.synchronize()
+        pl_ms.append((time.perf_counter() - ts) * 1e3)
+        flops_req.append(alg_flops(hp.stats(), "f64" if inputs[i][0].dtype == torch.float32 else "dd"))
+    t_plain = time.perf_counter() - t0
+    hp.close()
+    del Wp, Zp
+    torch.cuda.empty_cache()
+    peak = FP64_VECTOR_PEAK_TFLOPS * 1e12
+    mean_flops = float(np.mean(flops_req))
     free, _ = torch.cuda.mem_get_info(0)
-    srv = mr3.Server(mr3.Handle(0), hbm_budget_bytes=free // 2, max_batch=256)
+    srv = mr3.Server(mr3.Handle(0), hbm_budget_bytes=free // 2, max_batch=256, max_inflight=slots)
 
     def submit(i):
         kind, il, iu = reqs[i]["range"]
@@ -219,17 +282,67 @@ def served_c5(mr3, n_req=2000, seed=0, window=64, calib=600):
         return {"offered_req_per_s": round(rate, 1), "achieved_req_per_s": round(n_req / span, 1),
                 "p50_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                "mean_batch": round(float(np.mean(bs)), 2)}
+                "mean_batch": round(float(np.mean(bs)), 2),
+                "roofline_frac": round(mean_flops * n_req / span / peak, 5)}
 
     rs = np.random.default_rng(seed + 101)
     out = {"workload": f"{n_req} requests, n log-uniform in [64, 8192], 50/50 fp32/fp64 I/O, "
                        "30% index range of ceil(0.1 n), 50/50 U(-1,1) or 1-2-1 + N(0,(1e-6)^2), "
                        f"seed {seed}; HBM budget 50% of free",
+           "slots": slots,
            "saturation_req_per_s": round(sat, 1),
            "saturation_eigenpairs_per_s": round(sum(r["m"] for r in done) / t_closed, 1),
+           "saturation_roofline_frac": round(mean_flops * sat / peak, 5),
+           "plain": {"req_per_s": round(n_plain / t_plain, 1),
+                     "eigenpairs_per_s": round(pairs_plain / t_plain, 1),
+                     "p50_ms": round(float(np.median(pl_ms)), 3),
+                     "p99_ms": round(float(np.percentile(pl_ms, 99)), 3),
+                     "roofline_frac": round(sum(flops_req) / t_plain / peak, 5),
+                     "sample": f"first {n_plain} requests, one mr3_solve_f32/f64 each in sequence"},
+           "mean_alg_flops_per_request": round(mean_flops, 1),
            "load_0.5": open_loop(0.5 * sat, rs),
            "load_0.8": open_loop(0.8 * sat, rs)}
     srv.close()
+    return out
+
+
+def single_legs(mr3, steps):
+    """C1: n = 512 FP32 (U(-1,1) and 1-2-1), one mr3_solve_f32 per call, p50/p99
+    latency; C2: glued Wilkinson n = 4096 FP64 (double-double), one
+    mr3_solve_f64 per call.  Inputs resident on the device."""
+    import torch
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    h = mr3.Handle(0)
+    for name, (d, e), reps in (("c1_uniform_n512_fp32", W.uniform(512, 0, np.float32), 200),
+                               ("c1_121_n512_fp32", W.toeplitz_121(512, np.float32), 200),
+                               ("c2_glued_wilkinson_n4096_fp64", W.glued_wilkinson(4096), max(steps, 10))):
+        n = d.size
+        dg, eg = torch.from_numpy(d).to(dev), torch.from_numpy(e).to(dev)
+        Wt = torch.empty(n, dtype=dg.dtype, device=dev)
+        Zt = torch.empty((n, n), dtype=dg.dtype, device=dev)
+        fn = mr3.mr3_solve_f32 if d.dtype == np.float32 else mr3.mr3_solve_f64
+        for _ in range(3):
+            fn(h, n, dg, eg, mr3.RANGE_ALL, 0.0, 0.0, 1, n, Wt, Zt, n, stream)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            ts = time.perf_counter()
+            fn(h, n, dg, eg, mr3.RANGE_ALL, 0.0, 0.0, 1, n, Wt, Zt, n, stream)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - ts) * 1e3)
+        st = h.stats()
+        med = float(np.median(ms))
+        flops = alg_flops(st, "f64" if d.dtype == np.float32 else "dd")
+        out[name] = {"eigenpairs_per_s": round(n / (med / 1e3), 1), "p50_ms": round(med, 3),
+                     "p99_ms": round(float(np.percentile(ms, 99)), 3), "calls": reps,
+                     "roofline_frac": round(flops / (med / 1e3) / (FP64_VECTOR_PEAK_TFLOPS * 1e12), 5),
+                     "tree": {"d_max": st["d_max"], "clusters": st["n_clusters"],
+                              "largest_cluster": st["largest_cluster"]}}
+    h.close()
     return out
 
 
@@ -463,6 +576,7 @@ def main():
         extra["subset_il1_iu2000"] = {"eigenpairs_per_s": round(2000 / (np.median(ms) / 1e3), 1),
                                       "p50_ms": round(float(np.median(ms)), 3)}
 
+    extra["single_problem_legs"] = single_legs(mr3, args.steps)
     if not args.no_batched:
         hb = mr3.Handle(0)
         extra["batched_vs_plain"] = batched_c3(mr3, hb, max(3, args.steps), 1)

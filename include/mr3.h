@@ -274,14 +274,21 @@ int mr3_check_f64(mr3_handle h, int64_t n, int64_t m, const double *d, const dou
 
 /* ---- Serving: continuous batching of independent requests ----
  *
- * A server owns a worker thread and a stream on the handle's device.
- * Requests queue in arrival order; whenever the device is free the worker
- * takes the oldest request and every later queued request of the same
- * precision that fits (at most max_batch requests whose estimated workspace,
- * mr3_request_bytes, sums to at most hbm_budget_bytes) and solves them as one
- * batch, exactly like mr3_solve_batched.  Requests of the other precision
- * wait for a later batch.  The paper's eigenpairs are independent (Section
- * 3.1), so a batch's results equal those of solving each request alone. */
+ * A server runs max_inflight worker slots on the handle's device, each with
+ * its own solver handle (the caller's for slot 0, copies of its parameters
+ * for the others) and stream.  Requests queue in arrival order; an idle slot
+ * takes the oldest request and the later queued requests of the same
+ * precision (at most max_batch) whose estimated work regions fit the largest
+ * free part of the server's memory, and solves them as one batch, exactly
+ * like mr3_solve_batched.  Requests that arrive while batches run are
+ * admitted as slots and memory free up, so batches overlap on the device, FP32
+ * and FP64 ones included.  The server allocates one device arena of
+ * hbm_budget_bytes at creation and runs every batch on a region of it sized by
+ * mr3_workspace_bytes_batched: device use never exceeds the budget and the
+ * solves allocate nothing.  A request whose region does not fit waits for a
+ * batch to end; with nothing else running it gets the whole arena.  The
+ * paper's eigenpairs are independent (Section 3.1), so a batch's results
+ * equal those of solving each request alone, to the gates. */
 typedef struct mr3_server_s *mr3_server;
 
 typedef struct {
@@ -293,6 +300,9 @@ typedef struct {
     void *W;              /* device output, room for every requested eigenvalue */
     void *Z;              /* device output, column-major ldz x m, or NULL */
     int64_t ldz;
+    void *stream;         /* hipStream_t on which d and e are produced (NULL: the
+                             null stream); the solve starts after the work
+                             queued there before mr3_server_submit */
 } mr3_request;
 
 typedef struct {
@@ -301,40 +311,53 @@ typedef struct {
     double submit_ms;   /* host steady clock (ms) at submit */
     double start_ms;    /* ... when its batch was launched */
     double done_ms;     /* ... when its batch had completed on the device */
-    int64_t batch_id;   /* batches are numbered from 0 */
+    int64_t batch_id;   /* batches are numbered from 0 in the order they form */
     int batch_size;     /* requests in that batch */
+    int slot;           /* worker slot that ran the batch */
 } mr3_result;
 
-/* Device workspace a request of order n with k wanted eigenpairs is budgeted
- * at (eigenvector tiles, representations, per-row arrays). */
+/* Work region (device bytes) a request of order n with k wanted eigenpairs is
+ * budgeted at: mr3_workspace_bytes of the request alone with the default
+ * parameters (k >= n: all pairs). */
 size_t mr3_request_bytes(int64_t n, int64_t k, int precision);
 
 /* Create a server that takes over handle h (the caller must not use h until
- * mr3_server_destroy returns).  Arguments: 1 s (output), 2 h, 3
- * hbm_budget_bytes (> 0), 4 max_batch (>= 1). */
+ * mr3_server_destroy returns), with two worker slots.  Arguments: 1 s
+ * (output), 2 h, 3 hbm_budget_bytes (> 0; allocated on the device here), 4
+ * max_batch (>= 1).  MR3_ERR_HIP if the arena or the slots' streams cannot be
+ * created. */
 int mr3_server_create(mr3_server *s, mr3_handle h, size_t hbm_budget_bytes, int max_batch);
 
+/* The same with 5 max_inflight worker slots (1 to 8). */
+int mr3_server_create_ex(mr3_server *s, mr3_handle h, size_t hbm_budget_bytes, int max_batch,
+                         int max_inflight);
+
 /* Host-side scheduler tests: batches go to fn(ctx, count, reqs, m) instead of
- * the device solver; fn returns a status and fills m[count]. */
+ * the device solver (called from max_inflight worker threads); fn returns a
+ * status and fills m[count].  No device memory is allocated; a request is
+ * budgeted at mr3_request_bytes. */
 typedef int (*mr3_executor_fn)(void *ctx, int64_t count, const mr3_request *reqs, int64_t *m);
 int mr3_server_create_with_executor(mr3_server *s, mr3_executor_fn fn, void *ctx,
-                                    size_t hbm_budget_bytes, int max_batch);
+                                    size_t hbm_budget_bytes, int max_batch, int max_inflight);
 
 /* Queue a request (copied; its device buffers must stay valid until the
  * request completes).  Returns a ticket.  Arguments: 1 s, 2 r, 3 ticket.
  * Errors: -2 r NULL or invalid (precision, n, pointers, range, ldz); -3 the
- * request alone exceeds the HBM budget; -4 ticket NULL. */
+ * request cannot run even alone in the whole budget (its minimum work
+ * region, mr3_workspace_min_bytes, exceeds it); -4 ticket NULL;
+ * MR3_ERR_HIP if the ordering event cannot be recorded on r->stream. */
 int mr3_server_submit(mr3_server s, const mr3_request *r, uint64_t *ticket);
 
 /* *done = 1 once the request's batch has completed, else 0; -2 unknown ticket. */
 int mr3_server_poll(mr3_server s, uint64_t ticket, int *done);
 
 /* Block until the request has completed, copy its result to *out (may be
- * NULL) and release the ticket.  Returns the request's status. */
+ * NULL) and release the ticket.  Returns the request's status; -2 for an
+ * unknown ticket or one another thread is already waiting for. */
 int mr3_server_wait(mr3_server s, uint64_t ticket, mr3_result *out);
 
-/* Finish every queued request, stop the worker and free the server (not the
- * handle, which the caller may use again). */
+/* Finish every queued request, stop the workers and free the server and its
+ * arena (not the handle, which the caller may use again). */
 int mr3_server_destroy(mr3_server s);
 
 /* Library version string. */

@@ -102,6 +102,7 @@ class mr3_request(ctypes.Structure):
         ("W", ctypes.c_void_p),
         ("Z", ctypes.c_void_p),
         ("ldz", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
     ]
 
 
@@ -114,6 +115,7 @@ class mr3_result(ctypes.Structure):
         ("done_ms", ctypes.c_double),
         ("batch_id", ctypes.c_int64),
         ("batch_size", ctypes.c_int),
+        ("slot", ctypes.c_int),
     ]
 
 
@@ -126,7 +128,8 @@ EXPORTS = [
     "mr3_solve_f32", "mr3_solve_f64", "mr3_solve_batched", "mr3_check_f64", "mr3_version",
     "mr3_workspace_bytes", "mr3_workspace_min_bytes", "mr3_workspace_bytes_batched",
     "mr3_solve_noalloc",
-    "mr3_request_bytes", "mr3_server_create", "mr3_server_create_with_executor",
+    "mr3_request_bytes", "mr3_server_create", "mr3_server_create_ex",
+    "mr3_server_create_with_executor",
     "mr3_server_submit", "mr3_server_poll", "mr3_server_wait", "mr3_server_destroy",
 ]
 
@@ -165,8 +168,9 @@ def load_library(path: str | None = None):
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
     lib.mr3_request_bytes.argtypes = [i64, i64, i32]
     lib.mr3_server_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_size_t, i32]
+    lib.mr3_server_create_ex.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_size_t, i32, i32]
     lib.mr3_server_create_with_executor.argtypes = [ctypes.POINTER(vp), EXECUTOR_FN, vp,
-                                                    ctypes.c_size_t, i32]
+                                                    ctypes.c_size_t, i32, i32]
     lib.mr3_server_submit.argtypes = [vp, ctypes.POINTER(mr3_request), ctypes.POINTER(ctypes.c_uint64)]
     lib.mr3_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
     lib.mr3_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(mr3_result)]
@@ -457,11 +461,20 @@ def mr3_server_create(h, hbm_budget_bytes: int, max_batch: int):
     return s
 
 
-def mr3_server_create_with_executor(fn, ctx, hbm_budget_bytes: int, max_batch: int):
+def mr3_server_create_ex(h, hbm_budget_bytes: int, max_batch: int, max_inflight: int):
+    s = ctypes.c_void_p()
+    _check("mr3_server_create_ex",
+           load_library().mr3_server_create_ex(ctypes.byref(s), h.ptr, hbm_budget_bytes, max_batch,
+                                               max_inflight))
+    return s
+
+
+def mr3_server_create_with_executor(fn, ctx, hbm_budget_bytes: int, max_batch: int,
+                                    max_inflight: int = 1):
     s = ctypes.c_void_p()
     _check("mr3_server_create_with_executor",
            load_library().mr3_server_create_with_executor(ctypes.byref(s), fn, ctx,
-                                                          hbm_budget_bytes, max_batch))
+                                                          hbm_budget_bytes, max_batch, max_inflight))
     return s
 
 
@@ -490,9 +503,10 @@ def mr3_server_destroy(s) -> None:
 
 
 def make_request(d, e, W, Z=None, range: str = "all", vl: float = 0.0, vu: float = 0.0,
-                 il: int = 1, iu: int | None = None) -> mr3_request:
+                 il: int = 1, iu: int | None = None, stream=None) -> mr3_request:
     """Request for tensors d, e (inputs) and W, Z (outputs, Z an (m, n)
-    row-major == n x m column-major buffer or None)."""
+    row-major == n x m column-major buffer or None); the solve is ordered
+    after the work queued on `stream` (default: torch's current stream)."""
     n = d.numel()
     r = mr3_request()
     r.precision = 32 if d.dtype == torch.float32 else 64
@@ -505,6 +519,8 @@ def make_request(d, e, W, Z=None, range: str = "all", vl: float = 0.0, vu: float
     r.W = W.data_ptr()
     r.Z = Z.data_ptr() if Z is not None else None
     r.ldz = max(n, 1)
+    if d.is_cuda:
+        r.stream = _stream_ptr(stream).value
     return r
 
 
@@ -514,13 +530,13 @@ class Server:
     alive by the server until wait() has returned for it."""
 
     def __init__(self, handle: Handle | None = None, hbm_budget_bytes: int | None = None,
-                 max_batch: int = 256):
+                 max_batch: int = 256, max_inflight: int = 2):
         self.handle = handle or Handle()
         if hbm_budget_bytes is None:
             free, _ = torch.cuda.mem_get_info(self.handle.device)
             hbm_budget_bytes = free // 2
         self.budget = int(hbm_budget_bytes)
-        self._s = mr3_server_create(self.handle, self.budget, max_batch)
+        self._s = mr3_server_create_ex(self.handle, self.budget, max_batch, max_inflight)
         self._keep = {}
 
     def submit(self, d, e, range: str = "all", vl: float = 0.0, vu: float = 0.0, il: int = 1,

@@ -1821,7 +1821,8 @@ static int batched_ptrs(mr3_handle h, int64_t count, const int64_t* n, const int
 template <class X, class Y>
 static int solve_ptrs_typed(mr3_handle h, int64_t count, const int64_t* n, const void* const* d,
                             const void* const* e, const mr3_range_desc* ranges, int64_t* m,
-                            void* const* W, void* const* Z, const int64_t* ldz, hipStream_t st) {
+                            void* const* W, void* const* Z, const int64_t* ldz, void* work,
+                            size_t work_bytes, hipStream_t st) {
     std::vector<const X*> dp((size_t)count), ep((size_t)count);
     std::vector<X*> wp((size_t)count), zp((size_t)count, nullptr);
     for (int64_t p = 0; p < count; ++p) {
@@ -1830,20 +1831,28 @@ static int solve_ptrs_typed(mr3_handle h, int64_t count, const int64_t* n, const
         wp[p] = static_cast<X*>(W[p]);
         if (Z) zp[p] = static_cast<X*>(Z[p]);
     }
-    return solve_impl<X, Y>(h, count, n, dp.data(), ep.data(), ranges, m, wp.data(),
-                            Z ? zp.data() : nullptr, ldz, st, nullptr, 0);
+    const int rc = solve_impl<X, Y>(h, count, n, dp.data(), ep.data(), ranges, m, wp.data(),
+                                    Z ? zp.data() : nullptr, ldz, st, work, work_bytes);
+    return finish_on_region(h, rc, work, st);
 }
 
 int mr3_solve_ptrs(mr3_handle h, int precision, int64_t count, const int64_t* n,
                    const void* const* d, const void* const* e, const mr3_range_desc* ranges,
-                   int64_t* m, void* const* W, void* const* Z, const int64_t* ldz, void* stream) {
+                   int64_t* m, void* const* W, void* const* Z, const int64_t* ldz, void* work,
+                   size_t work_bytes, void* stream) {
     if (!h) return -1;
     if (count <= 0) return MR3_OK;
     if (precision == 32)
-        return solve_ptrs_typed<float, double>(h, count, n, d, e, ranges, m, W, Z, ldz,
-                                               (hipStream_t)stream);
-    return solve_ptrs_typed<double, dd>(h, count, n, d, e, ranges, m, W, Z, ldz,
+        return solve_ptrs_typed<float, double>(h, count, n, d, e, ranges, m, W, Z, ldz, work,
+                                               work_bytes, (hipStream_t)stream);
+    return solve_ptrs_typed<double, dd>(h, count, n, d, e, ranges, m, W, Z, ldz, work, work_bytes,
                                         (hipStream_t)stream);
+}
+
+void mr3_handle_copy_params(mr3_handle dst, mr3_handle src) {
+    if (!dst || !src) return;
+    dst->user = src->user;
+    dst->have_user = src->have_user;
 }
 
 int mr3_handle_device(mr3_handle h) { return h ? h->device : -1; }

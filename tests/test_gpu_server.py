@@ -88,3 +88,35 @@ def test_server_mixed_stream(mr3):
     print(f"batches {len(batches)}; alone vs mix: worst 1-|cos| {worst_c:.3g} n eps, "
           f"groups {ngroups}, worst sin / bound {worst_g:.3g}", flush=True)
     assert len(batches) < len(reqs)  # requests were batched
+
+
+def test_server_overlaps_a_long_batch(mr3):
+    """Continuous batching on the device: while a long FP64 solve runs on one
+    slot, short FP32 requests submitted after it are admitted by the other
+    slot and complete first; every result meets the oracle gates."""
+    srv = mr3.Server(mr3.Handle(0), hbm_budget_bytes=16 << 30, max_batch=8, max_inflight=2)
+    dl, el, _ = W.prescribed_spectrum(12000, 3)
+    t_long = srv.submit(_dev(dl), _dev(el))
+    import time
+
+    time.sleep(0.002)
+    shorts = [W.uniform(200 + 10 * i, 40 + i, np.float32) for i in range(4)]
+    t_short = [srv.submit(_dev(d), _dev(e)) for d, e in shorts]
+    res_short = [srv.wait(t) for t in t_short]
+    res_long, Wl, Zl = srv.wait(t_long)
+    srv.close()
+    first_short = min(r[0]["done_ms"] for r in res_short)
+    print(f"long: {res_long['start_ms']:.1f}..{res_long['done_ms']:.1f} slot {res_long['slot']}; "
+          f"shorts done at {[round(r[0]['done_ms'], 1) for r in res_short]} slots "
+          f"{[r[0]['slot'] for r in res_short]}", flush=True)
+    assert first_short < res_long["done_ms"]
+    assert any(r[0]["slot"] != res_long["slot"] for r in res_short)
+    for (d, e), (res, Wt, Zt) in zip(shorts, res_short):
+        n = d.size
+        d64, e64 = d.astype(np.float64), e.astype(np.float64)
+        hi, lo = oracle.eigvals(d64, e64)
+        tn = M.tnorm(d64, e64)
+        assert np.max(np.abs(Wt.double().cpu().numpy() - (hi + lo))) <= 4 * n * 2.0 ** -24 * tn
+    (off, diag), R = mr3.check(_dev(dl), _dev(el), Wl, Zl)
+    n = dl.size
+    assert max(off, diag) <= 10 * n * 2.0 ** -53 and R <= 10 * n * 2.0 ** -53

@@ -53,8 +53,8 @@ def req(rid, n=100, precision=64, rng=None):
     return r
 
 
-def make_server(ex, budget=1 << 30, max_batch=8):
-    return mr3.mr3_server_create_with_executor(ex.cb, None, budget, max_batch)
+def make_server(ex, budget=1 << 30, max_batch=8, max_inflight=1):
+    return mr3.mr3_server_create_with_executor(ex.cb, None, budget, max_batch, max_inflight)
 
 
 def test_batches_group_precision_and_keep_arrival_order():
@@ -95,7 +95,7 @@ def test_budget_limits_batches_and_rejects_oversized():
     one = mr3.mr3_request_bytes(1000, 1000, 64)
     s = make_server(ex, budget=int(2.5 * one), max_batch=64)
     with pytest.raises(mr3.MR3Error) as ei:
-        mr3.mr3_server_submit(s, req(99, n=2000))
+        mr3.mr3_server_submit(s, req(99, n=4000))
     assert ei.value.code == -3
     tickets = [mr3.mr3_server_submit(s, req(1, n=1000))]
     time.sleep(0.05)
@@ -177,3 +177,88 @@ def test_concurrent_submitters_and_drain_on_destroy():
     mr3.mr3_server_destroy(s)
     ids = [i for b, _ in ex.batches for i in b]
     assert len(ids) == 110 and len(set(ids)) == 110
+
+
+class SlowExecutor:
+    """Each batch takes `delay(ids)` seconds; records when it ran, which
+    requests it held, and the largest sum of request estimates in flight at
+    once."""
+
+    def __init__(self, delay):
+        self.delay = delay
+        self.lock = threading.Lock()
+        self.inflight_bytes = 0
+        self.max_inflight_bytes = 0
+        self.max_concurrent = 0
+        self.concurrent = 0
+        self.cb = mr3.EXECUTOR_FN(self._run)
+
+    def _run(self, ctx, count, reqs, m):
+        ids, est = [], 0
+        for i in range(count):
+            r = reqs[i]
+            ids.append(int(r.W))
+            k = r.range.iu - r.range.il + 1 if r.range.range == mr3.RANGE_INDEX else r.n
+            est += mr3.mr3_request_bytes(r.n, k, r.precision)
+            m[i] = k
+        with self.lock:
+            self.inflight_bytes += est
+            self.concurrent += 1
+            self.max_inflight_bytes = max(self.max_inflight_bytes, self.inflight_bytes)
+            self.max_concurrent = max(self.max_concurrent, self.concurrent)
+        time.sleep(self.delay(ids))
+        with self.lock:
+            self.inflight_bytes -= est
+            self.concurrent -= 1
+        return mr3.MR3_OK
+
+
+def test_later_request_overtakes_a_long_batch():
+    """With two slots, a short request submitted while a long batch runs is
+    admitted by the free slot and completes first (continuous batching)."""
+    ex = SlowExecutor(lambda ids: 0.5 if 1 in ids else 0.01)
+    s = make_server(ex, max_batch=8, max_inflight=2)
+    t_long = mr3.mr3_server_submit(s, req(1, n=4000, precision=64))
+    time.sleep(0.05)
+    t_short = mr3.mr3_server_submit(s, req(2, n=100, precision=32))
+    short = mr3.mr3_server_wait(s, t_short)
+    assert not mr3.mr3_server_poll(s, t_long)
+    long_ = mr3.mr3_server_wait(s, t_long)
+    mr3.mr3_server_destroy(s)
+    assert short["done_ms"] < long_["done_ms"]
+    assert short["slot"] != long_["slot"]
+    assert short["start_ms"] < long_["done_ms"]  # overlapped in time
+
+
+def test_memory_in_flight_stays_within_the_budget():
+    """Batches on several slots never hold more than the budget together, and
+    every request runs."""
+    one = mr3.mr3_request_bytes(1000, 1000, 64)
+    budget = int(3.5 * one)
+    ex = SlowExecutor(lambda ids: 0.02)
+    s = make_server(ex, budget=budget, max_batch=2, max_inflight=4)
+    tickets = [mr3.mr3_server_submit(s, req(i, n=1000)) for i in range(1, 25)]
+    res = [mr3.mr3_server_wait(s, t) for t in tickets]
+    mr3.mr3_server_destroy(s)
+    assert all(r["status"] == 0 for r in res)
+    assert ex.max_inflight_bytes <= budget
+    assert ex.max_concurrent >= 2  # several batches did run at once
+    assert len({r["slot"] for r in res}) >= 2
+
+
+def test_a_ticket_has_one_waiter():
+    hold = threading.Event()
+    ex = FakeExecutor(hold=hold)
+    s = make_server(ex)
+    t = mr3.mr3_server_submit(s, req(1))
+    first = {}
+    th = threading.Thread(target=lambda: first.update(mr3.mr3_server_wait(s, t)))
+    th.start()
+    time.sleep(0.05)
+    with pytest.raises(mr3.MR3Error) as ei:  # already claimed by the first waiter
+        mr3.mr3_server_wait(s, t)
+    assert ei.value.code == -2
+    hold.set()
+    th.join()
+    assert first["status"] == 0
+    mr3.mr3_server_destroy(s)
