@@ -348,8 +348,10 @@ def single_legs(mr3, steps):
 
 def gaptol_study(mr3):
     """Clustering rho (largest cluster / n), tree depth and solve time against
-    gaptol, with and without splitting by absolute gaps (gaptol_abs = gaptol),
-    on the synthetic stand-ins of the paper's matrix types."""
+    gaptol, with and without splitting by absolute gaps (gaptol_abs = gaptol)
+    and with and without the refinement of cluster ends in y before the shift,
+    on the synthetic stand-ins of the paper's matrix types.  FP64 gaptols
+    below 20 n eps run with their brackets refined in y."""
     import torch
     import workloads as W
 
@@ -367,19 +369,19 @@ def gaptol_study(mr3):
     for name, d, e in cases:
         n = d.size
         prec = 32 if d.dtype == np.float32 else 64
-        tols = (1e-3, 1e-4, 1e-5, 1e-6) if prec == 32 else (1e-3, 1e-5, 1e-8, 1e-10, 1e-12)
+        tols = (1e-3, 1e-4, 1e-5, 1e-6, 1e-7) if prec == 32 else (1e-3, 1e-5, 1e-8, 1e-10, 1e-12, 1e-13)
         dg, eg = torch.from_numpy(d).to(dev), torch.from_numpy(e).to(dev)
         for g in tols:
-            for ab in (0.0, g):
+            for ab, ends in ((0.0, 0), (g, 0), (0.0, 1)):
                 h = mr3.Handle(0)
-                h.set_params(precision=prec, gaptol=g, gaptol_abs=ab)
+                h.set_params(precision=prec, gaptol=g, gaptol_abs=ab, refine_ends=ends)
                 try:
                     mr3.solve(dg, eg, handle=h)
                 except mr3.MR3Error as err:
                     if err.code != mr3.MR3_ERR_GAPTOL:
                         raise
-                    row = {"matrix": name, "gaptol": g, "abs_split": ab > 0,
-                           "rejected": "gaptol below the binary64 eigenvalue accuracy 20 n eps"}
+                    row = {"matrix": name, "gaptol": g, "abs_split": ab > 0, "refine_ends": ends,
+                           "rejected": "gaptol below min(1e-3, eps_y sqrt(n) / eps_x)"}
                     rows.append(row)
                     print(json.dumps(row), flush=True)
                     h.close()
@@ -392,9 +394,10 @@ def gaptol_study(mr3):
                     torch.cuda.synchronize()
                     ts.append((time.perf_counter() - t0) * 1e3)
                 st = h.stats()
-                row = {"matrix": name, "gaptol": g, "abs_split": ab > 0,
+                row = {"matrix": name, "gaptol": g, "abs_split": ab > 0, "refine_ends": ends,
                        "rho": max(st["largest_cluster"], 1) / n, "d_max": st["d_max"],
-                       "clusters": st["n_clusters"], "ms": round(float(np.median(ts)), 3)}
+                       "clusters": st["n_clusters"], "y_refined": st["n_y_refined"],
+                       "best_candidate": st["n_best_candidate"], "ms": round(float(np.median(ts)), 3)}
                 if prec == 64:
                     (off, diag), res = mr3.check(dg, eg, Wg, Zg, handle=h)
                     row["orth"] = max(off, diag)

@@ -77,10 +77,12 @@ extern "C" {
 #define MR3_ERR_NUMERIC 1
 #define MR3_ERR_HIP 2
 #define MR3_ERR_NO_DEVICE 3
-/* FP64 path: gaptol below the accuracy of eigenvalues approximated on the
- * binary64 copy of a representation, (k_rr + k_bi) n eps_x with
- * k_rr = k_bi = 10 (Sec. 3.2, "Arithmetic used to approximate eigenvalues")
- * for the longest block of the call */
+/* gaptol below the lower end of the interval eq. (gaptolinterval) allows,
+ * min{1e-3, eps_y sqrt(n) / eps_x} (n of the longest block with wanted
+ * eigenvalues), or below 400 * 2^-53, under which the refinement target
+ * 1e-2 gaptol comes within 4 ulp of the binary64 interval endpoints.  (A
+ * gaptol below the accuracy of eigenvalues approximated on binary64 copies,
+ * (k_rr + k_bi) n eps_x, is not refused: those brackets are refined in y.) */
 #define MR3_ERR_GAPTOL 4
 
 typedef enum { MR3_RANGE_ALL = 0, MR3_RANGE_VALUE = 1, MR3_RANGE_INDEX = 2 } mr3_range;
@@ -130,6 +132,13 @@ typedef struct {
                               use bisection).  The dqds values are checked with
                               Sturm counts and refined by bisection like any
                               other bracket [MR3_INITIAL_BISECTION] */
+    int refine_ends;       /* 1: before a cluster's shift is chosen, refine its
+                              two extreme eigenvalues by bisection in y to
+                              binary64 resolution (Sec. 3.2, footnote on the
+                              refinement of extreme eigenvalues prior to
+                              selecting shifts); candidate shifts may then come
+                              as close to the cluster as those brackets allow,
+                              and their inertia follows from them [0] */
 } mr3_params;
 
 #define MR3_INITIAL_BISECTION 0
@@ -165,6 +174,10 @@ typedef struct {
     int n_singleton_first_levels; /* tree levels whose singleton work was
                                      issued before their cluster work (the
                                      throughput-bound order of large batches) */
+    int64_t n_y_refined;      /* eigenvalue brackets refined by bisection in y
+                                 because the binary64 copy of their node does
+                                 not resolve gaptol (Sec. 3.2, "Arithmetic
+                                 used to approximate eigenvalues") */
 } mr3_stats;
 
 /* stage indices of mr3_stats.stage_ms */

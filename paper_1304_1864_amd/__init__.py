@@ -57,6 +57,7 @@ class mr3_params(ctypes.Structure):
         ("points_per_lane", ctypes.c_int),
         ("gaptol_abs", ctypes.c_double),
         ("initial", ctypes.c_int),
+        ("refine_ends", ctypes.c_int),
     ]
 
 
@@ -79,6 +80,7 @@ class mr3_stats(ctypes.Structure):
         ("dqds_transforms", ctypes.c_int64),
         ("n_sliced_roots", ctypes.c_int64),
         ("n_singleton_first_levels", ctypes.c_int),
+        ("n_y_refined", ctypes.c_int64),
     ]
 
 

@@ -1498,7 +1498,9 @@ k_slice_small(const int* __restrict__ blist, const Block* __restrict__ blocks,
 // results of x-bit eigenvalue computations may be verified or refined in y).
 // Two lanes per slot count the y representation at lo and hi; a bracket that
 // does not hold for the y representation is widened until it does and then
-// refined by bisection in y to relative width rtol.
+// refined by bisection in y to relative width rtol.  With refine_all every
+// bracket is refined that way (the binary64 copy does not resolve gaptol:
+// (k_rr + k_bi) n eps_x > gaptol).
 // ---------------------------------------------------------------------------
 // Sturm count in y at x for threads with on == true; the node's rows stream
 // through an LDS window filled by the 64 threads of the workgroup (all call).
@@ -1570,7 +1572,7 @@ __global__ void __launch_bounds__(64)
 k_verify(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list, Slot* __restrict__ slots,
          const Node* __restrict__ nodes, const Block* __restrict__ blocks,
          const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld, double rtol,
-         unsigned long long* __restrict__ repaired) {
+         unsigned long long* __restrict__ repaired, int refine_all) {
     __shared__ Y wd[2][STAGE_ROWS], wl[2][STAGE_ROWS];
     const BisWG w = wgs[blockIdx.x];
     const int lane = threadIdx.x;
@@ -1607,8 +1609,8 @@ k_verify(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list, Slot* 
             fix = !ok;
         }
     }
-    // refine repaired brackets by bisection in y (two points per step)
-    bool busy = bad;
+    // refine repaired brackets (or all) by bisection in y (two points per step)
+    bool busy = bad || (refine_all && active);
     for (int it = 0; it < 200; ++it) {
         if (busy) {
             const double wdt = hi - lo;
@@ -1627,10 +1629,10 @@ k_verify(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list, Slot* 
             else lo = x2;
         }
     }
-    if (active && !side && bad) {
+    if (active && !side && (bad || refine_all)) {
         slots[s].lo = lo;
         slots[s].hi = hi;
-        atomicAdd(repaired, 1ull);
+        if (bad) atomicAdd(repaired, 1ull);
     }
 }
 
@@ -2501,7 +2503,11 @@ k_child_select(ChildJob* __restrict__ jobs, int64_t njobs, const Slot* __restric
         __syncthreads();
     }
     const int64_t want = left ? sp.idx - 1 : sq.idx;
-    valid = valid && (negc == want) && isfinite(gmax);
+    // the inertia of the child: from the binary64 copy's count, or, when the
+    // cluster ends were refined in y and the outside gap is known, from their
+    // brackets (tau lies outside the end bracket and within half the gap to
+    // the outside neighbour, whose bracket holds for the representation in y)
+    valid = valid && ((prm.refine_ends && gapo >= 0.0) || negc == want) && isfinite(gmax);
     // element growth bound relaxed as the mixed precision analysis allows:
     // k_elg <= max(k_elg, eps_x / (eps_y sqrt(n))) (Sec. 3.2, "Requirements on
     // the representations")

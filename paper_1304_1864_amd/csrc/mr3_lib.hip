@@ -589,6 +589,7 @@ static Params effective(const mr3_handle_s* h, int precision) {
     p.lanes_per_eig = h->have_user ? u.lanes_per_eig : 0;
     p.points_per_lane = h->have_user ? u.points_per_lane : 0;
     p.initial = h->have_user ? u.initial : MR3_INITIAL_BISECTION;
+    p.refine_ends = h->have_user ? u.refine_ends : 0;
     p.force_rqi_fallback = h->have_user ? u.force_rqi_fallback : 0;
     p.force_best_candidate = h->have_user ? u.force_best_candidate : 0;
     p.seed = (h->have_user && u.seed) ? u.seed : d.seed;
@@ -913,17 +914,29 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     stats.n_blocks = NB;
     for (int64_t p = 0; p < count; ++p) { m_out[p] = m_p[p]; stats.n_eigenpairs += m_p[p]; }
     if (K == 0) { h->stats = stats; h->clean_exit = true; return MR3_OK; }
-    if (is_dd) {
-        // eigenvalues are approximated on binary64 copies: their accuracy
-        // (k_rr + k_bi) n eps_x must stay below gaptol
+    // Eigenvalues are approximated on binary64 copies, accurate to
+    // (k_rr + k_bi) n eps_x relative (k_rr = k_bi = 10, Sec. 3.2 "Arithmetic
+    // used to approximate eigenvalues").  On the double-double path a block
+    // whose copy does not resolve gaptol has its brackets refined in y.
+    // gaptol itself may go down to eps_y sqrt(n) / eps_x (eq. gaptolinterval);
+    // brackets are held in binary64, so the refinement target 1e-2 gaptol also
+    // stays above 4 ulp: smaller values are refused.
+    std::vector<char> yref((size_t)NB, 0);
+    {
         int64_t nmax = 0;
-        for (const Block& bk : blocks)
-            if (bk.nslot > 0) nmax = std::max(nmax, bk.n);
-        if (prm.gaptol < 20.0 * (double)nmax * 1.1102230246251565e-16) {
+        for (int64_t b = 0; b < NB; ++b)
+            if (blocks[b].nslot > 0) {
+                nmax = std::max(nmax, blocks[b].n);
+                yref[b] = is_dd && prm.gaptol < 20.0 * (double)blocks[b].n * prm.eps_x;
+            }
+        const double floor_ = std::max((double)YEps<Y>::v / prm.eps_x * std::sqrt((double)nmax),
+                                       400.0 * 1.1102230246251565e-16);
+        if (prm.gaptol < std::min(1e-3, floor_)) {
             h->clean_exit = true;
             return MR3_ERR_GAPTOL;
         }
     }
+    const double rtol_y = std::max(prm.bisect_rel, 4.0 * 1.1102230246251565e-16);
     if (fixed) {
         // the rest of the plan, now that blocks and slots are known
         Shape sh;
@@ -1125,6 +1138,30 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         std::fprintf(stderr, "[mr3] root bisection: %lld intervals (%lld staged, lanes %d), passes max %.0f total %.0f\n",
                      (long long)K, (long long)k_staged, Ls.L, wk[6], wk[7]);
         HIPCHK(hipMemsetAsync(work + 6, 0, 2 * sizeof(double), st));
+    }
+    // brackets of roots whose binary64 copy does not resolve gaptol: checked
+    // and refined in y (one workgroup per 32 slots of a root)
+    {
+        std::vector<int64_t> vlist;
+        std::vector<BisWG> vwg;
+        for (int64_t b = 0; b < NB; ++b) {
+            if (!yref[b]) continue;
+            const int64_t m = blocks[b].nslot;
+            for (int64_t o = 0; o < m; o += 32)
+                vwg.push_back(BisWG{(int64_t)vlist.size() + o, (int)std::min<int64_t>(32, m - o), (int)b});
+            for (int64_t q = 0; q < m; ++q) vlist.push_back(blocks[b].slot0 + q);
+        }
+        if (!vwg.empty()) {
+            stats.n_y_refined += (int64_t)vlist.size();
+            HIPCHK(upload(B[B_VLIST], vlist, st));
+            HIPCHK(upload(B[B_VWG], vwg, st));
+            prof.begin(MR3_STAGE_VERIFY, st);
+            hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)vwg.size()), dim3(64), 0, st,
+                               B[B_VWG].as<BisWG>(), B[B_VLIST].as<int64_t>(), dslots, dnodes, dblocks,
+                               B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(), rtol_y, counters + 3, 1);
+            prof.end(st);
+            HIPCHK(hipGetLastError());
+        }
     }
     // ---- output columns of split problems: order by eigenvalue ----
     bool any_multi = false;
@@ -1460,11 +1497,13 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         std::vector<ClusterRec> crec;
         HIPCHK(download(crec, B[B_CREC].p, (size_t)C, st));
         std::vector<int64_t> cl_n((size_t)C);  // rows of each cluster's block
+        std::vector<char> cl_y((size_t)C);     // ... and whether it is refined in y
         {
             std::vector<Node> allnodes;
             HIPCHK(download(allnodes, dnodes, (size_t)n_nodes, st));
             for (int64_t c = 0; c < C; ++c) {
                 cl_n[c] = blocks[allnodes[crec[c].parent].block].n;
+                cl_y[c] = yref[allnodes[crec[c].parent].block];
                 stats.largest_cluster = std::max<int64_t>(stats.largest_cluster, crec[c].last - crec[c].head + 1);
             }
         }
@@ -1519,6 +1558,24 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             HIPCHK(B[B_TMPC].ensure(sizeof(Y) * new_rows));
             HIPCHK(B[B_TMPE].ensure(sizeof(int) * new_rows));
             HIPCHK(upload(B[B_JOBS], jobs, st));
+            if (prm.refine_ends) {
+                // both extreme eigenvalues of each cluster, refined in y on
+                // the parent (one workgroup of two slots per cluster)
+                std::vector<int64_t> vlist;
+                std::vector<BisWG> vwg;
+                for (int64_t c = 0; c < CG; ++c) {
+                    vwg.push_back(BisWG{(int64_t)vlist.size(), 2, jobs[c].parent});
+                    vlist.push_back(jobs[c].head);
+                    vlist.push_back(jobs[c].last);
+                }
+                HIPCHK(upload(B[B_VLIST], vlist, st));
+                HIPCHK(upload(B[B_VWG], vwg, st));
+                prof.begin(MR3_STAGE_VERIFY, st);
+                hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)CG), dim3(64), 0, st, B[B_VWG].as<BisWG>(),
+                                   B[B_VLIST].as<int64_t>(), dslots, dnodes, dblocks, B[B_REPD].rows<Y>(),
+                                   B[B_REPL].rows<Y>(), 4.0 * 1.1102230246251565e-16, counters + 3, 1);
+                prof.end(st);
+            }
             prof.begin(MR3_STAGE_CHILD, st);
             hipLaunchKernelGGL(k_child_select, dim3((unsigned)CG), dim3(64), 0, st,
                                B[B_JOBS].as<ChildJob>(), CG, dslots, dnodes, dblocks,
@@ -1603,24 +1660,41 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                 // copy brackets its eigenvalues after the widening.  A child
                 // accepted under the relaxed bound or as least-growth
                 // candidate may not be: check its brackets with counts in y.
-                // one workgroup per 32 slots of one child node
+                // Children of blocks whose binary64 copies do not resolve
+                // gaptol have every bracket refined in y.  One workgroup per
+                // 32 slots of one child node; the list holds the refined
+                // children first.
                 std::vector<int64_t> vlist;
                 std::vector<BisWG> vwg;
-                for (int64_t c = 0; c < CG; ++c) {
-                    if (done_jobs[c].strict) continue;
-                    const int64_t m = jobs[c].last - jobs[c].head + 1;
-                    for (int64_t o = 0; o < m; o += 32)
-                        vwg.push_back(BisWG{(int64_t)vlist.size() + o, (int)std::min<int64_t>(32, m - o),
-                                            jobs[c].child});
-                    for (int64_t sidx = jobs[c].head; sidx <= jobs[c].last; ++sidx) vlist.push_back(sidx);
-                }
+                int64_t nwg_all = 0;
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int64_t c = 0; c < CG; ++c) {
+                        const bool all = cl_y[g0 + c];
+                        if (pass == 0 ? !all : (all || done_jobs[c].strict)) continue;
+                        const int64_t m = jobs[c].last - jobs[c].head + 1;
+                        for (int64_t o = 0; o < m; o += 32)
+                            vwg.push_back(BisWG{(int64_t)vlist.size() + o, (int)std::min<int64_t>(32, m - o),
+                                                jobs[c].child});
+                        for (int64_t sidx = jobs[c].head; sidx <= jobs[c].last; ++sidx) vlist.push_back(sidx);
+                        if (pass == 0) {
+                            nwg_all = (int64_t)vwg.size();
+                            stats.n_y_refined += m;
+                        }
+                    }
                 if (!vwg.empty()) {
                     HIPCHK(upload(B[B_VLIST], vlist, st));
                     HIPCHK(upload(B[B_VWG], vwg, st));
-                    hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)vwg.size()), dim3(64), 0, st,
-                                       B[B_VWG].as<BisWG>(), B[B_VLIST].as<int64_t>(), dslots, dnodes,
-                                       dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
-                                       prm.bisect_rel, counters + 3);
+                    if (nwg_all > 0)
+                        hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)nwg_all), dim3(64), 0, st,
+                                           B[B_VWG].as<BisWG>(), B[B_VLIST].as<int64_t>(), dslots, dnodes,
+                                           dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(), rtol_y,
+                                           counters + 3, 1);
+                    if ((int64_t)vwg.size() > nwg_all)
+                        hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)((int64_t)vwg.size() - nwg_all)),
+                                           dim3(64), 0, st, B[B_VWG].as<BisWG>() + nwg_all,
+                                           B[B_VLIST].as<int64_t>(), dslots, dnodes, dblocks,
+                                           B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(), prm.bisect_rel,
+                                           counters + 3, 0);
                 }
             }
             prof.end(st);

@@ -120,6 +120,7 @@ struct Params {
     int force_rqi_fallback;
     int force_best_candidate;
     int profile;
+    int refine_ends;      // cluster ends refined in y before the shift
     long long debug_slot;  // development trace (MR3_DEBUG_SLOT), -1 = off
     unsigned long long seed;
 };

@@ -352,19 +352,50 @@ def test_metamorphic_relations(mr3):
 def test_gaptol_settings(mr3):
     """Non-default gaptol: a smaller value (more parallelism) still meets the
     gates; a value below what binary64 eigenvalue approximation resolves at
-    this size, 20 n eps (Sec. 3.2), is rejected; absolute-gap splitting is
-    accepted and keeps the gates."""
+    this size, 20 n eps_x (Sec. 3.2), has its brackets refined in y and meets
+    every gate against the oracle, vectors included; a value below the lower
+    end of eq. (gaptolinterval) is refused; absolute-gap splitting is
+    accepted and keeps the gates; an FP32 gaptol of 1e-6."""
     d, e, _ = W.prescribed_spectrum(2000, 2)
     h = mr3.Handle(0)
     h.set_params(precision=64, gaptol=1e-11, gaptol_abs=1e-11)
     run_case(mr3, d, e, handle=h, check_angles=False)
+    assert h.stats()["n_y_refined"] == 0
     h.set_params(precision=64, gaptol=1e-13)
+    run_case(mr3, d, e, handle=h)
+    st = h.stats()
+    assert st["n_y_refined"] >= d.size
+    print("gaptol 1e-13: y-refined brackets", st["n_y_refined"], "clusters", st["n_clusters"],
+          "d_max", st["d_max"], flush=True)
+    run_case(mr3, d, e, rng="index", il=300, iu=420, handle=h)
+    h.set_params(precision=64, gaptol=1e-14)
     with pytest.raises(mr3.MR3Error) as ei:
         mr3.solve(_dev(d), _dev(e), handle=h)
     assert ei.value.code == mr3.MR3_ERR_GAPTOL
     h.set_params(precision=32, gaptol=1e-6)
     d32, e32 = W.uniform(700, 8, np.float32)
     run_case(mr3, d32, e32, handle=h)
+
+
+def test_refine_cluster_ends_in_y(mr3):
+    """The option that refines each cluster's extreme eigenvalues in y before
+    its shift is chosen (the footnote of Sec. 3.2): every gate against the
+    oracle on matrices with clusters, shallow and deep trees."""
+    h = mr3.Handle(0)
+    for name, (d, e), g in (("glued Wilkinson n=336", W.glued_wilkinson(336), 1e-10),
+                            ("glued Wilkinson n=336, gaptol 1e-3", W.glued_wilkinson(336), 1e-3),
+                            ("prescribed n=3000", W.prescribed_spectrum(3000, 5)[:2], 1e-10),
+                            ("prescribed n=3000, gaptol 1e-5", W.prescribed_spectrum(3000, 5)[:2], 1e-5)):
+        h.set_params(precision=64, refine_ends=1, gaptol=g)
+        print("refine ends:", name, flush=True)
+        run_case(mr3, d, e, handle=h)
+        st = h.stats()
+        print("   clusters", st["n_clusters"], "d_max", st["d_max"], "best", st["n_best_candidate"],
+              flush=True)
+    h.set_params(precision=32, refine_ends=1)
+    d, e = W.toeplitz_121_noisy(3000, 4, 1e-6, np.float32)
+    run_case(mr3, d, e, handle=h)
+    assert h.stats()["n_clusters"] > 0
 
 
 def test_dqds_initial_values(mr3):
@@ -409,6 +440,7 @@ def test_dqds_initial_values(mr3):
     run_case(mr3, d, e, rng="index", il=20, iu=80, handle=h)
     assert h.stats()["n_dqds_roots"] == 0
     d, e = W.uniform(mr3.MR3_DQDS_MAX_N + 1, 6, np.float32)
+    h.set_params(precision=32, initial=mr3.MR3_INITIAL_DQDS)
     mr3.solve(_dev(d), _dev(e), vectors=False, handle=h)
     assert h.stats()["n_dqds_roots"] == 0
     with pytest.raises(mr3.MR3Error):
