@@ -139,6 +139,10 @@ typedef struct {
                               selecting shifts); candidate shifts may then come
                               as close to the cluster as those brackets allow,
                               and their inertia follows from them [0] */
+    int force_resort;      /* fault injection (tests): reverse every problem's
+                              eigenvalues and eigenvectors on the device before
+                              the ascending-order check, so that the host-side
+                              reordering runs */
 } mr3_params;
 
 #define MR3_INITIAL_BISECTION 0
@@ -178,6 +182,8 @@ typedef struct {
                                  because the binary64 copy of their node does
                                  not resolve gaptol (Sec. 3.2, "Arithmetic
                                  used to approximate eigenvalues") */
+    int64_t n_resorted;       /* problems whose eigenpairs came out of order
+                                 and were reordered on the host */
 } mr3_stats;
 
 /* stage indices of mr3_stats.stage_ms */

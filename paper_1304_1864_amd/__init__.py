@@ -58,6 +58,7 @@ class mr3_params(ctypes.Structure):
         ("gaptol_abs", ctypes.c_double),
         ("initial", ctypes.c_int),
         ("refine_ends", ctypes.c_int),
+        ("force_resort", ctypes.c_int),
     ]
 
 
@@ -81,6 +82,7 @@ class mr3_stats(ctypes.Structure):
         ("n_sliced_roots", ctypes.c_int64),
         ("n_singleton_first_levels", ctypes.c_int),
         ("n_y_refined", ctypes.c_int64),
+        ("n_resorted", ctypes.c_int64),
     ]
 
 

@@ -615,9 +615,16 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
     // takes
     double delta = fmax(fmax(2.0 * (s_hi - s_lo), 8.0 * (double)n * 1.1102230246251565e-16),
                         prm.root_gap * spd);
+    // The serial lane stores each continuant q_i as computed and, after rows
+    // 4k+3, the exponent em by which q and q_{i-1} were then scaled down;
+    // the pivots d_i = q_i / q_{i-1} (times 2^em across a rescaling, exact)
+    // are formed afterwards by all threads, so no division is on the serial
+    // lane's instruction stream.  q_i goes to d64, em to lld64 (both rewritten
+    // below).
+    double* qst = d64 + blk.row0;
+    double* est = lld64 + blk.row0;
     for (int attempt = 0; attempt < 40; ++attempt) {
         const double mu = right ? s_hi + delta : s_lo - delta;
-        int ok = 1;
         double qm = 1.0, q = 1.0;
         wT[0][t] = load_row(t);
         __syncthreads();
@@ -628,16 +635,16 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
             if (t == 0) {
                 auto row = [&](const double2& r, int i) {
                     const double qn = __fma_rn(r.x - mu, q, -r.y * qm);
-                    const double di = qn / q;
-                    d64[blk.row0 + c0 + i] = di;
-                    ok &= right ? (di < 0.0) : (di > 0.0);
+                    qst[c0 + i] = qn;
                     qm = q;
                     q = qn;
+                    int em = 0;
                     if ((i & 3) == 3) {
-                        const int em = max(dexp(q), dexp(qm));
+                        em = max(dexp(q), dexp(qm));
                         q = __builtin_ldexp(q, -em);
                         qm = __builtin_ldexp(qm, -em);
                     }
+                    est[c0 + i] = (double)em;
                 };
                 int i = 0;
                 for (; i + 8 <= cnt; i += 8) {
@@ -652,9 +659,18 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
             wT[cur ^ 1][t] = nx;
             __syncthreads();
         }
+        // pivots, and the definiteness check: every d_i of one sign
+        int bad = 0;
+        for (int64_t i = t; i < n; i += blockDim.x) {
+            const double di = (i == 0) ? qst[0] : __builtin_ldexp(qst[i] / qst[i - 1], (int)est[i - 1]);
+            bad |= right ? !(di < 0.0) : !(di > 0.0);
+            rep_lld[blk.row0 + i] = y_from(di, Y());  // staged (rewritten below)
+        }
+        const int anybad = __syncthreads_or(bad);
+        for (int64_t i = t; i < n; i += blockDim.x) d64[blk.row0 + i] = hi_of(rep_lld[blk.row0 + i]);
         if (t == 0) {
             s_mu = mu;
-            s_ok = ok;
+            s_ok = !anybad;
         }
         __syncthreads();
         if (s_ok) break;
@@ -737,7 +753,8 @@ __device__ __forceinline__ void normalise(Y& m, int& e) {
 template <class Y>
 __global__ void __launch_bounds__(256)
 k_pq(const Block* __restrict__ blocks, const Y* __restrict__ rep_e, Y* __restrict__ P,
-     int* __restrict__ Pe, Y* __restrict__ Q, int* __restrict__ Qe) {
+     int* __restrict__ Pe, Y* __restrict__ Q, int* __restrict__ Qe, double* __restrict__ P64,
+     double* __restrict__ Q64) {
     __shared__ Y sm[256];
     __shared__ int se[256];
     const Block blk = blocks[blockIdx.x];
@@ -775,6 +792,7 @@ k_pq(const Block* __restrict__ blocks, const Y* __restrict__ rep_e, Y* __restric
     for (int64_t j = c0; j < c1; ++j) {
         P[blk.row0 + j] = m;
         Pe[blk.row0 + j] = ex;
+        if (P64) P64[blk.row0 + j] = hi_of(m);  // binary64 mantissa, same exponent
         if (j + 1 < n) { m = mul(m, neg(div(one, e[j]))); normalise(m, ex); }
     }
     __syncthreads();
@@ -806,6 +824,7 @@ k_pq(const Block* __restrict__ blocks, const Y* __restrict__ rep_e, Y* __restric
         if (j + 1 < n) { m = mul(m, neg(div(one, e[j]))); normalise(m, ex); }
         Q[blk.row0 + j] = m;
         Qe[blk.row0 + j] = ex;
+        if (Q64) Q64[blk.row0 + j] = hi_of(m);
     }
 }
 
@@ -2042,7 +2061,8 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
       const Slot* __restrict__ slots, const Node* __restrict__ nodes,
       const Block* __restrict__ blocks, const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld,
       const double* __restrict__ d64, const double* __restrict__ lld64, const Y* __restrict__ P,
-      const int* __restrict__ Pe, const Y* __restrict__ Q, const int* __restrict__ Qe, Params prm,
+      const int* __restrict__ Pe, const Y* __restrict__ Q, const int* __restrict__ Qe,
+      const double* __restrict__ P64, const double* __restrict__ Q64, Params prm,
       double eps_y, RqiResult* __restrict__ res, unsigned long long* __restrict__ counters,
       double* __restrict__ work) {
     __shared__ SweepWin<Y> wins[NW];
@@ -2100,10 +2120,35 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
     int64_t r = rmin;
     if (r < 0 || r >= n) r = n / 2;
     wave_sync();
+    // ---- double-double path: one Rayleigh-quotient step in binary64 on the
+    // copy at the midpoint and twist r gives a better starting shift than the
+    // midpoint, whose error (the bracket width) costs pairs of small relative
+    // gap several double-double sweeps; a result outside the bracket is not
+    // used.  (The copy's window space is the double-double window's.) ----
+    double lam0 = tau0;
+    if (P64 != nullptr) {
+        SweepWin<double>& w64 = *reinterpret_cast<SweepWin<double>*>(&win);
+        const int64_t st0 = active ? (top ? r + 1 : n - r) : 0;
+        Half<double> h0 = sweep_staged<double>(top, D64, LL64, P64 + brow, Pe + brow, Q64 + brow,
+                                               Qe + brow, n, r, tau0, tile, false, st0, w64);
+        const double spo = __shfl_xor(h0.sp, 1, 64);
+        const double zro = __shfl_xor(h0.zr, 1, 64);
+        const double sso = __shfl_xor(h0.ss, 1, 64);
+        if (active) {
+            const double s_r = top ? h0.sp : spo, p_r = top ? spo : h0.sp;
+            const double zrT = top ? h0.zr : zro, zrB = top ? zro : h0.zr;
+            const double ssT = top ? h0.ss : sso, ssB = top ? sso : h0.ss;
+            const double nrm2 = 1.0 + (r > 0 ? ssT / (zrT * zrT) : 0.0) +
+                                (r < n - 1 ? ssB / (zrB * zrB) : 0.0);
+            const double l1 = tau0 + ((s_r + p_r) + tau0) / nrm2;
+            if (isfinite(l1) && l1 > lo && l1 < hi) lam0 = l1;
+        }
+        wave_sync();
+    }
     // ---- RQI in y at a fixed twist ----
     const double sqn = sqrt((double)(n > 0 ? n : 1));
     const double tol = prm.k_rs * gap * prm.eps_x * sqn;
-    Y lam = y_from(tau0, Y());
+    Y lam = y_from(lam0, Y());
     bool done = !active;
     bool fallback = prm.force_rqi_fallback != 0;
     int iters = 0;
@@ -2309,7 +2354,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
         res[idx] = o;
         atomicAdd(&counters[0], (unsigned long long)iters);
         atomicAdd(&work[1], (double)iters * (double)(n + 1));
-        atomicAdd(&work[2], (double)n);
+        atomicAdd(&work[2], (double)n * (P64 != nullptr ? 2.0 : 1.0));  // pre-pass (+ binary64 step)
         if (fallback) atomicAdd(&counters[1], 1ull);
         if (o.status == 2) atomicAdd(&counters[2], 1ull);
     }

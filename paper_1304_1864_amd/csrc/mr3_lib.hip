@@ -196,6 +196,27 @@ __global__ void k_check_sorted(const ProbDesc* __restrict__ probs, const int64_t
     if (b) atomicOr(&bad[p], 1);
 }
 
+// fault injection: reverse the order of problem blockIdx.x's eigenpairs
+template <class X>
+__global__ void k_reverse_outputs(const ProbDesc* __restrict__ probs, const int64_t* __restrict__ m) {
+    const ProbDesc pd = probs[blockIdx.x];
+    const int64_t mp = m[blockIdx.x];
+    X* w = reinterpret_cast<X*>(pd.wout);
+    X* z = reinterpret_cast<X*>(pd.zout);
+    for (int64_t i = threadIdx.x; i < mp / 2; i += blockDim.x) {
+        const X t = w[i];
+        w[i] = w[mp - 1 - i];
+        w[mp - 1 - i] = t;
+    }
+    if (!z) return;
+    for (int64_t i = 0; i < mp / 2; ++i)
+        for (int64_t k = threadIdx.x; k < pd.n; k += blockDim.x) {
+            const X t = z[i * pd.ldz + k];
+            z[i * pd.ldz + k] = z[(mp - 1 - i) * pd.ldz + k];
+            z[(mp - 1 - i) * pd.ldz + k] = t;
+        }
+}
+
 template <class X>
 __global__ void k_zero_cols(X* __restrict__ Z, int64_t ldz, int64_t n, int64_t m) {
     const int64_t total = n * m;
@@ -300,7 +321,7 @@ enum BufId {
     B_PROBS, B_PINFO, B_TD, B_TE, B_BINFO, B_BLOCKS, B_SLOTS, B_NODES, B_REPD, B_REPL, B_REPE,
     B_D64, B_L64, B_P, B_PE, B_Q, B_QE, B_LIST, B_LIST2, B_CNT, B_TILEOFF, B_TILES, B_RES,
     B_FLAGS, B_CUBTMP, B_JOBS, B_TMPC, B_TMPE, B_M, B_BAD, B_COUNTERS,
-    B_BOFF, B_CREC, B_CHECK, B_NSLOT, B_SLOT0, B_GKEY, B_GVAL, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SLB, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_DQDS, B_DQB, B_NBUF
+    B_BOFF, B_CREC, B_CHECK, B_NSLOT, B_SLOT0, B_GKEY, B_GVAL, B_BWG, B_VLIST, B_VWG, B_SLICE, B_SLB, B_SEG, B_CMARK, B_CID, B_CHUNK0, B_CHUNK1, B_SLIST0, B_SLIST1, B_TILEOFF1, B_TILES1, B_RES1, B_DQDS, B_DQB, B_P64, B_Q64, B_NBUF
 };
 
 // singleton work of tree level d runs on the handle's side stream with the
@@ -387,6 +408,7 @@ static void solve_sizes(const Shape& s, size_t* sz) {
     sz[B_REPE] = ys * std::max<int64_t>(s.R, 1);
     sz[B_P] = sz[B_Q] = ys * (s.R + G2);
     sz[B_PE] = sz[B_QE] = sizeof(int) * (s.R + G2);
+    sz[B_P64] = sz[B_Q64] = s.dd ? sizeof(double) * (s.R + G2) : 0;  // binary64 mantissas of P, Q
     sz[B_LIST] = sizeof(int64_t) * KN;  // level nodes, identity and bisection lists
     sz[B_LIST2] = sizeof(int64_t) * K;
     sz[B_CNT] = sizeof(int64_t) * 4;
@@ -590,6 +612,7 @@ static Params effective(const mr3_handle_s* h, int precision) {
     p.points_per_lane = h->have_user ? u.points_per_lane : 0;
     p.initial = h->have_user ? u.initial : MR3_INITIAL_BISECTION;
     p.refine_ends = h->have_user ? u.refine_ends : 0;
+    p.force_resort = h->have_user ? u.force_resort : 0;
     p.force_rqi_fallback = h->have_user ? u.force_rqi_fallback : 0;
     p.force_best_candidate = h->have_user ? u.force_best_candidate : 0;
     p.seed = (h->have_user && u.seed) ? u.seed : d.seed;
@@ -985,6 +1008,12 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(B[B_Q].ensure(sizeof(Y) * (R + 2 * GUARD)));
     HIPCHK(B[B_PE].ensure(sizeof(int) * (R + 2 * GUARD)));
     HIPCHK(B[B_QE].ensure(sizeof(int) * (R + 2 * GUARD)));
+    if (is_dd) {
+        HIPCHK(B[B_P64].ensure(sizeof(double) * (R + 2 * GUARD)));
+        HIPCHK(B[B_Q64].ensure(sizeof(double) * (R + 2 * GUARD)));
+    }
+    double* P64 = is_dd ? B[B_P64].rows<double>() : nullptr;
+    double* Q64 = is_dd ? B[B_Q64].rows<double>() : nullptr;
     HIPCHK(B[B_COUNTERS].ensure(COUNTER_BYTES));
     HIPCHK(hipMemsetAsync(B[B_COUNTERS].p, 0, COUNTER_BYTES, st));
     unsigned long long* counters = B[B_COUNTERS].as<unsigned long long>();
@@ -1014,7 +1043,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                        B[B_REPE].as<Y>(), B[B_D64].rows<double>(), B[B_L64].rows<double>(), dnodes,
                        dslots, status);
     hipLaunchKernelGGL(k_pq<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_REPE].as<Y>(),
-                       B[B_P].rows<Y>(), B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>());
+                       B[B_P].rows<Y>(), B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>(),
+                       P64, Q64);
     prof.end(st);
     HIPCHK(hipGetLastError());
     // ---- a3: bisection of every slot on its root ----
@@ -1378,8 +1408,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                                    STI.rows<double>(32), dslots,
                                    dnodes, dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
                                    B[B_D64].rows<double>(), B[B_L64].rows<double>(), B[B_P].rows<Y>(),
-                                   B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>(), prm,
-                                   (double)YEps<Y>::v, SRE.as<RqiResult>(), counters, work);
+                                   B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>(), P64, Q64,
+                                   prm, (double)YEps<Y>::v, SRE.as<RqiResult>(), counters, work);
                 prof.end(side);
                 prof.begin(MR3_STAGE_ZOUT, side);
                 // rows of a chunk are split over zsplit workgroups (blocks of
@@ -1743,6 +1773,9 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(upload(B[B_M], mv, st));
     HIPCHK(B[B_BAD].ensure(sizeof(int) * count));
     HIPCHK(hipMemsetAsync(B[B_BAD].p, 0, sizeof(int) * count, st));
+    if (prm.force_resort)
+        hipLaunchKernelGGL(k_reverse_outputs<X>, dim3((unsigned)count), dim3(256), 0, st,
+                           B[B_PROBS].as<ProbDesc>(), B[B_M].as<int64_t>());
     hipLaunchKernelGGL(k_check_sorted<X>, dim3((unsigned)count), dim3(256), 0, st,
                        B[B_PROBS].as<ProbDesc>(), B[B_M].as<int64_t>(), B[B_BAD].as<int>(),
                        (int)count);
@@ -1750,6 +1783,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(download(bad, B[B_BAD].p, (size_t)count, st));
     for (int64_t p = 0; p < count; ++p) {
         if (!bad[p]) continue;
+        h->stats.n_resorted++;
         if (debug_on()) std::fprintf(stderr, "[mr3] problem %lld: eigenvalues reordered on the host\n", (long long)p);
         // rare: eigenvalues equal to working accuracy came out in the wrong
         // order; sort the pairs on the host

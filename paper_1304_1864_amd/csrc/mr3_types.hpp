@@ -121,6 +121,7 @@ struct Params {
     int force_best_candidate;
     int profile;
     int refine_ends;      // cluster ends refined in y before the shift
+    int force_resort;     // tests: outputs reversed before the order check
     long long debug_slot;  // development trace (MR3_DEBUG_SLOT), -1 = off
     unsigned long long seed;
 };

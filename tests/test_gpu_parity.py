@@ -328,6 +328,37 @@ def test_fault_injection_paths(mr3):
     assert h.stats()["n_fallbacks"] == 300
 
 
+def test_host_reordering_fallback(mr3):
+    """The host-side reordering (taken when eigenvalues come out of ascending
+    order) forced by reversing every problem's outputs on the device: the
+    results equal those of the normal path bit for bit (the permutation of
+    columns is exact), single solves of both precisions, a split problem,
+    and a batch."""
+    h = mr3.Handle(0)
+    ref = mr3.Handle(0)
+    d_split, e_split = W.uniform(90, 4, np.float64)
+    e_split[29] = 0.0
+    for d, e in (W.uniform(300, 3, np.float32), W.uniform(200, 4, np.float64), (d_split, e_split)):
+        prec = 32 if d.dtype == np.float32 else 64
+        h.set_params(precision=prec, force_resort=1)
+        ref.set_params(precision=prec)
+        W0, Z0 = mr3.solve(_dev(d), _dev(e), handle=ref)
+        W1, Z1 = mr3.solve(_dev(d), _dev(e), handle=h)
+        assert h.stats()["n_resorted"] == 1
+        assert torch.equal(W0, W1) and torch.equal(Z0, Z1)
+        W2, _ = mr3.solve(_dev(d), _dev(e), range="index", il=5, iu=40, vectors=False, handle=h)
+        W3, _ = mr3.solve(_dev(d), _dev(e), range="index", il=5, iu=40, vectors=False, handle=ref)
+        assert torch.equal(W2, W3)
+    probs = W.batch_normal(12, 32, 200, seed=17, dtype=np.float64)
+    h.set_params(precision=64, force_resort=1)
+    ds, es = [_dev(p[0]) for p in probs], [_dev(p[1]) for p in probs]
+    Wa, Za = mr3.solve_batched(ds, es, handle=h)
+    assert h.stats()["n_resorted"] == 12
+    Wb, Zb = mr3.solve_batched(ds, es, handle=ref)
+    for i in range(12):
+        assert torch.equal(Wa[i], Wb[i]) and torch.equal(Za[i], Zb[i]), i
+
+
 def test_metamorphic_relations(mr3):
     """Exact relations of the method: scaling T by a power of two scales the
     eigenvalues exactly and leaves the vectors unchanged (the input is
