@@ -470,6 +470,7 @@ def main():
     ap.add_argument("--no-subset", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-single", action="store_true", help="skip the C1 and C2 single-problem legs")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (calibrates "
                          "hardware byte counters against a known traffic) and exit")
@@ -579,7 +580,8 @@ def main():
         extra["subset_il1_iu2000"] = {"eigenpairs_per_s": round(2000 / (np.median(ms) / 1e3), 1),
                                       "p50_ms": round(float(np.median(ms)), 3)}
 
-    extra["single_problem_legs"] = single_legs(mr3, args.steps)
+    if not args.no_single:
+        extra["single_problem_legs"] = single_legs(mr3, args.steps)
     if not args.no_batched:
         hb = mr3.Handle(0)
         extra["batched_vs_plain"] = batched_c3(mr3, hb, max(3, args.steps), 1)

@@ -716,13 +716,16 @@ static bool no_stage() {
 }
 
 // slot list for a bisection launch: the slots of staged nodes first (with one
-// workgroup per G of them), then the rest
+// workgroup per G of them), then the rest.  Every child node is staged: its
+// eigenvalues share its rows, which a node of at most RESIDENT_ROWS rows keeps
+// in LDS for all passes (the per-lane kernel, reading rows from memory per
+// lane, took 7.5 ms for the clusters of a 4096-problem batch).
 struct BisectPlan {
     std::vector<int64_t> list;
     std::vector<BisWG> wgs;
     int64_t n_staged = 0;
     void add(int node, int64_t n, int64_t first, int64_t count, int G, std::vector<int64_t>& rest) {
-        if (n >= STAGE_MIN_N && !no_stage()) {
+        if (n >= 1 && !no_stage()) {
             for (int64_t o = 0; o < count; o += G)
                 wgs.push_back(BisWG{(int64_t)list.size() + o, (int)std::min<int64_t>(G, count - o), node});
             for (int64_t i = 0; i < count; ++i) list.push_back(first + i);
@@ -1633,7 +1636,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             for (int64_t c = 0; c < CG; ++c) {
                 const int64_t m = jobs[c].last - jobs[c].head + 1;
                 KC += m;
-                if (cl_n[g0 + c] >= STAGE_MIN_N && !no_stage()) KCs += m;
+                if (!no_stage()) KCs += m;
             }
             BisectShape L = pick_shape(KC - KCs, prm.lanes_per_eig, prm.points_per_lane);
             // one wave per workgroup: the clusters of a level are many and small
@@ -1642,7 +1645,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             {
                 std::vector<int64_t> sizes;
                 for (int64_t c = 0; c < CG; ++c)
-                    if (cl_n[g0 + c] >= STAGE_MIN_N && !no_stage()) sizes.push_back(jobs[c].last - jobs[c].head + 1);
+                    if (!no_stage()) sizes.push_back(jobs[c].last - jobs[c].head + 1);
                 Lcs = pick_shape_groups(sizes, prm.lanes_per_eig);
             }
             BisectPlan cplan;
