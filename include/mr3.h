@@ -107,8 +107,11 @@ typedef struct {
     double k_rs;           /* RQI stopping constant: ||r|| <= k_rs*gap*eps_x*sqrt(n) [1] */
     int max_depth;         /* cap on the depth of the representation tree [6] */
     int rqi_max_iter;      /* RQI iterations before the bisection fallback [10] */
-    int lanes_per_eig;     /* bisection lanes per eigenvalue, power of two <= 64;
-                              0 = chosen from the problem size */
+    int lanes_per_eig;     /* bisection lanes per eigenvalue, 1..64: the
+                              LDS-staged multisection takes the largest of 1,
+                              2, 3, 4, 6, 8, 12, 16, 24, 32, 64 not above it,
+                              the per-lane kernel the largest power of two;
+                              0 = from the tuning table, else the size */
     unsigned long long seed; /* seed of the counter-based perturbation generator [0x5eed] */
     /* fault injection (tests): force the bisection fallback of RQI for every
      * eigenvector; reject every candidate shift so the least-growth candidate
@@ -184,6 +187,13 @@ typedef struct {
                                  used to approximate eigenvalues") */
     int64_t n_resorted;       /* problems whose eigenpairs came out of order
                                  and were reordered on the host */
+    /* the largest multisection launch of each kind in the last solve, indexed
+     * by MR3_TUNE_ROOT / MR3_TUNE_CHILD: eigenvalues it bisected, the mean row
+     * count of their nodes, and the lanes per eigenvalue it took (the key and
+     * the result of a look-up in the tuning table below; 0 when none ran) */
+    int64_t bisect_count[2];
+    int64_t bisect_rows[2];
+    int bisect_lanes[2];
 } mr3_stats;
 
 /* stage indices of mr3_stats.stage_ms */
@@ -207,6 +217,45 @@ int mr3_default_params(mr3_params *p, int precision);
 int mr3_set_params(mr3_handle h, const mr3_params *p);
 /* Diagnostics of the last solve. */
 int mr3_get_stats(mr3_handle h, mr3_stats *s);
+
+/* Multisection shapes measured on the device (the autotuner's table).  The
+ * eigenvalue intervals of a level are refined by multisection (Sec. 2,
+ * Alg. 1: bisection to classify and to start RQI) with L lanes per
+ * eigenvalue: each pass counts at L points and gains log2(L + 1) bits, so a
+ * larger L costs more Sturm counts but fewer dependent passes.  A launch over
+ * `count` eigenvalues whose nodes have on average `rows` rows takes `lanes`
+ * from the first entry whose stage and precision match and whose ranges hold
+ * count and rows; with no such entry a size rule is used, and a nonzero
+ * mr3_params.lanes_per_eig overrides both.  A handle starts with the table
+ * the library was built with, which the package's tuner writes from timed
+ * runs of this kind on gfx950. */
+#define MR3_TUNE_ROOT 0  /* root eigenvalues (stage MR3_STAGE_BISECT) */
+#define MR3_TUNE_CHILD 1 /* members of clusters in their child nodes (MR3_STAGE_CBISECT) */
+typedef struct {
+    int stage;                  /* MR3_TUNE_ROOT or MR3_TUNE_CHILD */
+    int precision;              /* 32 or 64: I/O precision of the solve */
+    int64_t count_lo, count_hi; /* eigenvalues in the launch: count_lo <= count < count_hi */
+    int64_t rows_lo, rows_hi;   /* mean rows of their nodes: rows_lo <= rows < rows_hi */
+    int lanes;                  /* lanes per eigenvalue: 1, 2, 3, 4, 6, 8, 12, 16, 24, 32 or 64 */
+    int reserved;               /* 0 */
+} mr3_tune_entry;
+
+/* Replace the handle's table by a copy of t[0 .. count): count 0 leaves no
+ * table (size rules only); t NULL with count < 0 restores the built-in table.
+ * Returns -1 for a null handle, -2 (table unchanged) for an entry with an
+ * unknown stage or precision, an empty range or a lanes value not listed
+ * above. */
+int mr3_set_tuning(mr3_handle h, const mr3_tune_entry *t, int count);
+
+/* Copy up to `cap` entries of the handle's table to t (t may be NULL when cap
+ * is 0).  Returns the number of entries in the table, -1 for a null handle. */
+int mr3_get_tuning(mr3_handle h, mr3_tune_entry *t, int cap);
+
+/* Lanes per eigenvalue that a multisection launch of this stage, precision,
+ * eigenvalue count and mean node rows takes from the handle's override or
+ * table; 0 when neither applies (the size rule decides).  -1 for a null
+ * handle, -2 for an unknown stage or precision. */
+int mr3_bisect_lanes(mr3_handle h, int stage, int precision, int64_t count, int64_t rows);
 
 /* Single problem, FP32 input/output with binary64 internal arithmetic
  * (Section 4.1, single/double).  Arguments (1-based positions, used in the

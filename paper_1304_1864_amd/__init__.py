@@ -83,6 +83,26 @@ class mr3_stats(ctypes.Structure):
         ("n_singleton_first_levels", ctypes.c_int),
         ("n_y_refined", ctypes.c_int64),
         ("n_resorted", ctypes.c_int64),
+        ("bisect_count", ctypes.c_int64 * 2),
+        ("bisect_rows", ctypes.c_int64 * 2),
+        ("bisect_lanes", ctypes.c_int * 2),
+    ]
+
+
+MR3_TUNE_ROOT, MR3_TUNE_CHILD = 0, 1
+LANE_CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64)
+
+
+class mr3_tune_entry(ctypes.Structure):
+    _fields_ = [
+        ("stage", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("count_lo", ctypes.c_int64),
+        ("count_hi", ctypes.c_int64),
+        ("rows_lo", ctypes.c_int64),
+        ("rows_hi", ctypes.c_int64),
+        ("lanes", ctypes.c_int),
+        ("reserved", ctypes.c_int),
     ]
 
 
@@ -131,7 +151,7 @@ EXPORTS = [
     "mr3_create", "mr3_destroy", "mr3_default_params", "mr3_set_params", "mr3_get_stats",
     "mr3_solve_f32", "mr3_solve_f64", "mr3_solve_batched", "mr3_check_f64", "mr3_version",
     "mr3_workspace_bytes", "mr3_workspace_min_bytes", "mr3_workspace_bytes_batched",
-    "mr3_solve_noalloc",
+    "mr3_solve_noalloc", "mr3_set_tuning", "mr3_get_tuning", "mr3_bisect_lanes",
     "mr3_request_bytes", "mr3_server_create", "mr3_server_create_ex",
     "mr3_server_create_with_executor",
     "mr3_server_submit", "mr3_server_poll", "mr3_server_wait", "mr3_server_destroy",
@@ -168,6 +188,9 @@ def load_library(path: str | None = None):
     lib.mr3_workspace_bytes_batched.argtypes = [vp, i64, i32, pi64, ctypes.POINTER(mr3_range_desc)]
     lib.mr3_solve_noalloc.argtypes = [vp, i32, i64, vp, vp, i32, dbl, dbl, i64, i64, pi64, vp, vp,
                                       i64, vp]
+    lib.mr3_set_tuning.argtypes = [vp, ctypes.POINTER(mr3_tune_entry), i32]
+    lib.mr3_get_tuning.argtypes = [vp, ctypes.POINTER(mr3_tune_entry), i32]
+    lib.mr3_bisect_lanes.argtypes = [vp, i32, i32, i64, i64]
     lib.mr3_check_f64.argtypes = [vp, i64, i64, vp, vp, vp, vp, i64,
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
     lib.mr3_request_bytes.argtypes = [i64, i64, i32]
@@ -240,6 +263,35 @@ class Handle:
 
     def reset_params(self):
         _check("mr3_set_params", load_library().mr3_set_params(self._h, None))
+
+    def set_tuning(self, entries=None):
+        """Replace the handle's multisection tuning table: a list of
+        (stage, precision, count_lo, count_hi, rows_lo, rows_hi, lanes)
+        tuples ([] = no table), or None for the built-in table."""
+        lib = load_library()
+        if entries is None:
+            _check("mr3_set_tuning", lib.mr3_set_tuning(self._h, None, -1))
+            return
+        arr = (mr3_tune_entry * max(len(entries), 1))()
+        for i, t in enumerate(entries):
+            arr[i] = mr3_tune_entry(*t, 0)
+        _check("mr3_set_tuning", lib.mr3_set_tuning(self._h, arr, len(entries)))
+
+    def tuning(self) -> list:
+        """The handle's tuning table as a list of 7-tuples."""
+        lib = load_library()
+        nt = lib.mr3_get_tuning(self._h, None, 0)
+        arr = (mr3_tune_entry * max(nt, 1))()
+        lib.mr3_get_tuning(self._h, arr, nt)
+        return [(t.stage, t.precision, t.count_lo, t.count_hi, t.rows_lo, t.rows_hi, t.lanes)
+                for t in arr[:nt]]
+
+    def bisect_lanes(self, stage: int, precision: int, count: int, rows: int) -> int:
+        """Lanes per eigenvalue from the override or the table (0: size rule)."""
+        r = load_library().mr3_bisect_lanes(self._h, stage, precision, count, rows)
+        if r < 0:
+            raise MR3Error("mr3_bisect_lanes", r)
+        return r
 
     def stats(self) -> dict:
         s = mr3_stats()

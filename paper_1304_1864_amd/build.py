@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmr3.so")
 SOURCES = ["mr3_lib.hip", "mr3_check.hip", "mr3_server.cpp"]
-HEADERS = ["dd.hpp", "mr3_types.hpp", "mr3_kernels.hip", "mr3_internal.h"]
+HEADERS = ["dd.hpp", "mr3_types.hpp", "mr3_kernels.hip", "mr3_internal.h", "tuning_gfx950.inc"]
 
 FLAGS = [
     "--offload-arch=gfx950",

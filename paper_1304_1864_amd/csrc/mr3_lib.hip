@@ -509,6 +509,7 @@ struct mr3_handle_s {
     mr3::Staging stage;      // pinned host staging
     bool clean_exit = true;  // the last solve synchronised its stream
     void* scratch = nullptr; // device address of this device's no-allocation scratch
+    std::vector<mr3_tune_entry> tune;  // measured multisection shapes
 };
 
 namespace mr3 {
@@ -754,17 +755,64 @@ static BisectShape pick_shape(int64_t count, int user_lanes, int user_points) {
     return sh;
 }
 
+// lanes per eigenvalue of the LDS-staged kernels (its lane groups need not
+// divide the wave)
+static const int kLaneCands[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64};
+static bool lane_cand(int L) {
+    for (int c : kLaneCands)
+        if (c == L) return true;
+    return false;
+}
+static int lanes_at_most(int L) {
+    int r = 1;
+    for (int c : kLaneCands)
+        if (c <= L) r = c;
+    return r;
+}
+
+// the table the library is built with: entries written by the package's
+// tuner from timed solves on gfx950 (stage, precision, eigenvalue count range,
+// mean node rows range, lanes)
+static const mr3_tune_entry kBuiltinTuning[] = {
+#define MR3_TUNE(st, pr, c0, c1, r0, r1, l) {st, pr, c0, c1, r0, r1, l, 0},
+#include "tuning_gfx950.inc"
+#undef MR3_TUNE
+    {-1, 0, 0, 0, 0, 0, 0, 0}};
+
+static std::vector<mr3_tune_entry> builtin_tuning() {
+    std::vector<mr3_tune_entry> v;
+    for (const mr3_tune_entry& t : kBuiltinTuning)
+        if (t.stage >= 0) v.push_back(t);
+    return v;
+}
+
+static bool tune_entry_ok(const mr3_tune_entry& t) {
+    return (t.stage == MR3_TUNE_ROOT || t.stage == MR3_TUNE_CHILD) &&
+           (t.precision == 32 || t.precision == 64) && t.count_lo < t.count_hi &&
+           t.rows_lo < t.rows_hi && lane_cand(t.lanes);
+}
+
+// lanes of a staged launch from the override or the table; 0: the size rule
+static int table_lanes(const std::vector<mr3_tune_entry>& tab, const Params& prm, int stage,
+                       int precision, int64_t count, int64_t rows) {
+    if (prm.lanes_per_eig > 0) return lanes_at_most(prm.lanes_per_eig);
+    for (const mr3_tune_entry& t : tab)
+        if (t.stage == stage && t.precision == precision && count >= t.count_lo &&
+            count < t.count_hi && rows >= t.rows_lo && rows < t.rows_hi)
+            return t.lanes;
+    return 0;
+}
+
 // shape of the LDS-staged kernel for many small node-pure groups (the
 // members of the clusters of a level): a pass costs about the same while the
 // waves fit one per SIMD (1024) and proportionally more beyond, and gains
 // log2(L + 1) bits, so L minimises max(1, waves(L) / 1024) / log2(L + 1), with
 // waves(L) = sum over groups of ceil(size / (64 / L)) for one-wave workgroups
 static BisectShape pick_shape_groups(const std::vector<int64_t>& sizes, int user_lanes) {
-    static const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64};
+    if (user_lanes > 0) return BisectShape{lanes_at_most(user_lanes), 1};
     BisectShape best{64, 1};
     double best_cost = 1e300;
-    for (int L : cand) {
-        if (user_lanes > 0 && L > user_lanes) break;
+    for (int L : kLaneCands) {
         const int64_t gw = 64 / L;
         double waves = 0.0;
         for (int64_t m : sizes) waves += (double)((m + gw - 1) / gw);
@@ -782,13 +830,9 @@ static BisectShape pick_shape_groups(const std::vector<int64_t>& sizes, int user
 // (1024 SIMDs), which spreads the waves evenly and keeps the redundant
 // multisection work low
 static BisectShape pick_shape_staged(int64_t count, int user_lanes) {
-    static const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 64};
+    if (user_lanes > 0) return BisectShape{lanes_at_most(user_lanes), 1};
     BisectShape sh{64, 1};
-    for (int L : cand) {
-        if (user_lanes > 0) {
-            if (L <= user_lanes) sh.L = L;
-            continue;
-        }
+    for (int L : kLaneCands) {
         const int64_t gw = 64 / L;
         if ((count + gw - 1) / gw >= 900) {
             sh.L = L;
@@ -1074,7 +1118,20 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             }
     stats.n_dqds_roots = (int64_t)dq_blocks.size();
     BisectShape L = pick_shape(K - k_staged, prm.lanes_per_eig, prm.points_per_lane);
-    const BisectShape Ls = pick_shape_staged(k_staged, prm.lanes_per_eig);
+    // staged shape: the tuning table keyed by the eigenvalue count and the
+    // mean rows of their roots, else the size rule
+    BisectShape Ls = pick_shape_staged(k_staged, 0);
+    if (k_staged > 0) {
+        double rs = 0.0;
+        for (int64_t b = 0; b < NB; ++b)
+            if (blocks[b].n >= root_stage_n && !no_stage()) rs += (double)blocks[b].nslot * (double)blocks[b].n;
+        const int64_t rows = (int64_t)(rs / (double)k_staged + 0.5);
+        const int tl = table_lanes(h->tune, prm, MR3_TUNE_ROOT, precision, k_staged, rows);
+        if (tl > 0) Ls = BisectShape{tl, 1};
+        stats.bisect_count[MR3_TUNE_ROOT] = k_staged;
+        stats.bisect_rows[MR3_TUNE_ROOT] = rows;
+        stats.bisect_lanes[MR3_TUNE_ROOT] = Ls.L;
+    }
     std::vector<BisWG> rwgs;
     int64_t k_small = 0;
     // one-wave workgroups when every root is resident in LDS (each then loads
@@ -1644,9 +1701,23 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             BisectShape Lcs;
             {
                 std::vector<int64_t> sizes;
+                double rs = 0.0;
                 for (int64_t c = 0; c < CG; ++c)
-                    if (!no_stage()) sizes.push_back(jobs[c].last - jobs[c].head + 1);
-                Lcs = pick_shape_groups(sizes, prm.lanes_per_eig);
+                    if (!no_stage()) {
+                        sizes.push_back(jobs[c].last - jobs[c].head + 1);
+                        rs += (double)sizes.back() * (double)cl_n[g0 + c];
+                    }
+                Lcs = pick_shape_groups(sizes, 0);
+                if (KCs > 0) {
+                    const int64_t rows = (int64_t)(rs / (double)KCs + 0.5);
+                    const int tl = table_lanes(h->tune, prm, MR3_TUNE_CHILD, precision, KCs, rows);
+                    if (tl > 0) Lcs = BisectShape{tl, 1};
+                    if (KCs >= stats.bisect_count[MR3_TUNE_CHILD]) {
+                        stats.bisect_count[MR3_TUNE_CHILD] = KCs;
+                        stats.bisect_rows[MR3_TUNE_CHILD] = rows;
+                        stats.bisect_lanes[MR3_TUNE_CHILD] = Lcs.L;
+                    }
+                }
             }
             BisectPlan cplan;
             {
@@ -1964,6 +2035,7 @@ void mr3_handle_copy_params(mr3_handle dst, mr3_handle src) {
     if (!dst || !src) return;
     dst->user = src->user;
     dst->have_user = src->have_user;
+    dst->tune = src->tune;
 }
 
 int mr3_handle_device(mr3_handle h) { return h ? h->device : -1; }
@@ -1979,6 +2051,7 @@ int mr3_create(mr3_handle* h, int device) {
     if (device < 0 || device >= nd) return -2;
     mr3_handle_s* x = new mr3_handle_s();
     x->device = device;
+    x->tune = mr3::builtin_tuning();
     // set-up on the device: the side streams and their events, the device
     // address of the no-allocation scratch array, and a first pinned staging
     // chunk (a solve on a caller's work region does not grow it)
@@ -2038,6 +2111,33 @@ int mr3_set_params(mr3_handle h, const mr3_params* p) {
         h->have_user = false;
     }
     return MR3_OK;
+}
+
+int mr3_set_tuning(mr3_handle h, const mr3_tune_entry* t, int count) {
+    if (!h) return -1;
+    if (!t && count < 0) {
+        h->tune = mr3::builtin_tuning();
+        return MR3_OK;
+    }
+    if (count < 0 || (count > 0 && !t)) return -2;
+    for (int i = 0; i < count; ++i)
+        if (!mr3::tune_entry_ok(t[i])) return -2;
+    h->tune.assign(t, t + count);
+    return MR3_OK;
+}
+
+int mr3_get_tuning(mr3_handle h, mr3_tune_entry* t, int cap) {
+    if (!h) return -1;
+    const int nt = (int)h->tune.size();
+    for (int i = 0; i < nt && i < cap && t; ++i) t[i] = h->tune[i];
+    return nt;
+}
+
+int mr3_bisect_lanes(mr3_handle h, int stage, int precision, int64_t count, int64_t rows) {
+    if (!h) return -1;
+    if ((stage != MR3_TUNE_ROOT && stage != MR3_TUNE_CHILD) || (precision != 32 && precision != 64))
+        return -2;
+    return mr3::table_lanes(h->tune, mr3::effective(h, precision), stage, precision, count, rows);
 }
 
 int mr3_get_stats(mr3_handle h, mr3_stats* s) {

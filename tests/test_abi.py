@@ -50,6 +50,9 @@ int main(void) {
     printf("mr3_params %zu\nmr3_stats %zu\nmr3_range_desc %zu\nmr3_request %zu\nmr3_result %zu\n",
            sizeof(mr3_params), sizeof(mr3_stats), sizeof(mr3_range_desc), sizeof(mr3_request),
            sizeof(mr3_result));
+    printf("mr3_tune_entry %zu\n", sizeof(mr3_tune_entry));
+    F(mr3_stats, bisect_count) F(mr3_stats, bisect_rows) F(mr3_stats, bisect_lanes)
+    F(mr3_tune_entry, count_lo) F(mr3_tune_entry, rows_hi) F(mr3_tune_entry, lanes)
     F(mr3_params, seed) F(mr3_params, profile) F(mr3_params, points_per_lane) F(mr3_params, gaptol_abs) F(mr3_params, initial)
     F(mr3_stats, stage_ms) F(mr3_stats, twist_row_steps) F(mr3_stats, dqds_transforms)
     F(mr3_stats, n_sliced_roots) F(mr3_stats, n_singleton_first_levels)
@@ -68,7 +71,8 @@ int main(void) {
 
 def test_struct_layout_matches_c():
     lay = _c_layout()
-    for name in ("mr3_params", "mr3_stats", "mr3_range_desc", "mr3_request", "mr3_result"):
+    for name in ("mr3_params", "mr3_stats", "mr3_range_desc", "mr3_request", "mr3_result",
+                 "mr3_tune_entry"):
         assert ctypes.sizeof(getattr(mr3, name)) == int(lay[name]), name
     for key, val in lay.items():
         if "." in key:
@@ -99,6 +103,9 @@ def test_argument_errors_without_device_work():
                                  None, 4, None) == -1
     assert lib.mr3_check_f64(None, 1, 1, None, None, None, None, 1, None, None, None) == -1
     assert lib.mr3_destroy(None) == -1
+    assert lib.mr3_set_tuning(None, None, -1) == -1
+    assert lib.mr3_get_tuning(None, None, 0) == -1
+    assert lib.mr3_bisect_lanes(None, mr3.MR3_TUNE_ROOT, 64, 100, 100) == -1
     assert lib.mr3_server_destroy(None) == -1
     assert lib.mr3_server_create(ctypes.byref(ctypes.c_void_p()), None, 1 << 20, 4) == -2
     if not torch.cuda.is_available():
