@@ -346,6 +346,64 @@ def single_legs(mr3, steps):
     return out
 
 
+def dense_leg(mr3, sizes=(2000, 4000), reps=3):
+    """The dense pipeline (Sec. 4.2, Fig. 3): A = Q T Q^T for the
+    prescribed-spectrum tridiagonal T and a seeded random orthogonal Q, all
+    eigenpairs through mr3_dense_f64 (reduction, this solver,
+    back-transformation) against torch.linalg.eigh on the same device (the
+    plain dense path), with residual and orthogonality of both in units of
+    n eps.  A is resident on the device; each call reduces a fresh copy."""
+    import torch
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    h = mr3.Handle(0)
+    out = {}
+    eps = 2.0 ** -53
+
+    def quality(A, w, Z):
+        n = A.shape[0]
+        nA = A.abs().sum(dim=0).max()
+        R = ((A @ Z - Z * w[None, :]).abs().sum(dim=0).max() / nA / (n * eps)).item()
+        O = ((Z.T @ Z - torch.eye(Z.shape[1], dtype=Z.dtype, device=dev)).abs().max() / (n * eps)).item()
+        return round(R, 4), round(O, 4)
+
+    for n in sizes:
+        d, e, _ = W.prescribed_spectrum(n, 0)
+        A = torch.from_numpy(W.dense_from_tridiagonal(d, e, 1)).to(dev)
+        Acm = A.t().contiguous()
+        work = torch.empty_like(Acm)
+        Wt = torch.empty(n, dtype=torch.float64, device=dev)
+        Zt = torch.empty((n, n), dtype=torch.float64, device=dev)
+        ms, ms_ref = [], []
+        for k in range(reps + 1):
+            work.copy_(Acm)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            mr3.mr3_dense_f64(h, n, work, n, mr3.RANGE_ALL, 0.0, 0.0, 1, n, Wt, Zt, n, stream)
+            torch.cuda.synchronize()
+            if k:
+                ms.append((time.perf_counter() - ts) * 1e3)
+        ours = quality(A, Wt, Zt.T)
+        for k in range(reps + 1):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            wr, Zr = torch.linalg.eigh(A)
+            torch.cuda.synchronize()
+            if k:
+                ms_ref.append((time.perf_counter() - ts) * 1e3)
+        ref = quality(A, wr, Zr)
+        out[f"dense_qtq_n{n}_fp64"] = {
+            "mr3_dense_ms": round(float(np.median(ms)), 2),
+            "torch_eigh_ms": round(float(np.median(ms_ref)), 2),
+            "mr3_dense": {"residual_n_eps": ours[0], "orthogonality_n_eps": ours[1]},
+            "torch_eigh": {"residual_n_eps": ref[0], "orthogonality_n_eps": ref[1]},
+        }
+    h.close()
+    return out
+
+
 def gaptol_study(mr3):
     """Clustering rho (largest cluster / n), tree depth and solve time against
     gaptol, with and without splitting by absolute gaps (gaptol_abs = gaptol)
@@ -471,6 +529,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-single", action="store_true", help="skip the C1 and C2 single-problem legs")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense A = Q T Q^T leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (calibrates "
                          "hardware byte counters against a known traffic) and exit")
@@ -588,6 +647,8 @@ def main():
         hb.close()
     if not args.no_served:
         extra["served"] = served_c5(mr3)
+    if not args.no_dense:
+        extra["dense_vs_plain"] = dense_leg(mr3)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(d, e, n)
     out = {

@@ -329,6 +329,40 @@ int mr3_solve_noalloc(mr3_handle h, int precision, int64_t n, const void *d, con
                       int range, double vl, double vu, int64_t il, int64_t iu, int64_t *m, void *W,
                       void *Z, int64_t ldz, void *stream);
 
+/* ---- Dense symmetric and Hermitian eigenproblems (Section 4.2, Fig. 3) ----
+ *
+ * The pipeline of the paper's dense experiments: reduce A to tridiagonal
+ * form A = Q T Q^H (Householder reduction, rocSOLVER sytrd / hetrd), compute
+ * the wanted eigenpairs of T with this library's solver of the same I/O
+ * precision (mixed precision inside), and back-transform the eigenvectors
+ * Z := Q Z (rocSOLVER ormtr / unmtr).  T is real symmetric in every case:
+ * the Hermitian reduction leaves a real tridiagonal.
+ *
+ * A: n x n, column-major, leading dimension lda >= max(1, n), device; only
+ * its lower triangle is read, and the call overwrites it with the reflectors.
+ * range, vl, vu, il, iu, m: as for mr3_solve_f32.  W: m eigenvalues,
+ * ascending, device, real (float for _f32, double otherwise).  Z: n x m
+ * eigenvectors, column-major, leading dimension ldz >= max(1, n), device,
+ * of A's element type (double complex = two doubles, real part first, for
+ * _c128), or NULL for eigenvalues only.  stream: as for the solves.
+ * Synchronous, like the other calls.  These entry points allocate: the
+ * tridiagonal's d, e and the reflector scalars (3n elements), for _c128 the
+ * real eigenvectors of T (n m doubles), the solver's work through the
+ * handle's pool, and rocSOLVER's own workspace.
+ * Returns MR3_OK, the solver's error codes, MR3_ERR_HIP for a failed
+ * reduction or back-transformation, or -k for an invalid argument k
+ * (1 h, 2 n, 3 A, 4 lda, 5 range, 6 vl, 7 vu, 8 il, 9 iu, 10 m, 11 W, 12 Z,
+ * 13 ldz, 14 stream); n above 2^31 - 1 is argument 2's error. */
+int mr3_dense_f32(mr3_handle h, int64_t n, float *A, int64_t lda, int range, double vl,
+                  double vu, int64_t il, int64_t iu, int64_t *m, float *W, float *Z,
+                  int64_t ldz, void *stream);
+int mr3_dense_f64(mr3_handle h, int64_t n, double *A, int64_t lda, int range, double vl,
+                  double vu, int64_t il, int64_t iu, int64_t *m, double *W, double *Z,
+                  int64_t ldz, void *stream);
+int mr3_dense_c128(mr3_handle h, int64_t n, void *A, int64_t lda, int range, double vl,
+                   double vu, int64_t il, int64_t iu, int64_t *m, double *W, void *Z,
+                   int64_t ldz, void *stream);
+
 /* Verification (not part of a solve; Section 1, eq. (1)).  For the FP64
  * eigenpairs (W, Z) of the FP64 tridiagonal (d, e), all device pointers:
  * orth_out[0] = max_{i != j} |z_i^T z_j| and orth_out[1] = max_i |z_i^T z_i - 1|,

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmr3.so")
-SOURCES = ["mr3_lib.hip", "mr3_check.hip", "mr3_server.cpp"]
+SOURCES = ["mr3_lib.hip", "mr3_check.hip", "mr3_dense.hip", "mr3_server.cpp"]
 HEADERS = ["dd.hpp", "mr3_types.hpp", "mr3_kernels.hip", "mr3_internal.h", "tuning_gfx950.inc"]
 
 FLAGS = [
@@ -23,12 +23,15 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
+# the dense pipeline's Householder reduction and back-transformation
+LIBS = ["-lrocsolver", "-lrocblas"]
 
 
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
+    cmd = ["hipcc", *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp,
+           *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

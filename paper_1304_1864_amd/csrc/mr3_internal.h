@@ -22,3 +22,6 @@ __attribute__((visibility("hidden"))) void mr3_handle_copy_params(mr3_handle dst
 
 // Device of a handle.
 __attribute__((visibility("hidden"))) int mr3_handle_device(mr3_handle h);
+
+// Release the rocBLAS handle the dense entry points made for `h` (if any).
+__attribute__((visibility("hidden"))) void mr3_dense_release(mr3_handle h);

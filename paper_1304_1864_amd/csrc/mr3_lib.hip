@@ -2081,6 +2081,7 @@ int mr3_create(mr3_handle* h, int device) {
 int mr3_destroy(mr3_handle h) {
     if (!h) return -1;
     (void)hipSetDevice(h->device);
+    mr3_dense_release(h);
     for (auto& sd : h->side)
         if (sd) (void)hipStreamSynchronize(sd);
     for (auto& b : h->buf) b.release();

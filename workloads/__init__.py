@@ -207,3 +207,43 @@ def served_requests(count: int, seed: int = 0, lo: int = 64, hi: int = 8192):
             rng_ = ("all", 1, n)
         out.append({"n": n, "dtype": dtype, "d": d, "e": e, "kind": kind, "range": rng_})
     return out
+
+
+def random_unitary(n: int, seed: int = 0, complex_: bool = False) -> np.ndarray:
+    """Seeded random orthogonal (or unitary) matrix: the Q factor of a
+    Gaussian matrix with the signs (phases) of R's diagonal moved into Q, so
+    that it is Haar distributed."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n))
+    if complex_:
+        G = G + 1j * rng.standard_normal((n, n))
+    Q, R = np.linalg.qr(G)
+    dg = np.diagonal(R).copy()
+    dg[dg == 0] = 1.0
+    return Q * (dg / np.abs(dg))
+
+
+def dense_from_tridiagonal(d: np.ndarray, e: np.ndarray, seed: int = 0, complex_: bool = False,
+                           dtype=None) -> np.ndarray:
+    """The dense inputs of the paper's dense experiments: A = Q T Q^H for the
+    tridiagonal T = (d, e) and a seeded random orthogonal (unitary) Q, formed
+    in binary64 (complex128) and rounded to ``dtype`` (default: float64, or
+    complex128 for the unitary case); exactly Hermitian."""
+    n = d.size
+    T = np.diag(d.astype(np.float64))
+    if n > 1:
+        T += np.diag(e.astype(np.float64), 1) + np.diag(e.astype(np.float64), -1)
+    Q = random_unitary(n, seed, complex_)
+    A = Q @ T @ Q.conj().T
+    A = 0.5 * (A + A.conj().T)
+    return A.astype(dtype or (np.complex128 if complex_ else np.float64))
+
+
+def dense_normal(n: int, seed: int = 0, complex_: bool = False, dtype=None) -> np.ndarray:
+    """Seeded random symmetric (Hermitian) matrix with N(0, 1) entries
+    (default dtype float64, or complex128)."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n))
+    if complex_:
+        G = G + 1j * rng.standard_normal((n, n))
+    return (0.5 * (G + G.conj().T)).astype(dtype or (np.complex128 if complex_ else np.float64))
