@@ -78,10 +78,14 @@ def alg_flops(st, y: str) -> float:
             + st["rqi_row_steps"] * FLOPS_RQI[y])
 
 
-def cpu_baseline(d, e, n, budget_s=20.0):
+def cpu_baseline(d, e, n, budget_s=20.0, w_gpu=None, z_gpu=None):
     """Oracle (double-double bisection + inverse iteration) on a bounded
     sample: contiguous index chunks spread over the spectrum, on the cores
-    this process may use (at most 16, the host share of one GPU)."""
+    this process may use (at most 16, the host share of one GPU).  After the
+    timing, the GPU's eigenvalues (host array w_gpu) and eigenvectors (z_gpu(i)
+    -> column i as a host array) of the sampled indices are compared with the
+    oracle's: eigenvalue error over its gate 4 n eps ||T||_1, and the largest
+    1 - |cos| between the two unit vectors."""
     import oracle
 
     avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
@@ -89,18 +93,33 @@ def cpu_baseline(d, e, n, budget_s=20.0):
     chunk = 512  # about 10-20 s of oracle work on 16 cores
     starts = [1, n // 4, n // 2, 3 * n // 4, n - chunk + 1]
     done = 0
+    got = []
     t0 = time.perf_counter()
     for s in starts:
         hi, lo = oracle.eigvals(d, e, s, s + chunk - 1, threads=threads)
-        oracle.eigvecs(d, e, hi, lo, threads=threads)
+        Zr = oracle.eigvecs(d, e, hi, lo, threads=threads)
+        got.append((s, hi + lo, Zr))
         done += chunk
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "eigenpairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} eigenpairs (index chunks of {chunk} at {starts[:done // chunk]}) "
-                      f"of the same n={n} matrix, {dt:.1f} s",
-            "host": {"nproc": os.cpu_count(), "usable": avail, "model": cpu_model()}}
+    out = {"value": done / dt, "unit": "eigenpairs/s", "cores": threads, "kind": "oracle",
+           "sample": f"{done} eigenpairs (index chunks of {chunk} at {starts[:done // chunk]}) "
+                     f"of the same n={n} matrix, {dt:.1f} s",
+           "host": {"nproc": os.cpu_count(), "usable": avail, "model": cpu_model()}}
+    if w_gpu is not None:
+        tn = float(np.max(np.abs(d) + np.concatenate([np.abs(e), [0.0]]) + np.concatenate([[0.0], np.abs(e)])))
+        gate = 4 * n * 2.0 ** -53 * tn
+        err, cos_gap = 0.0, 0.0
+        for s, ref, Zr in got:
+            err = max(err, float(np.max(np.abs(w_gpu[s - 1:s - 1 + ref.size] - ref))))
+            if z_gpu is not None:
+                for j in range(0, ref.size, 8):
+                    z = z_gpu(s - 1 + j)
+                    cos_gap = max(cos_gap, 1.0 - abs(float(z @ Zr[:, j])))
+        out["gpu_vs_oracle_on_sample"] = {"eig_err_over_gate": round(err / gate, 5),
+                                          "max_1_minus_abs_cos": float(f"{cos_gap:.3g}")}
+    return out
 
 
 def batched_c3(mr3, h, steps, warmup, plain_sample=512, seed=0):
@@ -129,9 +148,14 @@ def batched_c3(mr3, h, steps, warmup, plain_sample=512, seed=0):
     Zb = torch.empty(int(sum(k * k for k in n)), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
 
+    # per-problem host arrays built once (int64 numpy arrays pass without a copy)
+    n_a = np.array(n, dtype=np.int64)
+    wo_a = np.array(w_off, dtype=np.int64)
+    zo_a = np.array(z_off, dtype=np.int64)
+
     def step():
-        return mr3.mr3_solve_batched(h, count, 32, n, de_off.tolist(), dg, eg, None, Wb, w_off, Zb,
-                                     z_off, n, stream)
+        return mr3.mr3_solve_batched(h, count, 32, n_a, de_off, dg, eg, None, Wb, wo_a, Zb, zo_a,
+                                     n_a, stream)
 
     for _ in range(warmup):
         step()
@@ -337,11 +361,15 @@ def single_legs(mr3, steps):
         st = h.stats()
         med = float(np.median(ms))
         flops = alg_flops(st, "f64" if d.dtype == np.float32 else "dd")
+        (o_off, o_diag), resid = mr3.check(dg.double(), eg.double(), Wt.double(), Zt.double().T, handle=h)
+        gate = 10 * n * (2.0 ** -24 if d.dtype == np.float32 else 2.0 ** -53)
         out[name] = {"eigenpairs_per_s": round(n / (med / 1e3), 1), "p50_ms": round(med, 3),
                      "p99_ms": round(float(np.percentile(ms, 99)), 3), "calls": reps,
                      "roofline_frac": round(flops / (med / 1e3) / (FP64_VECTOR_PEAK_TFLOPS * 1e12), 5),
                      "tree": {"d_max": st["d_max"], "clusters": st["n_clusters"],
-                              "largest_cluster": st["largest_cluster"]}}
+                              "largest_cluster": st["largest_cluster"]},
+                     "orthogonality_over_gate": round(max(o_off, o_diag) / gate, 5),
+                     "residual_over_gate": round(resid / gate, 5)}
     h.close()
     return out
 
@@ -626,6 +654,12 @@ def main():
     }
     stages = {name: round(stage_ms[i] / args.steps, 3) for i, name in enumerate(mr3.STAGES)}
     st = h.stats()
+    # residual and orthogonality of the last timed solve, on the device
+    (o_off, o_diag), resid = mr3.check(dg, eg, W, Zt.T, handle=h)
+    gate = 10 * n * 2.0 ** -53
+    accuracy = {"orthogonality_over_gate": round(max(o_off, o_diag) / gate, 5),
+                "residual_over_gate": round(resid / gate, 5),
+                "gates": "max|Z^T Z - I| and max ||T z - lambda z||_1 / ||T||_1 against 10 n eps"}
 
     extra = {}
     if not args.no_subset:
@@ -650,7 +684,11 @@ def main():
     if not args.no_dense:
         extra["dense_vs_plain"] = dense_leg(mr3)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(d, e, n)
+    cpu = None
+    if not args.no_cpu_baseline:
+        step()  # the timed solve's results again, for the comparison on the sample
+        torch.cuda.synchronize()
+        cpu = cpu_baseline(d, e, n, w_gpu=W.cpu().numpy(), z_gpu=lambda i: Zt[i].cpu().numpy())
     out = {
         "metric": "eigenpairs/s (n=20000, fp64 I/O, dd internal) batched vs plain; p50/p99 solve ms",
         "value": round(value, 2),
@@ -675,6 +713,7 @@ def main():
                  "rqi_iters_per_pair": round(st["n_rqi_iters"] / max(n, 1), 3),
                  "fallbacks": st["n_fallbacks"], "best_candidate": st["n_best_candidate"]},
         "roofline": roofline,
+        "accuracy": accuracy,
         "cpu_baseline": cpu,
         **extra,
     }

@@ -20,6 +20,7 @@ import ctypes
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -393,13 +394,29 @@ def mr3_check_f64(h, n, m, d, e, W, Z, ldz, stream=None):
     return (orth[0], orth[1]), res[0]
 
 
+def _i64(x, count):
+    """A host int64 array of `count` entries (numpy arrays of that type pass
+    without a copy) and the pointer the C call takes."""
+    a = np.ascontiguousarray(x, dtype=np.int64)
+    if a.shape != (count,):
+        raise ValueError(f"expected {count} entries, got shape {a.shape}")
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
 def mr3_solve_batched(h, count, precision, n, de_off, d, e, ranges, W, w_off, Z, z_off, ldz,
                       stream=None, work=None):
-    i64a = ctypes.c_int64 * count
-    n_a, de_a, wo_a = i64a(*n), i64a(*de_off), i64a(*w_off)
-    zo_a = i64a(*z_off) if Z is not None else None
-    ld_a = i64a(*ldz) if Z is not None else None
-    m_a = i64a()
+    """Per-problem host arguments (n, de_off, w_off, z_off, ldz) may be lists
+    or int64 numpy arrays; returns the eigenpair counts m as a list."""
+    keep = []
+    def arr(x):
+        a, ptr = _i64(x, count)
+        keep.append(a)
+        return ptr
+    n_a, de_a, wo_a = arr(n), arr(de_off), arr(w_off)
+    zo_a = arr(z_off) if Z is not None else None
+    ld_a = arr(ldz) if Z is not None else None
+    m_np = np.zeros(count, dtype=np.int64)
+    m_a = m_np.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     rg = None
     if ranges is not None:
         rg = (mr3_range_desc * count)()
@@ -410,7 +427,7 @@ def mr3_solve_batched(h, count, precision, n, de_off, d, e, ranges, W, w_off, Z,
                                           m_a, _ptr(W), wo_a, _ptr(Z), zo_a, ld_a, wp, wb,
                                           _stream_ptr(stream))
     _check("mr3_solve_batched", rc)
-    return list(m_a)
+    return m_np.tolist()
 
 
 # --------------------------------------------------------------------------
