@@ -39,12 +39,14 @@ def test_oracle_under_asan_ubsan(tmp_path):
 def test_host_code_under_asan_ubsan(tmp_path):
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     exe = str(tmp_path / "san_server")
-    srcs = [os.path.join(CSRC, f) for f in ("mr3_lib.hip", "mr3_check.hip", "mr3_server.cpp")]
+    from paper_1304_1864_amd import build
+
+    srcs = [os.path.join(CSRC, f) for f in build.SOURCES]
     subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-ffp-contract=off",
                            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                            "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
                            "-Xarch_host", "-fno-omit-frame-pointer",
                            "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs,
-                           os.path.join(HERE, "san_server.cpp"), "-o", exe],
+                           os.path.join(HERE, "san_server.cpp"), "-o", exe, *build.LIBS],
                           stderr=subprocess.DEVNULL)
     _run(exe, "host")
