@@ -10,7 +10,9 @@
  *
  * Method (a different textbook method from the one under test, carried out in
  * double-double so that its own error is far below the I/O precision):
- *   1. the FP32/FP64 input is promoted exactly to double-double;
+ *   1. the FP32/FP64 input is promoted exactly to double-double and scaled
+ *      by a power of two so that ||T||_1 lies in [1/2, 1) (the scaling of the
+ *      entries in the paper's preprocessing; exact, and undone on output);
  *   2. eigenvalue i by bisection on the Sturm count of T - sigma I, i.e. the
  *      number of negative pivots of its LDL^T (Sylvester inertia), evaluated
  *      with the classic recurrence q_1 = d_1 - sigma,
@@ -21,7 +23,7 @@
  *      vectors are made orthogonal by modified Gram-Schmidt after each step;
  *   4. each vector is normalised and signed so that its largest-magnitude
  *      entry is positive.
- * No splitting, no shifting, no perturbation and no scaling of T is done.
+ * No splitting, no shifting and no perturbation of T is done.
  */
 #include <math.h>
 #include <omp.h>
@@ -125,17 +127,41 @@ typedef struct {
     xdd *d;   /* diagonal, exact copy of the input */
     xdd *e;   /* off-diagonal, exact copy */
     xdd *e2;  /* e_i^2 in double-double */
-    double tnorm;  /* ||T||_1 */
+    double tnorm;  /* ||T||_1 of the scaled matrix */
+    double tnorm_in; /* ||T||_1 of the input */
+    int sexp;      /* the data are the input times 2^-sexp */
     double pivmin; /* replacement for an exactly zero pivot */
     xdd gl, gu;    /* Gerschgorin interval */
 } prob_t;
 
-static void prob_init(prob_t *p, int n, const double *d, const double *e)
+/* Preprocessing (Sec. 2): the entries are scaled by a power of two (exact
+ * unless an entry falls below the normal range) so that ||T||_1 lies in
+ * [1/2, 1); eigenvalues are scaled back on output, shifts and eigenvalues
+ * passed in are scaled on input, and eigenvectors do not change.  Without it
+ * the squares of very small or very large entries leave the exponent range. */
+static void prob_init(prob_t *p, int n, const double *d_in, const double *e_in)
 {
     p->n = n;
     p->d = (xdd *)malloc(sizeof(xdd) * (size_t)(n > 0 ? n : 1));
     p->e = (xdd *)malloc(sizeof(xdd) * (size_t)(n > 1 ? n - 1 : 1));
     p->e2 = (xdd *)malloc(sizeof(xdd) * (size_t)(n > 1 ? n - 1 : 1));
+    double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *e = (double *)malloc(sizeof(double) * (size_t)(n > 1 ? n - 1 : 1));
+    double tn_in = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double row = fabs(d_in[i]) + ((i > 0) ? fabs(e_in[i - 1]) : 0.0) +
+                     ((i + 1 < n && ORACLE_MUTANT != 7) ? fabs(e_in[i]) : 0.0); /* mutant 7 */
+        if (row > tn_in)
+            tn_in = row;
+    }
+    p->tnorm_in = tn_in;
+    p->sexp = 0;
+    if (tn_in > 0.0 && isfinite(tn_in))
+        (void)frexp(tn_in, &p->sexp);
+    for (int i = 0; i < n; ++i)
+        d[i] = ldexp(d_in[i], -p->sexp);
+    for (int i = 0; i + 1 < n; ++i)
+        e[i] = ldexp(e_in[i], -p->sexp);
     double tn = 0.0, emax2 = 0.0;
     double glo = 0.0, ghi = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -162,6 +188,14 @@ static void prob_init(prob_t *p, int n, const double *d, const double *e)
     double widen = ldexp(1.0, -50) * (ghi - glo) + ldexp(1.0, -50) * tn + 1e-300;
     p->gl = from_d(glo - widen);
     p->gu = from_d(ghi + widen);
+    free(d);
+    free(e);
+}
+
+/* x * 2^k for a double-double (exact while it stays in range) */
+static xdd x_ldexp(xdd a, int k)
+{
+    return mk(ldexp(a.hi, k), ldexp(a.lo, k));
 }
 
 static void prob_free(prob_t *p)
@@ -349,7 +383,7 @@ int oracle_eigvals(int n, const double *d, const double *e, int il, int iu,
     int m = iu - il + 1;
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads > 0 ? nthreads : omp_threads())
     for (int k = 0; k < m; ++k) {
-        xdd lam = bisect_eig(&p, il + k);
+        xdd lam = x_ldexp(bisect_eig(&p, il + k), p.sexp);
         w_hi[k] = lam.hi;
         w_lo[k] = lam.lo;
     }
@@ -365,7 +399,7 @@ int oracle_count(int n, const double *d, const double *e, double s_hi, double s_
         return 0;
     prob_t p;
     prob_init(&p, n, d, e);
-    int c = sturm_count(&p, mk(s_hi, s_lo));
+    int c = sturm_count(&p, x_ldexp(mk(s_hi, s_lo), -p.sexp));
     prob_free(&p);
     return c;
 }
@@ -390,7 +424,7 @@ int oracle_eigvecs(int n, const double *d, const double *e, int m, const double 
     int ng = 0;
     gstart[ng++] = 0;
     for (int k = 1; k < m; ++k) {
-        xdd gap = x_sub(mk(w_hi[k], w_lo[k]), mk(w_hi[k - 1], w_lo[k - 1]));
+        xdd gap = x_ldexp(x_sub(mk(w_hi[k], w_lo[k]), mk(w_hi[k - 1], w_lo[k - 1])), -p.sexp);
         if (gap.hi > gtol)
             gstart[ng++] = k;
     }
@@ -408,7 +442,7 @@ int oracle_eigvecs(int n, const double *d, const double *e, int m, const double 
         for (int g = 0; g < ng; ++g) {
             for (int k = gstart[g]; k < gstart[g + 1]; ++k) {
                 xdd *x = zz + (size_t)k * (size_t)n;
-                xdd lam = mk(w_hi[k], w_lo[k]);
+                xdd lam = x_ldexp(mk(w_hi[k], w_lo[k]), -p.sexp);
                 lu_factor(&p, lam, &f);
                 for (int j = 0; j < n; ++j)
                     x[j] = from_d(start_entry(seed, k, j));
@@ -457,7 +491,7 @@ double oracle_tnorm(int n, const double *d, const double *e)
         return 0.0;
     prob_t p;
     prob_init(&p, n, d, e);
-    double t = p.tnorm;
+    double t = p.tnorm_in;
     prob_free(&p);
     return t;
 }
