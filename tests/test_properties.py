@@ -16,8 +16,13 @@ from tests import metrics as M
 
 EPS = 2.0 ** -53
 
+# Nonzero magnitudes stay above 2^-400: the squares of all entries, after the
+# oracle's scaling to ||T||_1 in [1/2, 1), must be representable in binary64
+# for a Sturm count to match the exact inertia (an eigenvalue of size
+# e^2 ~ 2^-900 at a shift of exactly 0 is beyond any binary64 computation).
 entry = st.one_of(
-    st.floats(-1.0, 1.0, allow_nan=False, allow_infinity=False),
+    st.floats(-1.0, 1.0, allow_nan=False, allow_infinity=False).filter(
+        lambda x: x == 0.0 or abs(x) >= 2.0 ** -400),
     st.sampled_from([0.0, 1.0, -1.0, 0.5, 2.0 ** -30]),
     st.integers(-40, 40).map(lambda k: float(2.0 ** k)),
 )
@@ -47,7 +52,7 @@ def _exact_negcount(d, e, sigma):
     return neg
 
 
-SETTINGS = settings(max_examples=150, deadline=None, derandomize=True,
+SETTINGS = settings(max_examples=150, deadline=None, derandomize=True, database=None,
                     suppress_health_check=[HealthCheck.too_slow])
 
 
@@ -89,7 +94,7 @@ def test_eigenvectors_at_the_gates(T):
     assert M.residual(d, ee, hi + lo, Z) <= 10 * n * EPS
 
 
-@settings(max_examples=60, deadline=None, derandomize=True,
+@settings(max_examples=60, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow])
 @given(tridiagonal(nmax=8), st.integers(-900, 900))
 def test_power_of_two_scaling_is_exact(T, k):
