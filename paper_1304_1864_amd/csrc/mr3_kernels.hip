@@ -690,7 +690,11 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
         const unsigned long long row = (unsigned long long)(blk.start + i);
         const unsigned long long key = prm.seed;
         const double xi_d = prm.xi * urand_pm1(key, row, 0);
-        const Y dt = mul(y_from(d64[blk.row0 + i], Y()), add_acc(one, y_from(xi_d, Y())));
+        Y dt = mul(y_from(d64[blk.row0 + i], Y()), add_acc(one, y_from(xi_d, Y())));
+        // a block of one row has its entry as eigenvalue: its pivot is formed
+        // in y from the entry (exact on the double-double path) and not
+        // perturbed, since there is no cluster to break up
+        if (n == 1) dt = sub(y_from(td[0], Y()), y_from(mu, Y()));
         rep_d[blk.row0 + i] = dt;
     }
     __syncthreads();
