@@ -43,7 +43,7 @@ def problem(draw):
     return d.astype(dt), e.astype(dt), window
 
 
-@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+@settings(max_examples=120, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
 @given(problem())
 def test_random_problems_against_the_oracle(mr3, pb):
@@ -53,3 +53,50 @@ def test_random_problems_against_the_oracle(mr3, pb):
     else:
         il, iu = min(window), max(window)
         run_case(mr3, d, e, rng="index", il=il, iu=iu)
+
+
+@st.composite
+def batch(draw):
+    prec = draw(st.sampled_from([32, 64]))
+    dt = np.float32 if prec == 32 else np.float64
+    count = draw(st.integers(1, 12))
+    probs = []
+    for _ in range(count):
+        n = draw(st.integers(1, 120))
+        vals = draw(st.lists(entry, min_size=2 * n - 1, max_size=2 * n - 1))
+        k = draw(st.integers(-30, 30))
+        d = np.ldexp(np.array(vals[:n]), k).astype(dt)
+        e = np.ldexp(np.array(vals[n:]), k).astype(dt)
+        probs.append((d, e))
+    return probs
+
+
+@settings(max_examples=25, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@given(batch())
+def test_random_batches_against_the_oracle(mr3, probs):
+    """A batched call of random problems: every problem's eigenpairs within
+    the gates against the oracle (eigenvalues) and on their own (residual,
+    orthogonality)."""
+    import torch
+
+    import oracle
+    from tests import metrics as M
+
+    ds = [torch.from_numpy(p[0]).to("cuda:0") for p in probs]
+    es = [torch.from_numpy(p[1] if p[0].size > 1 else np.zeros(1, p[0].dtype)).to("cuda:0")
+          for p in probs]
+    Ws, Zs = mr3.solve_batched(ds, es)
+    torch.cuda.synchronize()
+    for (d, e), w, Z in zip(probs, Ws, Zs):
+        n = d.size
+        eps = M.eps_of(d.dtype)
+        d64, e64 = d.astype(np.float64), e.astype(np.float64)
+        tn = M.tnorm(d64, e64)
+        hi, lo = oracle.eigvals(d64, e64 if n > 1 else np.zeros(0))
+        w = w.double().cpu().numpy()
+        assert w.size == n and np.all(np.diff(w) >= 0)
+        assert np.max(np.abs(w - (hi + lo))) <= 4 * n * eps * tn
+        Zn = Z.double().cpu().numpy()
+        assert M.residual(d64, e64, w, Zn) <= 10 * n * eps
+        assert M.orthogonality(Zn) <= 10 * n * eps
