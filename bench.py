@@ -432,6 +432,39 @@ def dense_leg(mr3, sizes=(2000, 4000), reps=3):
     return out
 
 
+def erep_study(mr3, reps=5):
+    """The e-representation without cached derived data (derive_lld = 1)
+    against the stored-lld variant on the n = 20000 prescribed matrix, FP64:
+    solve time with per-stage device times, and the workspace sizes of the
+    query (full speed and minimum)."""
+    import torch
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    n = 20000
+    d, e, _ = W.prescribed_spectrum(n, 0)
+    dg, eg = torch.from_numpy(d).to(dev), torch.from_numpy(e).to(dev)
+    Wt = torch.empty(n, dtype=torch.float64, device=dev)
+    Zt = torch.empty((n, n), dtype=torch.float64, device=dev)
+    for derive in (0, 1):
+        h = mr3.Handle(0)
+        h.set_params(precision=64, derive_lld=derive, profile=1)
+        ms = []
+        for k in range(reps + 1):
+            ts = time.perf_counter()
+            mr3.mr3_solve_f64(h, n, dg, eg, mr3.RANGE_ALL, 0.0, 0.0, 1, n, Wt, Zt, n)
+            torch.cuda.synchronize()
+            if k:
+                ms.append((time.perf_counter() - ts) * 1e3)
+        st = h.stats()
+        print(json.dumps({"derive_lld": derive, "n": n, "p50_ms": round(float(np.median(ms)), 3),
+                          "stage_ms": {k: round(v, 3) for k, v in zip(mr3.STAGES, st["stage_ms"])},
+                          "workspace_full_bytes": mr3.mr3_workspace_bytes(h, n, mr3.RANGE_ALL, 0, 64),
+                          "workspace_min_bytes": mr3.mr3_workspace_min_bytes(h, n, mr3.RANGE_ALL, 0, 64)}),
+              flush=True)
+        h.close()
+
+
 def gaptol_study(mr3):
     """Clustering rho (largest cluster / n), tree depth and solve time against
     gaptol, with and without splitting by absolute gaps (gaptol_abs = gaptol)
@@ -563,10 +596,18 @@ def main():
                          "hardware byte counters against a known traffic) and exit")
     ap.add_argument("--gaptol-study", action="store_true",
                     help="only run the clustering study against gaptol and exit")
+    ap.add_argument("--erep-study", action="store_true",
+                    help="only compare the e-representation without cached lld with the stored "
+                         "variant (time, workspace) and exit")
     ap.add_argument("--dqds-study", action="store_true",
                     help="only run the dqds against bisection comparison of initial eigenvalues "
                          "and exit")
     args = ap.parse_args()
+    if args.erep_study:
+        import paper_1304_1864_amd as mr3
+
+        erep_study(mr3)
+        return
     if args.dqds_study:
         import paper_1304_1864_amd as mr3
 

@@ -146,6 +146,16 @@ typedef struct {
                               eigenvalues and eigenvectors on the device before
                               the ascending-order check, so that the host-side
                               reordering runs */
+    int derive_lld;        /* 1: the e-representation without cached derived
+                              data (Sec. 3.2, "Choice of representations"): a
+                              tree node keeps only its d in y (and binary64
+                              copies); lld_i = e_i^2 / d_i is formed from the
+                              block's off-diagonals, stored once, wherever rows
+                              are read in y, with the bits the stored value
+                              would have.  Results are identical; each node row
+                              takes 16 (FP64) or 8 (FP32) bytes less, and the
+                              sweeps and counts in y form one quotient per row
+                              they load [0] */
 } mr3_params;
 
 #define MR3_INITIAL_BISECTION 0

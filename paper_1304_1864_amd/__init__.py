@@ -60,6 +60,7 @@ class mr3_params(ctypes.Structure):
         ("initial", ctypes.c_int),
         ("refine_ends", ctypes.c_int),
         ("force_resort", ctypes.c_int),
+        ("derive_lld", ctypes.c_int),
     ]
 
 

@@ -230,15 +230,28 @@ __device__ __forceinline__ int negcount_T(const double* __restrict__ Td,
     return neg;
 }
 
-// the same count in working precision y
+// lld_i = e_i^2 / d_i of a node in y: the stored array, or, when nodes keep
+// only d (the e-representation, Sec. 3.2 "Choice of representations": the
+// off-diagonals e are the same for every node of a block and stored once),
+// formed from the block's e and the node's d by the formula that would have
+// stored it (so both ways give the same bits).  Rows outside [0, n-1) give 0.
 template <class Y>
-__device__ int negcount_y(const Y* __restrict__ D, const Y* __restrict__ LL, int64_t n, Y x) {
+__device__ __forceinline__ Y lld_at(const Y* __restrict__ LL, const Y* __restrict__ E,
+                                    const Y* __restrict__ D, int64_t i, int64_t n) {
+    if (LL) return LL[i];
+    return (i >= 0 && i + 1 < n) ? div(mul(E[i], E[i]), D[i]) : y_from(0.0, Y());
+}
+
+// the same count in working precision y (LL null: lld from E and D)
+template <class Y>
+__device__ int negcount_y(const Y* __restrict__ D, const Y* __restrict__ LL,
+                          const Y* __restrict__ E, int64_t n, Y x) {
     Y a = neg(x), b = y_from(1.0, Y());
     int neg_ = 0;
     for (int64_t i = 0; i < n; ++i) {
         Y c = mul_add(D[i], b, a);
         neg_ += sign_differs(hi_of(c), hi_of(b));
-        a = mul_sub(LL[i], a, x, c);
+        a = mul_sub(lld_at(LL, E, D, i, n), a, x, c);
         b = c;
         if ((i & 3) == 3) {
             const int em = max(y_exp(a), y_exp(b));
@@ -664,10 +677,10 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
         for (int64_t i = t; i < n; i += blockDim.x) {
             const double di = (i == 0) ? qst[0] : __builtin_ldexp(qst[i] / qst[i - 1], (int)est[i - 1]);
             bad |= right ? !(di < 0.0) : !(di > 0.0);
-            rep_lld[blk.row0 + i] = y_from(di, Y());  // staged (rewritten below)
+            rep_d[blk.row0 + i] = y_from(di, Y());  // staged (rewritten below)
         }
         const int anybad = __syncthreads_or(bad);
-        for (int64_t i = t; i < n; i += blockDim.x) d64[blk.row0 + i] = hi_of(rep_lld[blk.row0 + i]);
+        for (int64_t i = t; i < n; i += blockDim.x) d64[blk.row0 + i] = hi_of(rep_d[blk.row0 + i]);
         if (t == 0) {
             s_mu = mu;
             s_ok = !anybad;
@@ -710,7 +723,7 @@ k_root(const Block* __restrict__ blocks, const double* __restrict__ Td,
             ll = div(mul(et, et), dt);
         }
         rep_e[blk.row0 + i] = et;
-        rep_lld[blk.row0 + i] = ll;
+        if (rep_lld) rep_lld[blk.row0 + i] = ll;
         d64[blk.row0 + i] = to_double(dt);
         lld64[blk.row0 + i] = to_double(ll);
     }
@@ -1528,7 +1541,8 @@ k_slice_small(const int* __restrict__ blist, const Block* __restrict__ blocks,
 // Sturm count in y at x for threads with on == true; the node's rows stream
 // through an LDS window filled by the 64 threads of the workgroup (all call).
 template <class Y>
-__device__ __forceinline__ int staged_count_y(const Y* __restrict__ D, const Y* __restrict__ LL, int64_t n, Y x,
+__device__ __forceinline__ int staged_count_y(const Y* __restrict__ D, const Y* __restrict__ LL,
+                              const Y* __restrict__ E, int64_t n, Y x,
                               bool on, Y (*wd)[STAGE_ROWS], Y (*wl)[STAGE_ROWS]) {
     constexpr int PER = STAGE_ROWS / 64;
     const int t = threadIdx.x;
@@ -1539,7 +1553,7 @@ __device__ __forceinline__ int staged_count_y(const Y* __restrict__ D, const Y* 
         const int64_t i = t + 64 * k;
         if (i < n) {
             wd[0][t + 64 * k] = D[i];
-            wl[0][t + 64 * k] = LL[i];
+            wl[0][t + 64 * k] = lld_at(LL, E, D, i, n);
         }
     }
     __syncthreads();
@@ -1550,7 +1564,7 @@ __device__ __forceinline__ int staged_count_y(const Y* __restrict__ D, const Y* 
         for (int k = 0; k < PER; ++k) {
             const int64_t i = c0 + STAGE_ROWS + t + 64 * k;
             nd[k] = (i < n) ? D[i] : y_from(0.0, Y());
-            nl[k] = (i < n) ? LL[i] : y_from(0.0, Y());
+            nl[k] = (i < n) ? lld_at(LL, E, D, i, n) : y_from(0.0, Y());
         }
         if (on) {
             const int cnt = (int)min<int64_t>(STAGE_ROWS, n - c0);
@@ -1594,8 +1608,8 @@ template <class Y>
 __global__ void __launch_bounds__(64)
 k_verify(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list, Slot* __restrict__ slots,
          const Node* __restrict__ nodes, const Block* __restrict__ blocks,
-         const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld, double rtol,
-         unsigned long long* __restrict__ repaired, int refine_all) {
+         const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld, const Y* __restrict__ rep_e,
+         double rtol, unsigned long long* __restrict__ repaired, int refine_all) {
     __shared__ Y wd[2][STAGE_ROWS], wl[2][STAGE_ROWS];
     const BisWG w = wgs[blockIdx.x];
     const int lane = threadIdx.x;
@@ -1605,7 +1619,8 @@ k_verify(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list, Slot* 
     const Node nd = nodes[w.node];
     const int64_t n = blocks[nd.block].n;
     const Y* D = rep_d + nd.rep;
-    const Y* LL = rep_lld + nd.rep;
+    const Y* LL = rep_lld ? rep_lld + nd.rep : nullptr;
+    const Y* E = rep_e + blocks[nd.block].row0;
     int64_t s = 0, j = 0;
     double lo = 0, hi = 0;
     if (active) {
@@ -1618,7 +1633,7 @@ k_verify(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list, Slot* 
     bool bad = false, fix = active;
     for (int it = 0; it < 80; ++it) {
         if (!__syncthreads_or(fix)) break;
-        const int c = staged_count_y<Y>(D, LL, n, y_from(side ? hi : lo, Y()), fix, wd, wl);
+        const int c = staged_count_y<Y>(D, LL, E, n, y_from(side ? hi : lo, Y()), fix, wd, wl);
         const int co = __shfl_xor(c, 1, 64);
         const int clo = side ? co : c, chi = side ? c : co;
         if (fix) {
@@ -1642,7 +1657,7 @@ k_verify(const BisWG* __restrict__ wgs, const int64_t* __restrict__ list, Slot* 
         if (!__syncthreads_or(busy)) break;
         const double h3 = (hi - lo) / 3.0;
         const double x = side ? lo + 2.0 * h3 : lo + h3;
-        const int c = staged_count_y<Y>(D, LL, n, y_from(x, Y()), busy, wd, wl);
+        const int c = staged_count_y<Y>(D, LL, E, n, y_from(x, Y()), busy, wd, wl);
         const int co = __shfl_xor(c, 1, 64);
         if (busy) {
             const int c1 = side ? co : c, c2 = side ? c : co;
@@ -1774,6 +1789,7 @@ template <class Y>
 __device__ __forceinline__ SweepStep<Y> load_sweep_step(int stream, int64_t it,
                                                         const Y* __restrict__ D,
                                                         const Y* __restrict__ LL,
+                                                        const Y* __restrict__ E,
                                                         const Y* __restrict__ P,
                                                         const int* __restrict__ Pe,
                                                         const Y* __restrict__ Q,
@@ -1786,14 +1802,14 @@ __device__ __forceinline__ SweepStep<Y> load_sweep_step(int stream, int64_t it,
         w.pq = P[it];
         w.pqe = Pe[it];
         w.f = D[it];
-        w.g = LL[it];
+        w.g = lld_at(LL, E, D, it, n);
     } else {
         // the advance row n-2-it is -1 only on the twist row of r = 0, whose
         // f and g are never used; the pool keeps a guard row there
         const int64_t kz = n - 1 - it, ka = kz - 1;
         w.pq = Q[kz];
         w.pqe = Qe[kz];
-        w.f = LL[ka];
+        w.f = lld_at(LL, E, D, ka, n);
         w.g = D[ka];
     }
     return w;
@@ -1958,6 +1974,7 @@ __device__ __forceinline__ void prepass_staged(bool top, const double* __restric
 // accesses also wait for the outstanding global stores)
 template <class Y>
 __device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __restrict__ LL,
+                                const Y* __restrict__ E,
                                 const Y* __restrict__ P, const int* __restrict__ Pe,
                                 const Y* __restrict__ Q, const int* __restrict__ Qe, int64_t n,
                                 int64_t r, Y tau, double* __restrict__ col, bool store,
@@ -1980,7 +1997,7 @@ __device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ 
     double* zp = col + (top ? (int64_t)0 : (n - 1) * 32);  // tile row of the current step
     const int64_t zstep = top ? 32 : -32;
     put_sweep_step<Y>(win, 0, t >> 5, t & 31,
-                      load_sweep_step<Y>(t >> 5, t & 31, D, LL, P, Pe, Q, Qe, n));
+                      load_sweep_step<Y>(t >> 5, t & 31, D, LL, E, P, Pe, Q, Qe, n));
     wave_sync();
     // the value of z at a step, after the storage check when `check`
     auto zvalue = [&](const SweepStep<Y>& w, int it, bool check) -> double {
@@ -2020,7 +2037,7 @@ __device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ 
     };
     for (int it0 = 0; it0 < smax; it0 += SW) {
         const int cur = (it0 / SW) & 1;
-        const SweepStep<Y> nx = load_sweep_step<Y>(t >> 5, it0 + SW + (t & 31), D, LL, P, Pe, Q, Qe, n);
+        const SweepStep<Y> nx = load_sweep_step<Y>(t >> 5, it0 + SW + (t & 31), D, LL, E, P, Pe, Q, Qe, n);
         if (it0 + SW < nsteps) {
             // the twist row lies beyond this window: straight-line steps
             for (int u = 0; u < SW; u += 4) {
@@ -2064,7 +2081,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
       const int64_t* __restrict__ tile_off, int64_t tile_base, double* __restrict__ tiles,
       const Slot* __restrict__ slots, const Node* __restrict__ nodes,
       const Block* __restrict__ blocks, const Y* __restrict__ rep_d, const Y* __restrict__ rep_lld,
-      const double* __restrict__ d64, const double* __restrict__ lld64, const Y* __restrict__ P,
+      const Y* __restrict__ rep_e, const double* __restrict__ d64, const double* __restrict__ lld64, const Y* __restrict__ P,
       const int* __restrict__ Pe, const Y* __restrict__ Q, const int* __restrict__ Qe,
       const double* __restrict__ P64, const double* __restrict__ Q64, Params prm,
       double eps_y, RqiResult* __restrict__ res, unsigned long long* __restrict__ counters,
@@ -2101,7 +2118,8 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
         gap = fmin(fmin(lg, rg), spd);
     }
     const Y* D = rep_d + rep;
-    const Y* LL = rep_lld + rep;
+    const Y* LL = rep_lld ? rep_lld + rep : nullptr;
+    const Y* E = rep_e + brow;
     const double* D64 = d64 + rep;
     const double* LL64 = lld64 + rep;
     // ---- twist index from a binary64 pass on the copy (argmin |gamma_k|) ----
@@ -2133,7 +2151,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
     if (P64 != nullptr) {
         SweepWin<double>& w64 = *reinterpret_cast<SweepWin<double>*>(&win);
         const int64_t st0 = active ? (top ? r + 1 : n - r) : 0;
-        Half<double> h0 = sweep_staged<double>(top, D64, LL64, P64 + brow, Pe + brow, Q64 + brow,
+        Half<double> h0 = sweep_staged<double>(top, D64, LL64, nullptr, P64 + brow, Pe + brow, Q64 + brow,
                                                Qe + brow, n, r, tau0, tile, false, st0, w64);
         const double spo = __shfl_xor(h0.sp, 1, 64);
         const double zro = __shfl_xor(h0.zr, 1, 64);
@@ -2175,7 +2193,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
     for (int it = 0; it < prm.rqi_max_iter; ++it) {
         if (!__any(!done && !fallback)) break;
         const int64_t steps = (done || fallback) ? 0 : (top ? r + 1 : n - r);
-        Half<Y> h = sweep_staged<Y>(top, D, LL, P + brow, Pe + brow, Q + brow, Qe + brow, n, r,
+        Half<Y> h = sweep_staged<Y>(top, D, LL, E, P + brow, Pe + brow, Q + brow, Qe + brow, n, r,
                                     lam, tile, true, steps, win);
         const Y spo = shfl_y<Y>(h.sp, lane ^ 1);
         const double zro = __shfl_xor(h.zr, 1, 64);
@@ -2247,7 +2265,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
         bool fixb = fallback;
         for (int it = 0; it < 80; ++it) {
             int c = 0;
-            if (fixb) c = negcount_y<Y>(D, LL, n, y_from(top ? blo : bhi, Y()));
+            if (fixb) c = negcount_y<Y>(D, LL, E, n, y_from(top ? blo : bhi, Y()));
             const int co = __shfl_xor(c, 1, 64);
             const int clo = top ? c : co, chi = top ? co : c;
             if (fixb) {
@@ -2274,7 +2292,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
             const Y w3 = mul(sub(yhi, ylo), y_from(1.0 / 3.0, Y()));
             const Y x = top ? add(ylo, w3) : add(ylo, add(w3, w3));
             const int j = (int)slots[list[active ? idx : 0]].idx;
-            int c = busy ? negcount_y<Y>(D, LL, n, x) : 0;
+            int c = busy ? negcount_y<Y>(D, LL, E, n, x) : 0;
             const int co = __shfl_xor(c, 1, 64);
             const Y xo = shfl_y<Y>(x, lane ^ 1);
             if (busy) {
@@ -2292,7 +2310,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
         for (int rep_it = 0; rep_it < 3; ++rep_it) {
             if (!__any(again)) break;
             const int64_t steps = again ? (top ? r + 1 : n - r) : 0;
-            Half<Y> h = sweep_staged<Y>(top, D, LL, P + brow, Pe + brow, Q + brow, Qe + brow, n, r,
+            Half<Y> h = sweep_staged<Y>(top, D, LL, E, P + brow, Pe + brow, Q + brow, Qe + brow, n, r,
                                         lam, tile, true, steps, win);
             const Y spo = shfl_y<Y>(h.sp, lane ^ 1);
             const double zro = __shfl_xor(h.zr, 1, 64);
@@ -2605,7 +2623,7 @@ k_child_rep(const ChildJob* __restrict__ jobs, int64_t njobs, Slot* __restrict__
     const Block bk = blocks[pn.block];
     const int64_t n = bk.n;
     const Y* D = rep_d + pn.rep;
-    const Y* LL = rep_lld + pn.rep;
+    const Y* LL = rep_lld ? rep_lld + pn.rep : nullptr;
     const Y* E = rep_e + bk.row0;
     Y* C = tmpc + job.tmp;
     int* CE = tmpe + job.tmp;
@@ -2623,7 +2641,7 @@ k_child_rep(const ChildJob* __restrict__ jobs, int64_t njobs, Slot* __restrict__
             const int64_t i = t + 64 * k;
             if (i < n) {
                 wd[0][t + 64 * k] = D[i];
-                wl[0][t + 64 * k] = LL[i];
+                wl[0][t + 64 * k] = lld_at(LL, E, D, i, n);
             }
         }
         __syncthreads();
@@ -2634,7 +2652,7 @@ k_child_rep(const ChildJob* __restrict__ jobs, int64_t njobs, Slot* __restrict__
             for (int k = 0; k < PER; ++k) {
                 const int64_t i = c0 + STAGE_ROWS + t + 64 * k;
                 nd[k] = (i < n) ? D[i] : y_from(0.0, Y());
-                nl[k] = (i < n) ? LL[i] : y_from(0.0, Y());
+                nl[k] = (i < n) ? lld_at(LL, E, D, i, n) : y_from(0.0, Y());
             }
             if (t == 0) {
                 const int cnt = (int)min<int64_t>(STAGE_ROWS, n - c0);
@@ -2673,7 +2691,7 @@ k_child_rep(const ChildJob* __restrict__ jobs, int64_t njobs, Slot* __restrict__
         }
     }
     Y* cd = rep_d + job.rep;
-    Y* cl = rep_lld + job.rep;
+    Y* cl = rep_lld ? rep_lld + job.rep : nullptr;
     for (int64_t i = t; i < n; i += blockDim.x) {
         // d+_i = c_i / c_{i-1} (c_{-1} = 1), then lld+_i = e_i^2 / d+_i
         Y dp = C[i];
@@ -2681,7 +2699,7 @@ k_child_rep(const ChildJob* __restrict__ jobs, int64_t njobs, Slot* __restrict__
         cd[i] = dp;
         Y ll = y_from(0.0, Y());
         if (i + 1 < n) ll = div(mul(E[i], E[i]), dp);
-        cl[i] = ll;
+        if (cl) cl[i] = ll;
         d64[job.rep + i] = to_double(dp);
         lld64[job.rep + i] = to_double(ll);
     }

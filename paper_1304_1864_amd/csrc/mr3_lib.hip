@@ -359,6 +359,7 @@ struct Shape {
     int max_depth = 6;
     bool dd = false;       // y = double-double
     bool dqds = false;
+    bool lld = true;       // nodes store lld in y (false: formed from e and d)
     size_t xsize = 8;
     int64_t rep_rows = 0;  // representation stack: root rows plus child rows
     int64_t tile_rows = 0; // eigenvector tile rows per side-stream parity
@@ -403,7 +404,8 @@ static void solve_sizes(const Shape& s, size_t* sz) {
     const int64_t tmp_rows = std::max<int64_t>(s.rep_rows - s.R, 1);
     sz[B_SLOTS] = sizeof(Slot) * K;
     sz[B_NODES] = sizeof(Node) * node_bound(s);
-    sz[B_REPD] = sz[B_REPL] = ys * (s.rep_rows + G2);
+    sz[B_REPD] = ys * (s.rep_rows + G2);
+    sz[B_REPL] = s.lld ? ys * (s.rep_rows + G2) : 0;
     sz[B_D64] = sz[B_L64] = sizeof(double) * (s.rep_rows + G2);
     sz[B_REPE] = ys * std::max<int64_t>(s.R, 1);
     sz[B_P] = sz[B_Q] = ys * (s.R + G2);
@@ -471,7 +473,8 @@ static bool plan_region(Shape& s, size_t avail, int64_t tile_full) {
     size_t left = avail - base;
     const size_t ys = s.dd ? 16 : 8;
     const size_t per_tile = 2 * sizeof(double);  // both side-stream parities
-    const size_t per_rep = 3 * ys + 2 * sizeof(double) + sizeof(int);  // d, lld, scratch; copies
+    // d, lld (unless formed on the fly), scratch; binary64 copies
+    const size_t per_rep = (s.lld ? 3 : 2) * ys + 2 * sizeof(double) + sizeof(int);
     const double want_t = (double)std::max<int64_t>(tile_full - s.tile_rows, 0) * per_tile;
     const double want_r = (double)(full_rep_rows(s) - s.rep_rows) * per_rep;
     const double f = (want_t + want_r <= (double)left) ? 1.0 : (double)left / (want_t + want_r);
@@ -613,6 +616,7 @@ static Params effective(const mr3_handle_s* h, int precision) {
     p.points_per_lane = h->have_user ? u.points_per_lane : 0;
     p.initial = h->have_user ? u.initial : MR3_INITIAL_BISECTION;
     p.refine_ends = h->have_user ? u.refine_ends : 0;
+    p.derive_lld = h->have_user ? u.derive_lld : 0;
     p.force_resort = h->have_user ? u.force_resort : 0;
     p.force_rqi_fallback = h->have_user ? u.force_rqi_fallback : 0;
     p.force_best_candidate = h->have_user ? u.force_best_candidate : 0;
@@ -856,6 +860,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     const bool fixed = work_region != nullptr;
     Buf Bf[B_NBUF];
     Buf* B = fixed ? Bf : h->buf;
+    // lld of the nodes in y: stored, or formed from e and d where rows are read
+    auto REPL = [&]() -> Y* { return prm.derive_lld ? nullptr : B[B_REPL].rows<Y>(); };
     Region reg;
     if (fixed) {
         const uintptr_t a = reinterpret_cast<uintptr_t>(work_region);
@@ -1017,6 +1023,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         sh.max_depth = prm.max_depth;
         sh.dd = is_dd;
         sh.dqds = prm.initial == MR3_INITIAL_DQDS;
+        sh.lld = !prm.derive_lld;
         sh.xsize = sizeof(X);
         int64_t tile_full = 0;
         for (const Block& bk : blocks)
@@ -1047,7 +1054,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     HIPCHK(B[B_NODES].ensure(sizeof(Node) * (size_t)std::max<int64_t>(node_cap, 1)));
     // representation stack: root rows first
     HIPCHK(B[B_REPD].ensure(sizeof(Y) * (R + 2 * GUARD)));
-    HIPCHK(B[B_REPL].ensure(sizeof(Y) * (R + 2 * GUARD)));
+    if (!prm.derive_lld) HIPCHK(B[B_REPL].ensure(sizeof(Y) * (R + 2 * GUARD)));
     HIPCHK(B[B_D64].ensure(sizeof(double) * (R + 2 * GUARD)));
     HIPCHK(B[B_L64].ensure(sizeof(double) * (R + 2 * GUARD)));
     HIPCHK(B[B_REPE].ensure(sizeof(Y) * R));
@@ -1086,7 +1093,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     // ---- a2: root representations ----
     prof.begin(MR3_STAGE_PREP, st);
     hipLaunchKernelGGL(k_root<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_TD].rows<double>(),
-                       B[B_TE].rows<double>(), prm, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
+                       B[B_TE].rows<double>(), prm, B[B_REPD].rows<Y>(), REPL(),
                        B[B_REPE].as<Y>(), B[B_D64].rows<double>(), B[B_L64].rows<double>(), dnodes,
                        dslots, status);
     hipLaunchKernelGGL(k_pq<Y>, dim3((unsigned)NB), dim3(256), 0, st, dblocks, B[B_REPE].as<Y>(),
@@ -1248,7 +1255,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             prof.begin(MR3_STAGE_VERIFY, st);
             hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)vwg.size()), dim3(64), 0, st,
                                B[B_VWG].as<BisWG>(), B[B_VLIST].as<int64_t>(), dslots, dnodes, dblocks,
-                               B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(), rtol_y, counters + 3, 1);
+                               B[B_REPD].rows<Y>(), REPL(), B[B_REPE].as<Y>(), rtol_y, counters + 3, 1);
             prof.end(st);
             HIPCHK(hipGetLastError());
         }
@@ -1466,7 +1473,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                                    pad, side, SCK.as<ChunkInfo>() + c0, nc,
                                    SL.as<int64_t>(), STO.as<int64_t>() + c0, base,
                                    STI.rows<double>(32), dslots,
-                                   dnodes, dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(),
+                                   dnodes, dblocks, B[B_REPD].rows<Y>(), REPL(), B[B_REPE].as<Y>(),
                                    B[B_D64].rows<double>(), B[B_L64].rows<double>(), B[B_P].rows<Y>(),
                                    B[B_PE].rows<int>(), B[B_Q].rows<Y>(), B[B_QE].rows<int>(), P64, Q64,
                                    prm, (double)YEps<Y>::v, SRE.as<RqiResult>(), counters, work);
@@ -1627,7 +1634,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             // (work region)
             const int64_t need = rep_top + new_rows;
             if (n_nodes + CG > node_cap || B[B_REPD].cap < sizeof(Y) * (need + 2 * GUARD) ||
-                B[B_REPL].cap < sizeof(Y) * (need + 2 * GUARD) ||
+                (!prm.derive_lld && B[B_REPL].cap < sizeof(Y) * (need + 2 * GUARD)) ||
                 B[B_D64].cap < sizeof(double) * (need + 2 * GUARD) ||
                 B[B_L64].cap < sizeof(double) * (need + 2 * GUARD))
                 HIPCHK(quiesce());
@@ -1642,7 +1649,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                 dnodes = B[B_NODES].as<Node>();
             }
             HIPCHK(B[B_REPD].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
-            HIPCHK(B[B_REPL].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
+            if (!prm.derive_lld) HIPCHK(B[B_REPL].ensure(sizeof(Y) * (need + 2 * GUARD), true, st));
             HIPCHK(B[B_D64].ensure(sizeof(double) * (need + 2 * GUARD), true, st));
             HIPCHK(B[B_L64].ensure(sizeof(double) * (need + 2 * GUARD), true, st));
             HIPCHK(B[B_TMPC].ensure(sizeof(Y) * new_rows));
@@ -1663,7 +1670,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                 prof.begin(MR3_STAGE_VERIFY, st);
                 hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)CG), dim3(64), 0, st, B[B_VWG].as<BisWG>(),
                                    B[B_VLIST].as<int64_t>(), dslots, dnodes, dblocks, B[B_REPD].rows<Y>(),
-                                   B[B_REPL].rows<Y>(), 4.0 * 1.1102230246251565e-16, counters + 3, 1);
+                                   REPL(), B[B_REPE].as<Y>(), 4.0 * 1.1102230246251565e-16, counters + 3, 1);
                 prof.end(st);
             }
             prof.begin(MR3_STAGE_CHILD, st);
@@ -1673,7 +1680,7 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                                prm.eps_x / (double)YEps<Y>::v);
             hipLaunchKernelGGL(k_child_rep<Y>, dim3((unsigned)CG), dim3(64), 0, st,
                                B[B_JOBS].as<ChildJob>(), CG, dslots, dnodes, dblocks, B[B_REPD].rows<Y>(),
-                               B[B_REPL].rows<Y>(), B[B_REPE].as<Y>(), B[B_D64].rows<double>(),
+                               REPL(), B[B_REPE].as<Y>(), B[B_D64].rows<double>(),
                                B[B_L64].rows<double>(), B[B_TMPC].as<Y>(), B[B_TMPE].as<int>(),
                                widen_root / prm.eps_x, prm.eps_x);
             prof.end(st);
@@ -1791,14 +1798,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                     if (nwg_all > 0)
                         hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)nwg_all), dim3(64), 0, st,
                                            B[B_VWG].as<BisWG>(), B[B_VLIST].as<int64_t>(), dslots, dnodes,
-                                           dblocks, B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(), rtol_y,
-                                           counters + 3, 1);
+                                           dblocks, B[B_REPD].rows<Y>(), REPL(), B[B_REPE].as<Y>(),
+                                           rtol_y, counters + 3, 1);
                     if ((int64_t)vwg.size() > nwg_all)
                         hipLaunchKernelGGL(k_verify<Y>, dim3((unsigned)((int64_t)vwg.size() - nwg_all)),
                                            dim3(64), 0, st, B[B_VWG].as<BisWG>() + nwg_all,
                                            B[B_VLIST].as<int64_t>(), dslots, dnodes, dblocks,
-                                           B[B_REPD].rows<Y>(), B[B_REPL].rows<Y>(), prm.bisect_rel,
-                                           counters + 3, 0);
+                                           B[B_REPD].rows<Y>(), REPL(), B[B_REPE].as<Y>(),
+                                           prm.bisect_rel, counters + 3, 0);
                 }
             }
             prof.end(st);
@@ -2197,6 +2204,7 @@ static Shape query_shape(mr3_handle h, int64_t n, int range, int64_t k_max, int 
     s.max_depth = h ? prm.max_depth : 6;
     s.dd = precision == 64;
     s.dqds = h && prm.initial == MR3_INITIAL_DQDS;
+    s.lld = !(h && prm.derive_lld);
     s.xsize = precision == 64 ? 8 : 4;
     return s;
 }
@@ -2235,6 +2243,7 @@ size_t mr3_workspace_bytes_batched(mr3_handle h, int64_t count, int precision, c
         s.max_depth = q.max_depth;
         s.dd = q.dd;
         s.dqds = q.dqds;
+        s.lld = q.lld;
         s.xsize = q.xsize;
         tile_full += q.R * (q.K + 32);
     }

@@ -122,6 +122,7 @@ struct Params {
     int profile;
     int refine_ends;      // cluster ends refined in y before the shift
     int force_resort;     // tests: outputs reversed before the order check
+    int derive_lld;       // nodes keep d only; lld = e^2 / d formed where read
     long long debug_slot;  // development trace (MR3_DEBUG_SLOT), -1 = off
     unsigned long long seed;
 };
