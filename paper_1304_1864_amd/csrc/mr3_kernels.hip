@@ -242,8 +242,8 @@ __device__ __forceinline__ Y lld_at(const Y* __restrict__ LL, const Y* __restric
     return (i >= 0 && i + 1 < n) ? div(mul(E[i], E[i]), D[i]) : y_from(0.0, Y());
 }
 
-// the same count in working precision y (LL null: lld from E and D)
-template <class Y>
+// the same count in working precision y (DL: lld from E and D)
+template <class Y, bool DL>
 __device__ int negcount_y(const Y* __restrict__ D, const Y* __restrict__ LL,
                           const Y* __restrict__ E, int64_t n, Y x) {
     Y a = neg(x), b = y_from(1.0, Y());
@@ -251,7 +251,7 @@ __device__ int negcount_y(const Y* __restrict__ D, const Y* __restrict__ LL,
     for (int64_t i = 0; i < n; ++i) {
         Y c = mul_add(D[i], b, a);
         neg_ += sign_differs(hi_of(c), hi_of(b));
-        a = mul_sub(lld_at(LL, E, D, i, n), a, x, c);
+        a = mul_sub(DL ? lld_at<Y>(nullptr, E, D, i, n) : LL[i], a, x, c);
         b = c;
         if ((i & 3) == 3) {
             const int em = max(y_exp(a), y_exp(b));
@@ -1785,7 +1785,9 @@ struct SweepWin {
     int pqe[2][2][SW];
 };
 
-template <class Y>
+// DL: lld formed from e and d (nodes without a stored lld); a template
+// argument, so that the sweeps of the stored form carry none of its code
+template <class Y, bool DL>
 __device__ __forceinline__ SweepStep<Y> load_sweep_step(int stream, int64_t it,
                                                         const Y* __restrict__ D,
                                                         const Y* __restrict__ LL,
@@ -1802,14 +1804,14 @@ __device__ __forceinline__ SweepStep<Y> load_sweep_step(int stream, int64_t it,
         w.pq = P[it];
         w.pqe = Pe[it];
         w.f = D[it];
-        w.g = lld_at(LL, E, D, it, n);
+        w.g = DL ? lld_at<Y>(nullptr, E, D, it, n) : LL[it];
     } else {
         // the advance row n-2-it is -1 only on the twist row of r = 0, whose
         // f and g are never used; the pool keeps a guard row there
         const int64_t kz = n - 1 - it, ka = kz - 1;
         w.pq = Q[kz];
         w.pqe = Qe[kz];
-        w.f = lld_at(LL, E, D, ka, n);
+        w.f = DL ? lld_at<Y>(nullptr, E, D, ka, n) : LL[ka];
         w.g = D[ka];
     }
     return w;
@@ -1972,7 +1974,7 @@ __device__ __forceinline__ void prepass_staged(bool top, const double* __restric
 // (always inlined, like every function here that takes an LDS window: as a
 // called function it would reach the window through generic pointers, whose
 // accesses also wait for the outstanding global stores)
-template <class Y>
+template <class Y, bool DL>
 __device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ D, const Y* __restrict__ LL,
                                 const Y* __restrict__ E,
                                 const Y* __restrict__ P, const int* __restrict__ Pe,
@@ -1997,7 +1999,7 @@ __device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ 
     double* zp = col + (top ? (int64_t)0 : (n - 1) * 32);  // tile row of the current step
     const int64_t zstep = top ? 32 : -32;
     put_sweep_step<Y>(win, 0, t >> 5, t & 31,
-                      load_sweep_step<Y>(t >> 5, t & 31, D, LL, E, P, Pe, Q, Qe, n));
+                      load_sweep_step<Y, DL>(t >> 5, t & 31, D, LL, E, P, Pe, Q, Qe, n));
     wave_sync();
     // the value of z at a step, after the storage check when `check`
     auto zvalue = [&](const SweepStep<Y>& w, int it, bool check) -> double {
@@ -2037,7 +2039,7 @@ __device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ 
     };
     for (int it0 = 0; it0 < smax; it0 += SW) {
         const int cur = (it0 / SW) & 1;
-        const SweepStep<Y> nx = load_sweep_step<Y>(t >> 5, it0 + SW + (t & 31), D, LL, E, P, Pe, Q, Qe, n);
+        const SweepStep<Y> nx = load_sweep_step<Y, DL>(t >> 5, it0 + SW + (t & 31), D, LL, E, P, Pe, Q, Qe, n);
         if (it0 + SW < nsteps) {
             // the twist row lies beyond this window: straight-line steps
             for (int u = 0; u < SW; u += 4) {
@@ -2075,7 +2077,8 @@ __device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ 
 
 // (two waves per SIMD: the binary64 instance would otherwise take more than
 // half the register file and run alone on its SIMD)
-template <class Y, int NW>
+// (DL: nodes without a stored lld, formed from e and d in the sweeps)
+template <class Y, int NW, bool DL>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
 k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __restrict__ list,
       const int64_t* __restrict__ tile_off, int64_t tile_base, double* __restrict__ tiles,
@@ -2151,7 +2154,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
     if (P64 != nullptr) {
         SweepWin<double>& w64 = *reinterpret_cast<SweepWin<double>*>(&win);
         const int64_t st0 = active ? (top ? r + 1 : n - r) : 0;
-        Half<double> h0 = sweep_staged<double>(top, D64, LL64, nullptr, P64 + brow, Pe + brow, Q64 + brow,
+        Half<double> h0 = sweep_staged<double, false>(top, D64, LL64, nullptr, P64 + brow, Pe + brow, Q64 + brow,
                                                Qe + brow, n, r, tau0, tile, false, st0, w64);
         const double spo = __shfl_xor(h0.sp, 1, 64);
         const double zro = __shfl_xor(h0.zr, 1, 64);
@@ -2193,7 +2196,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
     for (int it = 0; it < prm.rqi_max_iter; ++it) {
         if (!__any(!done && !fallback)) break;
         const int64_t steps = (done || fallback) ? 0 : (top ? r + 1 : n - r);
-        Half<Y> h = sweep_staged<Y>(top, D, LL, E, P + brow, Pe + brow, Q + brow, Qe + brow, n, r,
+        Half<Y> h = sweep_staged<Y, DL>(top, D, LL, E, P + brow, Pe + brow, Q + brow, Qe + brow, n, r,
                                     lam, tile, true, steps, win);
         const Y spo = shfl_y<Y>(h.sp, lane ^ 1);
         const double zro = __shfl_xor(h.zr, 1, 64);
@@ -2265,7 +2268,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
         bool fixb = fallback;
         for (int it = 0; it < 80; ++it) {
             int c = 0;
-            if (fixb) c = negcount_y<Y>(D, LL, E, n, y_from(top ? blo : bhi, Y()));
+            if (fixb) c = negcount_y<Y, DL>(D, LL, E, n, y_from(top ? blo : bhi, Y()));
             const int co = __shfl_xor(c, 1, 64);
             const int clo = top ? c : co, chi = top ? co : c;
             if (fixb) {
@@ -2292,7 +2295,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
             const Y w3 = mul(sub(yhi, ylo), y_from(1.0 / 3.0, Y()));
             const Y x = top ? add(ylo, w3) : add(ylo, add(w3, w3));
             const int j = (int)slots[list[active ? idx : 0]].idx;
-            int c = busy ? negcount_y<Y>(D, LL, E, n, x) : 0;
+            int c = busy ? negcount_y<Y, DL>(D, LL, E, n, x) : 0;
             const int co = __shfl_xor(c, 1, 64);
             const Y xo = shfl_y<Y>(x, lane ^ 1);
             if (busy) {
@@ -2310,7 +2313,7 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
         for (int rep_it = 0; rep_it < 3; ++rep_it) {
             if (!__any(again)) break;
             const int64_t steps = again ? (top ? r + 1 : n - r) : 0;
-            Half<Y> h = sweep_staged<Y>(top, D, LL, E, P + brow, Pe + brow, Q + brow, Qe + brow, n, r,
+            Half<Y> h = sweep_staged<Y, DL>(top, D, LL, E, P + brow, Pe + brow, Q + brow, Qe + brow, n, r,
                                         lam, tile, true, steps, win);
             const Y spo = shfl_y<Y>(h.sp, lane ^ 1);
             const double zro = __shfl_xor(h.zr, 1, 64);

@@ -1456,7 +1456,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             // CU holds one such workgroup and its waves get a SIMD each (two
             // workgroups on one CU would share SIMDs while other CUs idle)
             const unsigned pad = wpg > 1 ? 48u * 1024u : 0u;
-            auto rqi = wpg > 1 ? k_rqi<Y, RQI_WAVES> : k_rqi<Y, 1>;
+            auto rqi = prm.derive_lld ? (wpg > 1 ? k_rqi<Y, RQI_WAVES, true> : k_rqi<Y, 1, true>)
+                                      : (wpg > 1 ? k_rqi<Y, RQI_WAVES, false> : k_rqi<Y, 1, false>);
             // one round of consecutive chunks whose tiles fit the tile buffer
             // (all chunks unless the work region is smaller than the level's
             // tiles); the rounds reuse the buffer in stream order
