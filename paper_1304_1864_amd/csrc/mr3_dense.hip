@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cstdint>
 #include <mutex>
 #include <unordered_map>
 
@@ -178,6 +179,7 @@ int mr3_dense_c128(mr3_handle h, int64_t n, void* A, int64_t lda, int range, dou
     // d, e (real) and the complex reflector scalars; the real eigenvectors of
     // T (at most n columns: the count of a value range is not known before)
     const int64_t kcap = range == MR3_RANGE_INDEX ? iu - il + 1 : n;
+    if (Z && (size_t)kcap > SIZE_MAX / sizeof(double) / (size_t)n) return -2;  // n kcap doubles
     DevMem mem, zr;
     if (!mem.alloc(2 * (size_t)n * sizeof(double) + (size_t)n * sizeof(rocblas_double_complex)))
         return MR3_ERR_HIP;
