@@ -351,13 +351,14 @@ int mr3_solve_noalloc(mr3_handle h, int precision, int64_t n, const void *d, con
  * A: n x n, column-major, leading dimension lda >= max(1, n), device; only
  * its lower triangle is read, and the call overwrites it with the reflectors.
  * range, vl, vu, il, iu, m: as for mr3_solve_f32.  W: m eigenvalues,
- * ascending, device, real (float for _f32, double otherwise).  Z: n x m
- * eigenvectors, column-major, leading dimension ldz >= max(1, n), device,
- * of A's element type (double complex = two doubles, real part first, for
- * _c128), or NULL for eigenvalues only.  stream: as for the solves.
+ * ascending, device, real (float for _f32 and _c64, double otherwise).  Z:
+ * n x m eigenvectors, column-major, leading dimension ldz >= max(1, n),
+ * device, of A's element type (a complex number is two reals, real part
+ * first: two floats for _c64, two doubles for _c128), or NULL for
+ * eigenvalues only.  stream: as for the solves.
  * Synchronous, like the other calls.  These entry points allocate: the
- * tridiagonal's d, e and the reflector scalars (3n elements), for _c128 the
- * real eigenvectors of T (n m doubles), the solver's work through the
+ * tridiagonal's d, e and the reflector scalars (3n elements), for the complex
+ * forms the real eigenvectors of T (n m reals), the solver's work through the
  * handle's pool, and rocSOLVER's own workspace.
  * Returns MR3_OK, the solver's error codes, MR3_ERR_HIP for a failed
  * reduction or back-transformation, or -k for an invalid argument k
@@ -368,6 +369,9 @@ int mr3_dense_f32(mr3_handle h, int64_t n, float *A, int64_t lda, int range, dou
                   int64_t ldz, void *stream);
 int mr3_dense_f64(mr3_handle h, int64_t n, double *A, int64_t lda, int range, double vl,
                   double vu, int64_t il, int64_t iu, int64_t *m, double *W, double *Z,
+                  int64_t ldz, void *stream);
+int mr3_dense_c64(mr3_handle h, int64_t n, void *A, int64_t lda, int range, double vl,
+                  double vu, int64_t il, int64_t iu, int64_t *m, float *W, void *Z,
                   int64_t ldz, void *stream);
 int mr3_dense_c128(mr3_handle h, int64_t n, void *A, int64_t lda, int range, double vl,
                    double vu, int64_t il, int64_t iu, int64_t *m, double *W, void *Z,

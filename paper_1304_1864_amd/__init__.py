@@ -154,7 +154,7 @@ EXPORTS = [
     "mr3_solve_f32", "mr3_solve_f64", "mr3_solve_batched", "mr3_check_f64", "mr3_version",
     "mr3_workspace_bytes", "mr3_workspace_min_bytes", "mr3_workspace_bytes_batched",
     "mr3_solve_noalloc", "mr3_set_tuning", "mr3_get_tuning", "mr3_bisect_lanes",
-    "mr3_dense_f32", "mr3_dense_f64", "mr3_dense_c128",
+    "mr3_dense_f32", "mr3_dense_f64", "mr3_dense_c64", "mr3_dense_c128",
     "mr3_request_bytes", "mr3_server_create", "mr3_server_create_ex",
     "mr3_server_create_with_executor",
     "mr3_server_submit", "mr3_server_poll", "mr3_server_wait", "mr3_server_destroy",
@@ -191,7 +191,7 @@ def load_library(path: str | None = None):
     lib.mr3_workspace_bytes_batched.argtypes = [vp, i64, i32, pi64, ctypes.POINTER(mr3_range_desc)]
     lib.mr3_solve_noalloc.argtypes = [vp, i32, i64, vp, vp, i32, dbl, dbl, i64, i64, pi64, vp, vp,
                                       i64, vp]
-    for name in ("mr3_dense_f32", "mr3_dense_f64", "mr3_dense_c128"):
+    for name in ("mr3_dense_f32", "mr3_dense_f64", "mr3_dense_c64", "mr3_dense_c128"):
         getattr(lib, name).argtypes = [vp, i64, vp, i64, i32, dbl, dbl, i64, i64, pi64, vp, vp,
                                        i64, vp]
     lib.mr3_set_tuning.argtypes = [vp, ctypes.POINTER(mr3_tune_entry), i32]
@@ -471,15 +471,15 @@ def solve(d: torch.Tensor, e: torch.Tensor, range: str = "all", vl: float = 0.0,
 def dense(A: torch.Tensor, range: str = "all", vl: float = 0.0, vu: float = 0.0, il: int = 1,
           iu: int | None = None, vectors: bool = True, handle: Handle | None = None, stream=None):
     """Eigenpairs of the dense symmetric (float32, float64) or Hermitian
-    (complex128) device matrix A (its lower triangle is read; A itself is not
+    (complex64, complex128) device matrix A (its lower triangle is read; A itself is not
     modified): reduction to tridiagonal form, this library's solver,
     back-transformation.  Returns (W[m], Z[n, m] or None)."""
     if not A.is_cuda or A.dim() != 2 or A.shape[0] != A.shape[1]:
         raise ValueError("A must be a square device matrix")
     fns = {torch.float32: mr3_dense_f32, torch.float64: mr3_dense_f64,
-           torch.complex128: mr3_dense_c128}
+           torch.complex64: mr3_dense_c64, torch.complex128: mr3_dense_c128}
     if A.dtype not in fns:
-        raise ValueError("A must be float32, float64 or complex128")
+        raise ValueError("A must be float32, float64, complex64 or complex128")
     h = handle or default_handle()
     n = A.shape[0]
     if iu is None:
@@ -487,7 +487,7 @@ def dense(A: torch.Tensor, range: str = "all", vl: float = 0.0, vu: float = 0.0,
     rk = _RANGES[range]
     cap = n if rk != RANGE_INDEX else max(iu - il + 1, 0)
     Ac = A.t().contiguous()  # row-major storage of A^T is column-major A
-    wdt = torch.float32 if A.dtype == torch.float32 else torch.float64
+    wdt = torch.float32 if A.dtype in (torch.float32, torch.complex64) else torch.float64
     W = torch.empty(max(cap, 1), dtype=wdt, device=A.device)
     Zt = torch.empty((max(cap, 1), max(n, 1)), dtype=A.dtype, device=A.device) if vectors else None
     m = fns[A.dtype](h, n, Ac, max(n, 1), rk, vl, vu, il, iu, W, Zt, max(n, 1), stream)
@@ -508,6 +508,7 @@ def _dense_raw(name):
 
 mr3_dense_f32 = _dense_raw("mr3_dense_f32")
 mr3_dense_f64 = _dense_raw("mr3_dense_f64")
+mr3_dense_c64 = _dense_raw("mr3_dense_c64")
 mr3_dense_c128 = _dense_raw("mr3_dense_c128")
 
 

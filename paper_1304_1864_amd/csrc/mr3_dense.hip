@@ -60,14 +60,18 @@ int check_dense(mr3_handle h, int64_t n, const void* A, int64_t lda, int range, 
 }
 
 // real eigenvectors of T (n x m, leading dimension n) into the complex Z
+// (R2: float2 or double2, real part first)
+template <class R, class R2>
 __global__ void __launch_bounds__(256)
-k_real_to_complex(const double* __restrict__ zr, int64_t n, int64_t m, double2* __restrict__ z,
-                  int64_t ldz) {
+k_real_to_complex(const R* __restrict__ zr, int64_t n, int64_t m, R2* __restrict__ z, int64_t ldz) {
     const int64_t total = n * m;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t j = t / n, i = t - j * n;
-        z[j * ldz + i] = make_double2(zr[t], 0.0);
+        R2 v;
+        v.x = zr[t];
+        v.y = R(0);
+        z[j * ldz + i] = v;
     }
 }
 
@@ -140,6 +144,79 @@ int dense_real(mr3_handle h, int64_t n, X* A, int64_t lda, int range, double vl,
     return finish(rc, st);
 }
 
+template <class R>
+struct Cplx;
+template <>
+struct Cplx<float> {
+    using C = rocblas_float_complex;
+    using R2 = float2;
+    static rocblas_status trd(rocblas_handle b, rocblas_int n, C* A, rocblas_int lda, float* D,
+                              float* E, C* tau) {
+        return rocsolver_chetrd(b, rocblas_fill_lower, n, A, lda, D, E, tau);
+    }
+    static rocblas_status mtr(rocblas_handle b, rocblas_int n, rocblas_int m, C* A,
+                              rocblas_int lda, C* tau, C* Z, rocblas_int ldz) {
+        return rocsolver_cunmtr(b, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, n,
+                                m, A, lda, tau, Z, ldz);
+    }
+};
+template <>
+struct Cplx<double> {
+    using C = rocblas_double_complex;
+    using R2 = double2;
+    static rocblas_status trd(rocblas_handle b, rocblas_int n, C* A, rocblas_int lda, double* D,
+                              double* E, C* tau) {
+        return rocsolver_zhetrd(b, rocblas_fill_lower, n, A, lda, D, E, tau);
+    }
+    static rocblas_status mtr(rocblas_handle b, rocblas_int n, rocblas_int m, C* A,
+                              rocblas_int lda, C* tau, C* Z, rocblas_int ldz) {
+        return rocsolver_zunmtr(b, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none, n,
+                                m, A, lda, tau, Z, ldz);
+    }
+};
+
+// Hermitian A: the reduction leaves a real tridiagonal, solved by the real
+// solver of the same precision; its real eigenvectors are widened to complex
+// before the back-transformation
+template <class R>
+int dense_complex(mr3_handle h, int64_t n, void* A, int64_t lda, int range, double vl, double vu,
+                  int64_t il, int64_t iu, int64_t* m, R* W, void* Z, int64_t ldz, void* stream) {
+    using C = typename Cplx<R>::C;
+    int rc = check_dense(h, n, A, lda, range, vl, vu, il, iu, m, W, Z, ldz);
+    if (rc) return rc;
+    *m = 0;
+    if (n == 0 || (range == MR3_RANGE_INDEX && il > iu)) return MR3_OK;
+    const hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(mr3_handle_device(h)) != hipSuccess) return MR3_ERR_HIP;
+    rocblas_handle bh = blas_of(h);
+    if (!bh || rocblas_set_stream(bh, st) != rocblas_status_success) return MR3_ERR_HIP;
+    auto* Ac = (C*)A;
+    // d, e (real) and the complex reflector scalars; the real eigenvectors of
+    // T (at most n columns: the count of a value range is not known before)
+    const int64_t kcap = range == MR3_RANGE_INDEX ? iu - il + 1 : n;
+    if (Z && (size_t)kcap > SIZE_MAX / sizeof(R) / (size_t)n) return -2;  // n kcap reals
+    DevMem mem, zr;
+    if (!mem.alloc(2 * (size_t)n * sizeof(R) + (size_t)n * sizeof(C))) return MR3_ERR_HIP;
+    if (Z && !zr.alloc((size_t)n * (size_t)kcap * sizeof(R))) return MR3_ERR_HIP;
+    auto* tau = (C*)mem.p;  // (the complex scalars first: their alignment)
+    R* D = (R*)(tau + n);
+    R* E = D + n;
+    if (Cplx<R>::trd(bh, (rocblas_int)n, Ac, (rocblas_int)lda, D, E, tau) != rocblas_status_success)
+        return finish(MR3_ERR_HIP, st);
+    rc = Real<R>::solve(h, n, D, E, range, vl, vu, il, iu, m, W, Z ? (R*)zr.p : nullptr, n, stream);
+    if (rc == MR3_OK && Z && *m > 0) {
+        const int64_t total = n * *m;
+        const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
+        hipLaunchKernelGGL((k_real_to_complex<R, typename Cplx<R>::R2>), dim3(grid), dim3(256), 0,
+                           st, (const R*)zr.p, n, *m, (typename Cplx<R>::R2*)Z, ldz);
+        if (hipGetLastError() != hipSuccess ||
+            Cplx<R>::mtr(bh, (rocblas_int)n, (rocblas_int)*m, Ac, (rocblas_int)lda, tau, (C*)Z,
+                         (rocblas_int)ldz) != rocblas_status_success)
+            rc = MR3_ERR_HIP;
+    }
+    return finish(rc, st);
+}
+
 }  // namespace
 
 void mr3_dense_release(mr3_handle h) {
@@ -164,46 +241,16 @@ int mr3_dense_f64(mr3_handle h, int64_t n, double* A, int64_t lda, int range, do
     return dense_real<double>(h, n, A, lda, range, vl, vu, il, iu, m, W, Z, ldz, stream);
 }
 
+int mr3_dense_c64(mr3_handle h, int64_t n, void* A, int64_t lda, int range, double vl,
+                  double vu, int64_t il, int64_t iu, int64_t* m, float* W, void* Z, int64_t ldz,
+                  void* stream) {
+    return dense_complex<float>(h, n, A, lda, range, vl, vu, il, iu, m, W, Z, ldz, stream);
+}
+
 int mr3_dense_c128(mr3_handle h, int64_t n, void* A, int64_t lda, int range, double vl,
                    double vu, int64_t il, int64_t iu, int64_t* m, double* W, void* Z, int64_t ldz,
                    void* stream) {
-    int rc = check_dense(h, n, A, lda, range, vl, vu, il, iu, m, W, Z, ldz);
-    if (rc) return rc;
-    *m = 0;
-    if (n == 0 || (range == MR3_RANGE_INDEX && il > iu)) return MR3_OK;
-    const hipStream_t st = (hipStream_t)stream;
-    if (hipSetDevice(mr3_handle_device(h)) != hipSuccess) return MR3_ERR_HIP;
-    rocblas_handle bh = blas_of(h);
-    if (!bh || rocblas_set_stream(bh, st) != rocblas_status_success) return MR3_ERR_HIP;
-    auto* Ac = (rocblas_double_complex*)A;
-    // d, e (real) and the complex reflector scalars; the real eigenvectors of
-    // T (at most n columns: the count of a value range is not known before)
-    const int64_t kcap = range == MR3_RANGE_INDEX ? iu - il + 1 : n;
-    if (Z && (size_t)kcap > SIZE_MAX / sizeof(double) / (size_t)n) return -2;  // n kcap doubles
-    DevMem mem, zr;
-    if (!mem.alloc(2 * (size_t)n * sizeof(double) + (size_t)n * sizeof(rocblas_double_complex)))
-        return MR3_ERR_HIP;
-    if (Z && !zr.alloc((size_t)n * (size_t)kcap * sizeof(double))) return MR3_ERR_HIP;
-    double* D = (double*)mem.p;
-    double* E = D + n;
-    auto* tau = (rocblas_double_complex*)(E + n);
-    if (rocsolver_zhetrd(bh, rocblas_fill_lower, (rocblas_int)n, Ac, (rocblas_int)lda, D, E, tau) !=
-        rocblas_status_success)
-        return finish(MR3_ERR_HIP, st);
-    rc = mr3_solve_f64(h, n, D, E, range, vl, vu, il, iu, m, W, Z ? (double*)zr.p : nullptr, n,
-                       nullptr, 0, stream);
-    if (rc == MR3_OK && Z && *m > 0) {
-        const int64_t total = n * *m;
-        const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_real_to_complex, dim3(grid), dim3(256), 0, st, (const double*)zr.p, n,
-                           *m, (double2*)Z, ldz);
-        if (hipGetLastError() != hipSuccess ||
-            rocsolver_zunmtr(bh, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                             (rocblas_int)n, (rocblas_int)*m, Ac, (rocblas_int)lda, tau,
-                             (rocblas_double_complex*)Z, (rocblas_int)ldz) != rocblas_status_success)
-            rc = MR3_ERR_HIP;
-    }
-    return finish(rc, st);
+    return dense_complex<double>(h, n, A, lda, range, vl, vu, il, iu, m, W, Z, ldz, stream);
 }
 
 }  // extern "C"

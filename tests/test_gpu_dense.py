@@ -94,6 +94,15 @@ def test_dense_hermitian_c128(mr3, n):
     check(mr3, A, hi + lo, 2.0 ** -53)
 
 
+def test_dense_hermitian_c64(mr3):
+    """Single-complex Hermitian input: eigenvalues against the dense oracle of
+    the rounded matrix, vectors at the FP32 gates."""
+    d, e = W.uniform(200, 20, np.float64)
+    A = W.dense_from_tridiagonal(d, e, 21, complex_=True).astype(np.complex64)
+    hi, lo = OD.eigvals(A.astype(np.complex128))
+    check(mr3, A, hi + lo, 2.0 ** -24)
+
+
 def test_dense_argument_errors(mr3):
     lib = mr3.load_library()
     h = mr3.default_handle()
