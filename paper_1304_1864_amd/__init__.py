@@ -18,7 +18,6 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
 
 import numpy as np
 import torch

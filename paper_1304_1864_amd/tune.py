@@ -22,7 +22,6 @@ import json
 import math
 import os
 import sys
-import time
 
 import numpy as np
 

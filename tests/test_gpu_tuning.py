@@ -4,7 +4,6 @@ a solve takes its multisection shape from it (mr3_stats reports the key and
 the lanes), and results under different shapes pass the same oracle gates."""
 import os
 
-import numpy as np
 import pytest
 import torch
 
