@@ -6,6 +6,8 @@ import threading
 import time
 
 import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
 
 import paper_1304_1864_amd as mr3
 
@@ -262,3 +264,88 @@ def test_a_ticket_has_one_waiter():
     th.join()
     assert first["status"] == 0
     mr3.mr3_server_destroy(s)
+
+
+# ---------------------------------------------------------------------------
+# property-based: random request streams through the scheduler
+# ---------------------------------------------------------------------------
+
+
+class RecordingExecutor:
+    """Runs batches in a few milliseconds, failing those that hold a request
+    of `fail`; records every batch with the request bytes in flight."""
+
+    def __init__(self, fail):
+        self.fail = set(fail)
+        self.lock = threading.Lock()
+        self.batches = []
+        self.inflight = 0
+        self.max_inflight = 0
+        self.cb = mr3.EXECUTOR_FN(self._run)
+
+    def _run(self, ctx, count, reqs, m):
+        ids, precs, est = [], set(), 0
+        for i in range(count):
+            r = reqs[i]
+            ids.append(int(r.W))
+            precs.add(r.precision)
+            k = r.range.iu - r.range.il + 1 if r.range.range == mr3.RANGE_INDEX else r.n
+            est += mr3.mr3_request_bytes(r.n, k, r.precision)
+            m[i] = k
+        with self.lock:
+            self.batches.append((ids, precs))
+            self.inflight += est
+            self.max_inflight = max(self.max_inflight, self.inflight)
+        time.sleep(0.002)
+        with self.lock:
+            self.inflight -= est
+        return mr3.MR3_ERR_NUMERIC if self.fail & set(ids) else mr3.MR3_OK
+
+
+@st.composite
+def stream(draw):
+    count = draw(st.integers(1, 16))
+    reqs = []
+    for i in range(1, count + 1):
+        n = draw(st.integers(1, 3000))
+        prec = draw(st.sampled_from([32, 64]))
+        rng = None
+        if draw(st.booleans()):
+            il = draw(st.integers(1, n))
+            iu = draw(st.integers(il, n))
+            rng = (mr3.RANGE_INDEX, il, iu)
+        reqs.append((i, n, prec, rng))
+    fail = draw(st.sets(st.integers(1, count), max_size=2))
+    return reqs, fail
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(stream(), st.integers(1, 8), st.integers(1, 4), st.floats(1.0, 4.0))
+def test_random_streams_keep_the_scheduler_invariants(s_, max_batch, max_inflight, budget_factor):
+    """Every request completes once, with its wanted count, alone in failing
+    when it fails; batches hold one precision and at most max_batch
+    requests; the request bytes in flight stay within the budget."""
+    reqs, fail = s_
+    sizes = []
+    for i, n, prec, rng in reqs:
+        k = rng[2] - rng[1] + 1 if rng else n
+        sizes.append(mr3.mr3_request_bytes(n, k, prec))
+    budget = int(max(sizes) * budget_factor)
+    ex = RecordingExecutor(fail)
+    srv = make_server(ex, budget=budget, max_batch=max_batch, max_inflight=max_inflight)
+    tickets = [mr3.mr3_server_submit(srv, req(i, n=n, precision=prec, rng=rng))
+               for i, n, prec, rng in reqs]
+    results = [mr3.mr3_server_wait(srv, t) for t in tickets]
+    mr3.mr3_server_destroy(srv)
+    for (i, n, prec, rng), r in zip(reqs, results):
+        k = rng[2] - rng[1] + 1 if rng else n
+        if i in fail:
+            assert r["status"] != 0
+        else:
+            assert r["status"] == 0 and r["m"] == k
+    for ids, precs in ex.batches:
+        assert len(precs) == 1 and 1 <= len(ids) <= max_batch
+    assert ex.max_inflight <= budget
+    ran_ok = {i for ids, _ in ex.batches for i in ids}
+    assert {i for i, *_ in reqs} <= ran_ok
