@@ -2040,7 +2040,11 @@ __device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ 
     for (int it0 = 0; it0 < smax; it0 += SW) {
         const int cur = (it0 / SW) & 1;
         const SweepStep<Y> nx = load_sweep_step<Y, DL>(t >> 5, it0 + SW + (t & 31), D, LL, E, P, Pe, Q, Qe, n);
-        if (it0 + SW < nsteps) {
+        // a window that holds some lane's twist row runs the second form
+        // below for every lane (each step taken only up to the lane's twist
+        // row), so that the wave does not run both forms one after the other
+        const bool twin = __any(it0 < nsteps && it0 + SW >= nsteps);
+        if (!twin && it0 + SW < nsteps) {
             // the twist row lies beyond this window: straight-line steps
             for (int u = 0; u < SW; u += 4) {
                 SweepStep<Y> w[4];
@@ -2049,14 +2053,21 @@ __device__ __forceinline__ Half<Y> sweep_staged(bool top, const Y* __restrict__ 
 #pragma unroll
                 for (int v = 0; v < 4; ++v) body(w[v], it0 + u + v, v == 3, v == 3 && (u & 4));
             }
-        } else if (it0 < nsteps) {
-            // the window that ends with the twist row (step nsteps - 1)
-            for (int u = 0; u < SW; ++u) {
-                const int it = it0 + u;
-                if (it + 1 < nsteps) {
-                    body(get_sweep_step<Y>(win, cur, side, u), it, (u & 3) == 3, (u & 7) == 7);
-                } else if (it + 1 == nsteps) {
-                    h.zr = zvalue(get_sweep_step<Y>(win, cur, side, u), it, true);
+        } else if (twin && it0 < nsteps) {
+            // the same groups of four, each step taken only up to the twist
+            // row (step nsteps - 1), which gives z_r; in a short node nearly
+            // every window holds some lane's twist row
+            const int last = nsteps - 1 - it0;  // step of the twist row
+            for (int u = 0; u < SW; u += 4) {
+                if (u > last) break;
+                SweepStep<Y> w[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) w[v] = get_sweep_step<Y>(win, cur, side, u + v);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int it = it0 + u + v;
+                    if (it + 1 < nsteps) body(w[v], it, v == 3, v == 3 && (u & 4));
+                    else if (it + 1 == nsteps) h.zr = zvalue(w[v], it, true);
                 }
             }
         }
