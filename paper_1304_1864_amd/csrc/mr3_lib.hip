@@ -1455,7 +1455,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             // 34 KB of windows that is more than half of a CU's 160 KB, so each
             // CU holds one such workgroup and its waves get a SIMD each (two
             // workgroups on one CU would share SIMDs while other CUs idle)
-            const unsigned pad = wpg > 1 ? 48u * 1024u : 0u;
+            // One-wave workgroups take 20 KB of LDS with their windows, so that
+            // a CU holds at most 8 of them (two waves per SIMD) even where the
+            // kernel's registers would allow three: in the batch regime the
+            // cluster chain runs beside this launch and needs the rest of each
+            // SIMD (measured on the 4096-problem batch: 12 per CU 15.7 ms, 8 per
+            // CU 14.0 ms, 6 per CU 15.6 ms).
+            const unsigned pad = wpg > 1 ? 48u * 1024u
+                                         : (unsigned)(20u * 1024u - sizeof(SweepWin<Y>) - sizeof(TwistWin));
             auto rqi = prm.derive_lld ? (wpg > 1 ? k_rqi<Y, RQI_WAVES, true> : k_rqi<Y, 1, true>)
                                       : (wpg > 1 ? k_rqi<Y, RQI_WAVES, false> : k_rqi<Y, 1, false>);
             // one round of consecutive chunks whose tiles fit the tile buffer
