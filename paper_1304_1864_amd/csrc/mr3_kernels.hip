@@ -1764,6 +1764,8 @@ __device__ __forceinline__ dd shfl_y<dd>(dd v, int src) {
 // recurrence: c = f b + a, a' = g a - tau c.
 // ---------------------------------------------------------------------------
 constexpr int SW = 32;
+// largest node whose twist search runs in whole windows (see prepass_staged)
+constexpr int64_t PREPASS_WINDOW_ROWS = 8192;
 
 struct ChunkInfo {
     int64_t begin;  // first position in the singleton list
@@ -1865,11 +1867,26 @@ struct TwistWin {
 // progressive transform).  Without `combine` the quotient s_k = a/b (resp.
 // p_k) is stored in the lane's tile column; with it, the value the other lane
 // stored for row k is combined into |gamma_k| = |s_k + p_k + tau| and the
-// minimum is tracked.  The tile values are read one block of 8 steps ahead.
+// minimum is tracked.
+//
+// In a short node the phase is bound by memory latency unless its tile
+// traffic is issued well ahead: every lane of the wave, active or not, then
+// first runs `uni` steps (a count for which every lane's rows lie in its own
+// half of its own tile column) in whole windows of straight-line code, so that
+// a window's wait for the next window's rows counts exactly its SW stores
+// instead of waiting for all of them, and the combining phase loads each
+// window's tile values one window ahead, each block of 8 replaced once used.
+// (In a long node, where the tiles of a launch far exceed the caches, the
+// faster phase only takes HBM bandwidth from the launches running beside it;
+// there the caller takes the instance WIN = false, which has no whole
+// windows.)  The remaining steps run with per-lane counts, reading tile
+// values one block of 8 steps ahead.  Results of lanes without a pair are
+// never used.
+template <bool WIN>
 __device__ __forceinline__ void prepass_staged(bool top, const double* __restrict__ D,
                                const double* __restrict__ LL, int64_t n, double tau, int64_t s0t,
-                               int64_t s0b, int64_t cnt, double& a, double& b, bool combine,
-                               double* __restrict__ col, double& gmin, int64_t& rmin,
+                               int64_t s0b, int64_t cnt, int64_t uni, double& a, double& b,
+                               bool combine, double* __restrict__ col, double& gmin, int64_t& rmin,
                                TwistWin& win) {
     const int t = threadIdx.x & 63;
     const int side = top ? 0 : 1;
@@ -1891,10 +1908,6 @@ __device__ __forceinline__ void prepass_staged(bool top, const double* __restric
         win.g[0][t >> 5][t & 31] = w.y;
     }
     wave_sync();
-    // tile values of the next block of 8 steps
-    double ctn[8];
-#pragma unroll
-    for (int v = 0; v < 8; ++v) ctn[v] = (combine && v < cnt) ? col[rowk(v) * 32] : 0.0;
     // the quotient needs no correct rounding (it only ranks rows): the
     // hardware reciprocal refined by one Newton step is within a few ulps.
     // Ties go to the smallest row: the top lane visits rows upwards and keeps
@@ -1922,8 +1935,55 @@ __device__ __forceinline__ void prepass_staged(bool top, const double* __restric
             b = __builtin_ldexp(b, -em);
         }
     };
+    // one whole window at step o0 (a multiple of SW); with `combine` its tile
+    // values are in ct, and each block of 8 of them is replaced, once used,
+    // by the same block of the next window (a window past the whole ones
+    // loads the last of them again, never used).  The next window's rows are
+    // loaded meanwhile.
+    const int nfw = WIN ? (int)(uni / SW) : 0;
+    const int64_t zst = top ? 32 : -32;
+    auto window = [&](int o0, double (&ct)[SW]) {
+        const int cur = (o0 / SW) & 1;
+        const double2 nx = load(t >> 5, o0 + SW + (t & 31));
+        const double* p = col + rowk(min(o0 + SW, (nfw - 1) * SW)) * 32;
+#pragma unroll
+        for (int u = 0; u < SW; u += 8) {
+            double f[8], g[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                f[v] = win.f[cur][side][u + v];
+                g[v] = win.g[cur][side][u + v];
+            }
+#pragma unroll
+            for (int v = 0; v < 8; ++v) step(f[v], g[v], ct[u + v], o0 + u + v);
+            if (combine) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) ct[u + v] = p[(int64_t)(u + v) * zst];
+            }
+        }
+        win.f[cur ^ 1][t >> 5][t & 31] = nx.x;
+        win.g[cur ^ 1][t >> 5][t & 31] = nx.y;
+        wave_sync();
+    };
+    int ob = 0;  // first step of the per-lane remainder
+    if (nfw >= 1) {
+        double ct[SW];
+        if (combine) {
+            const double* p = col + rowk(0) * 32;
+#pragma unroll
+            for (int v = 0; v < SW; ++v) ct[v] = p[(int64_t)v * zst];
+        } else {
+#pragma unroll
+            for (int v = 0; v < SW; ++v) ct[v] = 0.0;
+        }
+        for (; ob < nfw * SW; ob += SW) window(ob, ct);
+    }
+    // the remaining steps: per-lane counts, tile values one block of 8 ahead
+    double ctn[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) ctn[v] = (combine && ob + v < cnt) ? col[rowk(ob + v) * 32] : 0.0;
     const int icnt = (int)cnt, icmax = (int)cmax;
-    for (int o0 = 0; o0 < icmax; o0 += SW) {
+    for (int o0 = ob; o0 < icmax; o0 += SW) {
         const int cur = (o0 / SW) & 1;
         const double2 nx = load(t >> 5, o0 + SW + (t & 31));
         if (o0 < icnt) {
@@ -2145,9 +2205,16 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
     const int64_t len2 = active ? (top ? n - hh : hh) : 0;
     double gmin = INFINITY;
     int64_t rmin = n / 2;
-    prepass_staged(top, D64, LL64, n, tau0, 0, 0, len1, a, b, false, tile, gmin, rmin, twin);
-    wave_sync();
-    prepass_staged(top, D64, LL64, n, tau0, hh, n - hh, len2, a, b, true, tile, gmin, rmin, twin);
+    // whole windows for nodes of up to PREPASS_WINDOW_ROWS rows
+    if (n <= PREPASS_WINDOW_ROWS) {
+        prepass_staged<true>(top, D64, LL64, n, tau0, 0, 0, len1, hh, a, b, false, tile, gmin, rmin, twin);
+        wave_sync();
+        prepass_staged<true>(top, D64, LL64, n, tau0, hh, n - hh, len2, hh, a, b, true, tile, gmin, rmin, twin);
+    } else {
+        prepass_staged<false>(top, D64, LL64, n, tau0, 0, 0, len1, 0, a, b, false, tile, gmin, rmin, twin);
+        wave_sync();
+        prepass_staged<false>(top, D64, LL64, n, tau0, hh, n - hh, len2, 0, a, b, true, tile, gmin, rmin, twin);
+    }
     {
         const double go = __shfl_xor(gmin, 1, 64);
         const int64_t ro = __shfl_xor(rmin, 1, 64);
