@@ -653,6 +653,36 @@ static hipError_t download(std::vector<T>& v, const void* src, size_t count, hip
     return e;
 }
 
+// several downloads behind one stream synchronisation (each host round trip
+// costs tens of microseconds, much of a small solve); the vectors must stay
+// unresized until finish()
+struct DownloadBatch {
+    struct Item {
+        void* dst;
+        const void* pin;
+        size_t bytes;
+    };
+    hipStream_t st;
+    std::vector<Item> items;
+    explicit DownloadBatch(hipStream_t s) : st(s) {}
+    template <class T>
+    hipError_t add(std::vector<T>& v, const void* src, size_t count) {
+        v.resize(count);
+        if (count == 0) return hipSuccess;
+        const size_t bytes = count * sizeof(T);
+        void* pin = g_stage ? g_stage->get(bytes) : nullptr;
+        if (pin) items.push_back(Item{v.data(), pin, bytes});
+        return hipMemcpyAsync(pin ? pin : v.data(), src, bytes, hipMemcpyDeviceToHost, st);
+    }
+    hipError_t finish() {
+        const hipError_t e = hipStreamSynchronize(st);
+        if (e == hipSuccess)
+            for (const Item& it : items) std::memcpy(it.dst, it.pin, it.bytes);
+        items.clear();
+        return e;
+    }
+};
+
 // multisection shape: L lanes per eigenvalue, P points per lane and pass
 struct BisectShape {
     int L, P;
@@ -1410,25 +1440,30 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                 tb3 = B[B_CUBTMP].cap;
                 HIPCHK(hipcub::DeviceScan::InclusiveSum(B[B_CUBTMP].p, tb3, cmark, cid, S, st));
             }
-            std::vector<int64_t> nck;
-            HIPCHK(download(nck, cid + S - 1, 1, st));
-            nchunk = nck[0];
-            HIPCHK(SCK.ensure(sizeof(ChunkInfo) * nchunk));
-            HIPCHK(STO.ensure(sizeof(int64_t) * (nchunk + 1)));
-            HIPCHK(B[B_FLAGS].ensure(sizeof(int64_t) * (nchunk + 1)));
+            // the chunk table and its tile offsets are built for the bound of S
+            // chunks (rows of absent chunks are 0), so that the chunk count and
+            // the total tile rows come back behind one synchronisation
+            HIPCHK(SCK.ensure(sizeof(ChunkInfo) * S));
+            HIPCHK(STO.ensure(sizeof(int64_t) * (S + 1)));
+            HIPCHK(B[B_FLAGS].ensure(sizeof(int64_t) * (S + 1)));
             int64_t* rows = reinterpret_cast<int64_t*>(B[B_FLAGS].p);
+            HIPCHK(hipMemsetAsync(rows, 0, sizeof(int64_t) * (S + 1), st));
             hipLaunchKernelGGL(k_chunk_table, dim3(gS), dim3(256), 0, st, SL.as<int64_t>(), S, dslots,
                                dnodes, dblocks, seg, cid, SCK.as<ChunkInfo>(), rows);
             size_t sb = 0;
-            HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, sb, rows, STO.as<int64_t>(), nchunk + 1,
-                                                    st));
+            HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, sb, rows, STO.as<int64_t>(), S + 1, st));
             HIPCHK(B[B_CUBTMP].ensure(sb + 256));
             sb = B[B_CUBTMP].cap;
-            HIPCHK(hipMemsetAsync(rows + nchunk, 0, sizeof(int64_t), st));
-            HIPCHK(hipcub::DeviceScan::ExclusiveSum(B[B_CUBTMP].p, sb, rows, STO.as<int64_t>(),
-                                                    nchunk + 1, st));
-            std::vector<int64_t> tot;
-            HIPCHK(download(tot, STO.as<int64_t>() + nchunk, 1, st));
+            HIPCHK(hipcub::DeviceScan::ExclusiveSum(B[B_CUBTMP].p, sb, rows, STO.as<int64_t>(), S + 1,
+                                                    st));
+            std::vector<int64_t> nck, tot;
+            {
+                DownloadBatch db(st);
+                HIPCHK(db.add(nck, cid + S - 1, 1));
+                HIPCHK(db.add(tot, STO.as<int64_t>() + S, 1));
+                HIPCHK(db.finish());
+            }
+            nchunk = nck[0];
             int64_t tile_need = tot[0];
             if (tile_need > tile_cap) {
                 HIPCHK(download(toff_h, STO.p, (size_t)(nchunk + 1), st));
@@ -1839,25 +1874,8 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             HIPCHK(hipStreamWaitEvent(st, h->ev_side[q], 0));
             h->side_pending[q] = false;
         }
-    std::vector<unsigned long long> ctr;
-    HIPCHK(download(ctr, counters, 8, st));
-    std::vector<int> sts;
-    HIPCHK(download(sts, status, 1, st));
-    stats.n_rqi_iters = (int64_t)ctr[0];
-    stats.n_fallbacks = (int64_t)ctr[1];
-    stats.dqds_transforms = (int64_t)ctr[4];
-    std::vector<double> wk;
-    HIPCHK(download(wk, work, 4, st));
-    stats.bisect_row_steps = wk[0];
-    stats.rqi_row_steps = wk[1];
-    stats.twist_row_steps = wk[2];
-    prof.collect(stats);
-    h->stats = stats;
-    if (sts[0] != 0 || ctr[2] != 0) return MR3_ERR_NUMERIC;
-    if (debug_on())
-        std::fprintf(stderr, "[mr3] levels done t=%.2f ms (rqi iters %llu fallbacks %llu repaired brackets %llu)\n",
-                     now_ms() - t_start, (unsigned long long)ctr[0], (unsigned long long)ctr[1],
-                     (unsigned long long)ctr[3]);
+    // the ascending-order check is enqueued first, so that its flags come
+    // back with the counters behind one synchronisation
     std::vector<int64_t> mv(m_p.begin(), m_p.end());
     HIPCHK(upload(B[B_M], mv, st));
     HIPCHK(B[B_BAD].ensure(sizeof(int) * count));
@@ -1868,8 +1886,30 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
     hipLaunchKernelGGL(k_check_sorted<X>, dim3((unsigned)count), dim3(256), 0, st,
                        B[B_PROBS].as<ProbDesc>(), B[B_M].as<int64_t>(), B[B_BAD].as<int>(),
                        (int)count);
-    std::vector<int> bad;
-    HIPCHK(download(bad, B[B_BAD].p, (size_t)count, st));
+    std::vector<unsigned long long> ctr;
+    std::vector<int> sts, bad;
+    std::vector<double> wk;
+    {
+        DownloadBatch db(st);
+        HIPCHK(db.add(ctr, counters, 8));
+        HIPCHK(db.add(sts, status, 1));
+        HIPCHK(db.add(wk, work, 4));
+        HIPCHK(db.add(bad, B[B_BAD].p, (size_t)count));
+        HIPCHK(db.finish());
+    }
+    stats.n_rqi_iters = (int64_t)ctr[0];
+    stats.n_fallbacks = (int64_t)ctr[1];
+    stats.dqds_transforms = (int64_t)ctr[4];
+    stats.bisect_row_steps = wk[0];
+    stats.rqi_row_steps = wk[1];
+    stats.twist_row_steps = wk[2];
+    prof.collect(stats);
+    h->stats = stats;
+    if (sts[0] != 0 || ctr[2] != 0) return MR3_ERR_NUMERIC;
+    if (debug_on())
+        std::fprintf(stderr, "[mr3] levels done t=%.2f ms (rqi iters %llu fallbacks %llu repaired brackets %llu)\n",
+                     now_ms() - t_start, (unsigned long long)ctr[0], (unsigned long long)ctr[1],
+                     (unsigned long long)ctr[3]);
     for (int64_t p = 0; p < count; ++p) {
         if (!bad[p]) continue;
         h->stats.n_resorted++;
