@@ -1764,8 +1764,6 @@ __device__ __forceinline__ dd shfl_y<dd>(dd v, int src) {
 // recurrence: c = f b + a, a' = g a - tau c.
 // ---------------------------------------------------------------------------
 constexpr int SW = 32;
-// largest node whose twist search runs in whole windows (see prepass_staged)
-constexpr int64_t PREPASS_WINDOW_ROWS = 8192;
 
 struct ChunkInfo {
     int64_t begin;  // first position in the singleton list
@@ -1869,20 +1867,15 @@ struct TwistWin {
 // stored for row k is combined into |gamma_k| = |s_k + p_k + tau| and the
 // minimum is tracked.
 //
-// In a short node the phase is bound by memory latency unless its tile
-// traffic is issued well ahead: every lane of the wave, active or not, then
-// first runs `uni` steps (a count for which every lane's rows lie in its own
-// half of its own tile column) in whole windows of straight-line code, so that
-// a window's wait for the next window's rows counts exactly its SW stores
-// instead of waiting for all of them, and the combining phase loads each
-// window's tile values one window ahead, each block of 8 replaced once used.
-// (In a long node, where the tiles of a launch far exceed the caches, the
-// faster phase only takes HBM bandwidth from the launches running beside it;
-// there the caller takes the instance WIN = false, which has no whole
-// windows.)  The remaining steps run with per-lane counts, reading tile
-// values one block of 8 steps ahead.  Results of lanes without a pair are
-// never used.
-template <bool WIN>
+// The phase is bound by memory latency unless its tile traffic is issued well
+// ahead: every lane of the wave, active or not, first runs `uni` steps (a
+// count for which every lane's rows lie in its own half of its own tile
+// column) in whole windows of straight-line code, so that a window's wait for
+// the next window's rows counts exactly its SW stores instead of waiting for
+// all of them, and the combining phase loads each window's tile values one
+// window ahead, each block of 8 replaced once used.  The remaining steps run
+// with per-lane counts, reading tile values one block of 8 steps ahead.
+// Results of lanes without a pair are never used.
 __device__ __forceinline__ void prepass_staged(bool top, const double* __restrict__ D,
                                const double* __restrict__ LL, int64_t n, double tau, int64_t s0t,
                                int64_t s0b, int64_t cnt, int64_t uni, double& a, double& b,
@@ -1940,7 +1933,7 @@ __device__ __forceinline__ void prepass_staged(bool top, const double* __restric
     // by the same block of the next window (a window past the whole ones
     // loads the last of them again, never used).  The next window's rows are
     // loaded meanwhile.
-    const int nfw = WIN ? (int)(uni / SW) : 0;
+    const int nfw = (int)(uni / SW);
     const int64_t zst = top ? 32 : -32;
     auto window = [&](int o0, double (&ct)[SW]) {
         const int cur = (o0 / SW) & 1;
@@ -2205,16 +2198,9 @@ k_rqi(const ChunkInfo* __restrict__ chunks, int64_t nchunks, const int64_t* __re
     const int64_t len2 = active ? (top ? n - hh : hh) : 0;
     double gmin = INFINITY;
     int64_t rmin = n / 2;
-    // whole windows for nodes of up to PREPASS_WINDOW_ROWS rows
-    if (n <= PREPASS_WINDOW_ROWS) {
-        prepass_staged<true>(top, D64, LL64, n, tau0, 0, 0, len1, hh, a, b, false, tile, gmin, rmin, twin);
-        wave_sync();
-        prepass_staged<true>(top, D64, LL64, n, tau0, hh, n - hh, len2, hh, a, b, true, tile, gmin, rmin, twin);
-    } else {
-        prepass_staged<false>(top, D64, LL64, n, tau0, 0, 0, len1, 0, a, b, false, tile, gmin, rmin, twin);
-        wave_sync();
-        prepass_staged<false>(top, D64, LL64, n, tau0, hh, n - hh, len2, 0, a, b, true, tile, gmin, rmin, twin);
-    }
+    prepass_staged(top, D64, LL64, n, tau0, 0, 0, len1, hh, a, b, false, tile, gmin, rmin, twin);
+    wave_sync();
+    prepass_staged(top, D64, LL64, n, tau0, hh, n - hh, len2, hh, a, b, true, tile, gmin, rmin, twin);
     {
         const double go = __shfl_xor(gmin, 1, 64);
         const int64_t ro = __shfl_xor(rmin, 1, 64);

@@ -683,6 +683,9 @@ struct DownloadBatch {
     }
 };
 
+// LDS taken by a multi-wave RQI workgroup, windows included
+constexpr size_t RQI_CU_LDS = 159u * 1024u;
+
 // multisection shape: L lanes per eigenvalue, P points per lane and pass
 struct BisectShape {
     int L, P;
@@ -1486,17 +1489,18 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             // (they share rows through L1); one when many small problems'
             // chunks of unequal lengths would hold each other's CU slots
             const int wpg = nchunk <= 2048 ? RQI_WAVES : 1;
-            // a multi-wave workgroup also asks for 48 KB of unused LDS: with its
-            // 34 KB of windows that is more than half of a CU's 160 KB, so each
-            // CU holds one such workgroup and its waves get a SIMD each (two
-            // workgroups on one CU would share SIMDs while other CUs idle)
+            // A multi-wave workgroup takes almost all of a CU's 160 KB of LDS, so
+            // that its waves get a SIMD each and no other launch's waves share
+            // them: the bracket check in y runs beside the depth-0 RQI on the
+            // CUs the RQI leaves (at n = 20000 it went from 2.9 to 1.7 ms, the
+            // solve from 33.1 to 32.4 ms, against workgroups of 82 KB).
             // One-wave workgroups take 20 KB of LDS with their windows, so that
             // a CU holds at most 8 of them (two waves per SIMD) even where the
             // kernel's registers would allow three: in the batch regime the
             // cluster chain runs beside this launch and needs the rest of each
             // SIMD (measured on the 4096-problem batch: 12 per CU 15.7 ms, 8 per
             // CU 14.0 ms, 6 per CU 15.6 ms).
-            const unsigned pad = wpg > 1 ? 48u * 1024u
+            const unsigned pad = wpg > 1 ? (unsigned)(RQI_CU_LDS - RQI_WAVES * (sizeof(SweepWin<Y>) + sizeof(TwistWin)))
                                          : (unsigned)(20u * 1024u - sizeof(SweepWin<Y>) - sizeof(TwistWin));
             auto rqi = prm.derive_lld ? (wpg > 1 ? k_rqi<Y, RQI_WAVES, true> : k_rqi<Y, 1, true>)
                                       : (wpg > 1 ? k_rqi<Y, RQI_WAVES, false> : k_rqi<Y, 1, false>);
