@@ -1895,6 +1895,10 @@ __device__ __forceinline__ void prepass_staged(bool top, const double* __restric
         return make_double2(LL[ka], D[ka]);
     };
     auto rowk = [&](int64_t o) -> int64_t { return top ? s0 + o : n - 1 - (s0 + o); };
+    // lanes without a pair (cnt == 0) run the whole windows too, on one row
+    // of their own tile column, so that their accesses stay in the cache
+    const bool live = cnt > 0;
+    auto rowt = [&](int64_t o) -> int64_t { return live ? rowk(o) : 0; };
     {
         const double2 w = load(t >> 5, t & 31);
         win.f[0][t >> 5][t & 31] = w.x;
@@ -1917,7 +1921,7 @@ __device__ __forceinline__ void prepass_staged(bool top, const double* __restric
             gmin = take ? gv : gmin;
             omin = take ? o : omin;
         } else {
-            col[rowk(o) * 32] = q;
+            col[rowt(o) * 32] = q;
         }
         const double c = __fma_rn(f, b, a);
         a = __fma_rn(-tau, c, g * a);
@@ -1934,11 +1938,11 @@ __device__ __forceinline__ void prepass_staged(bool top, const double* __restric
     // loads the last of them again, never used).  The next window's rows are
     // loaded meanwhile.
     const int nfw = (int)(uni / SW);
-    const int64_t zst = top ? 32 : -32;
+    const int64_t zst = live ? (top ? 32 : -32) : 0;
     auto window = [&](int o0, double (&ct)[SW]) {
         const int cur = (o0 / SW) & 1;
         const double2 nx = load(t >> 5, o0 + SW + (t & 31));
-        const double* p = col + rowk(min(o0 + SW, (nfw - 1) * SW)) * 32;
+        const double* p = col + rowt(min(o0 + SW, (nfw - 1) * SW)) * 32;
 #pragma unroll
         for (int u = 0; u < SW; u += 8) {
             double f[8], g[8];
@@ -1962,7 +1966,7 @@ __device__ __forceinline__ void prepass_staged(bool top, const double* __restric
     if (nfw >= 1) {
         double ct[SW];
         if (combine) {
-            const double* p = col + rowk(0) * 32;
+            const double* p = col + rowt(0) * 32;
 #pragma unroll
             for (int v = 0; v < SW; ++v) ct[v] = p[(int64_t)v * zst];
         } else {
