@@ -1639,12 +1639,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         hipLaunchKernelGGL(k_cluster_recs, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, st,
                            B[B_LIST2].as<int64_t>(), C, dslots, B[B_CREC].as<ClusterRec>());
         std::vector<ClusterRec> crec;
-        HIPCHK(download(crec, B[B_CREC].p, (size_t)C, st));
         std::vector<int64_t> cl_n((size_t)C);  // rows of each cluster's block
         std::vector<char> cl_y((size_t)C);     // ... and whether it is refined in y
         {
             std::vector<Node> allnodes;
-            HIPCHK(download(allnodes, dnodes, (size_t)n_nodes, st));
+            DownloadBatch db(st);
+            HIPCHK(db.add(crec, B[B_CREC].p, (size_t)C));
+            HIPCHK(db.add(allnodes, dnodes, (size_t)n_nodes));
+            HIPCHK(db.finish());
             for (int64_t c = 0; c < C; ++c) {
                 cl_n[c] = blocks[allnodes[crec[c].parent].block].n;
                 cl_y[c] = yref[allnodes[crec[c].parent].block];
