@@ -1397,7 +1397,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             std::fprintf(stderr, "[mr3] depth %d: nodes %zu singletons %lld clusters %lld  t=%.2f ms\n",
                          depth, level_nodes.size(), (long long)S, (long long)C, now_ms() - t_start);
         // ---- a6 + a7: singletons, on the side stream ----
-        if (S > 1) {
+        // With more chunks than SIMDs the singletons are put in node-major
+        // order by gap bucket within a node, so that pairs needing the same
+        // number of iterations share waves.  With fewer, every chunk has a
+        // SIMD and the launch ends with its slowest wave either way; the list
+        // stays in slot order, which is node-major already (every node owns
+        // a contiguous slot range), and the sort's launches and their host
+        // round trips are saved.
+        if (S > 32 * 1024) {
             // node-major order, gap bucket within a node
             HIPCHK(B[B_GKEY].ensure(sizeof(unsigned long long) * 2 * S));
             HIPCHK(B[B_GVAL].ensure(sizeof(int64_t) * S));
