@@ -507,6 +507,7 @@ struct mr3_handle_s {
     // parity, and their events
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_jobs = nullptr;  // marks the copy of a level's shift-choice outcomes
     hipEvent_t ev_side[2] = {nullptr, nullptr};
     bool side_pending[2] = {false, false};
     mr3::Staging stage;      // pinned host staging
@@ -1741,11 +1742,17 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                                widen_root / prm.eps_x, prm.eps_x);
             prof.end(st);
             HIPCHK(hipGetLastError());
-            std::vector<ChildJob> done_jobs;
-            HIPCHK(download(done_jobs, B[B_JOBS].p, (size_t)CG, st));
-            for (auto& j : done_jobs) {
-                if (j.best == 1) stats.n_best_candidate++;
-                if (j.best == 2) return MR3_ERR_NUMERIC;
+            // the outcomes of the shift choice (strict, least-growth candidate,
+            // none) are copied now and read once the child multisection has
+            // been enqueued, waiting on an event that marks the copy: the
+            // multisection then follows the transform without a host round trip
+            std::vector<ChildJob> done_jobs((size_t)CG);
+            ChildJob* jpin = g_stage ? static_cast<ChildJob*>(g_stage->get(sizeof(ChildJob) * CG)) : nullptr;
+            if (jpin) {
+                HIPCHK(hipMemcpyAsync(jpin, B[B_JOBS].p, sizeof(ChildJob) * CG, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipEventRecord(h->ev_jobs, st));
+            } else {
+                HIPCHK(download(done_jobs, B[B_JOBS].p, (size_t)CG, st));
             }
             const int64_t child0 = n_nodes, top_saved = rep_top;
             rep_top += new_rows;
@@ -1802,6 +1809,14 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
                           dnodes, dblocks, B[B_D64].rows<double>(), B[B_L64].rows<double>(),
                           prm.bisect_rel, widen_root, work, INT64_MAX, st);
             prof.end(st);
+            if (jpin) {
+                HIPCHK(hipEventSynchronize(h->ev_jobs));
+                std::memcpy(done_jobs.data(), jpin, sizeof(ChildJob) * CG);
+            }
+            for (auto& j : done_jobs) {
+                if (j.best == 1) stats.n_best_candidate++;
+                if (j.best == 2) return MR3_ERR_NUMERIC;
+            }
             if (debug_on()) {
                 std::vector<double> wk;
                 HIPCHK(download(wk, work, 8, st));
@@ -2127,6 +2142,7 @@ int mr3_create(mr3_handle* h, int device) {
               hipStreamCreateWithFlags(&x->side[0], hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&x->side[1], hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&x->ev_fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&x->ev_jobs, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&x->ev_side[0], hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&x->ev_side[1], hipEventDisableTiming) == hipSuccess;
     if (ok) {
@@ -2154,6 +2170,7 @@ int mr3_destroy(mr3_handle h) {
         if (sd) (void)hipStreamSynchronize(sd);
     for (auto& b : h->buf) b.release();
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_jobs) (void)hipEventDestroy(h->ev_jobs);
     for (auto& ev : h->ev_side)
         if (ev) (void)hipEventDestroy(ev);
     for (auto& sd : h->side)
