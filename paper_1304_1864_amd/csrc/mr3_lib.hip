@@ -1079,6 +1079,15 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
             std::fprintf(stderr, "[mr3] work region: %zu of %zu bytes, representation rows %lld (roots %lld), tile rows %lld of %lld\n",
                          reg.used, reg.cap, (long long)rep_cap, (long long)R, (long long)tile_cap, (long long)tile_full);
     }
+    // inputs of the ascending-order check at the end, enqueued now (after a
+    // caller's work region has been carved: B_M and B_BAD live there) so that
+    // they are off the solve's tail
+    {
+        std::vector<int64_t> mv(m_p.begin(), m_p.end());
+        HIPCHK(upload(B[B_M], mv, st));
+        HIPCHK(B[B_BAD].ensure(sizeof(int) * count));
+        HIPCHK(hipMemsetAsync(B[B_BAD].p, 0, sizeof(int) * count, st));
+    }
     HIPCHK(B[B_SLOTS].ensure(sizeof(Slot) * (size_t)K));
     hipLaunchKernelGGL(k_slots, dim3((unsigned)NB), dim3(256), 0, st, B[B_BLOCKS].as<Block>(),
                        B[B_PINFO].as<ProbInfo>(), B[B_SLOTS].as<Slot>());
@@ -1904,10 +1913,6 @@ static int solve_impl(mr3_handle_s* h, int64_t count, const int64_t* n_h, const 
         }
     // the ascending-order check is enqueued first, so that its flags come
     // back with the counters behind one synchronisation
-    std::vector<int64_t> mv(m_p.begin(), m_p.end());
-    HIPCHK(upload(B[B_M], mv, st));
-    HIPCHK(B[B_BAD].ensure(sizeof(int) * count));
-    HIPCHK(hipMemsetAsync(B[B_BAD].p, 0, sizeof(int) * count, st));
     if (prm.force_resort)
         hipLaunchKernelGGL(k_reverse_outputs<X>, dim3((unsigned)count), dim3(256), 0, st,
                            B[B_PROBS].as<ProbDesc>(), B[B_M].as<int64_t>());

@@ -104,3 +104,25 @@ def test_too_small_and_batched(mr3):
     Wb, Zb = mr3.solve_batched(ds, es, handle=h, work=_region(q))
     for i in range(len(probs)):
         assert torch.equal(Wa[i], Wb[i]) and torch.equal(Za[i], Zb[i]), i
+
+
+def test_pool_and_region_solves_alternate_on_one_handle(mr3):
+    """A handle alternating between its pool and work regions that the caller
+    frees in between (each region solve takes its buffers from its own region,
+    whatever an earlier solve left in the handle): every solve gives the pool
+    solve's bits, the ascending order included."""
+    d, e = W.uniform(700, 5, np.float32)
+    n = d.size
+    h = mr3.Handle(0)
+    q = mr3.mr3_workspace_bytes(h, n, mr3.RANGE_ALL, 0, 32)
+    W0, Z0 = mr3.solve(_dev(d), _dev(e), handle=h)
+    for k in range(3):
+        reg = _region(q)
+        W1, Z1 = mr3.solve(_dev(d), _dev(e), handle=h, work=reg)
+        torch.cuda.synchronize()
+        del reg
+        torch.cuda.empty_cache()
+        assert torch.equal(W0, W1) and torch.equal(Z0, Z1), k
+        assert bool(torch.all(W1[1:] >= W1[:-1]))
+        W2, Z2 = mr3.solve(_dev(d), _dev(e), handle=h)
+        assert torch.equal(W0, W2) and torch.equal(Z0, Z2), k
